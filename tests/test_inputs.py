@@ -1,0 +1,80 @@
+"""Synthetic inputs: foams are watertight, oriented, periodic and porous as asked."""
+from collections import Counter
+
+import numpy as np
+import pytest
+
+import foamgen as fg
+
+
+def _directed_edges_pair_up(tris, canon):
+    ct = canon[tris]
+    de = Counter()
+    for a, b, c in ct:
+        for x, y in ((a, b), (b, c), (c, a)):
+            de[(int(x), int(y))] += 1
+    return all(n == 1 and de.get((y, x), 0) == 1 for (x, y), n in de.items())
+
+
+@pytest.mark.parametrize("n,p,seed", [(8, 0.5, 0), (12, 0.3, 1), (12, 0.8, 2)])
+def test_foam_is_watertight_modulo_periodicity(n, p, seed):
+    m = fg.make_grf_foam(n, p, 2.0, seed=seed)
+    assert _directed_edges_pair_up(m.tris, m.meta["canon"])
+
+
+def test_foam_normals_point_into_the_void():
+    m = fg.make_grf_foam(12, 0.5, 2.0, seed=3)
+    f, tau = fg.foam_field(12, 0.5, 2.0, seed=3)
+    canon = m.meta["canon"]
+    ax = canon % 3
+    base = canon // 3
+    nx, ny, nz = f.shape
+    z = base % nz
+    y = (base // nz) % ny
+    x = base // (nz * ny)
+    step = np.eye(3, dtype=int)[ax]
+    f0 = f[x, y, z]
+    dirv = step * np.where(f0 >= tau, 1.0, -1.0)[:, None]  # solid -> void along the edge
+    V = m.verts[m.tris].astype(np.float64)
+    s = np.cross(V[:, 1] - V[:, 0], V[:, 2] - V[:, 0])
+    score = (s[:, None, :] * dirv[m.tris]).sum(-1).sum(-1)
+    assert (score > 0).all()
+
+
+def test_foam_porosity_and_size():
+    m = fg.make_grf_foam(16, 0.5, 2.0, seed=0)
+    assert abs(m.meta["void_fraction"] - 0.5) < 1e-3
+    assert 2500 < m.n_tris < 6000  # "~4k triangles" for the 16^3 foam
+    assert m.verts.min() >= 0 and m.verts[:, :2].max() <= 16 and m.verts[:, 2].max() <= 15
+    # periodic copies: vertices on x = 16 mirror those on x = 0
+    canon = m.meta["canon"]
+    on_hi = np.nonzero(m.verts[:, 0] == 16)[0]
+    for i in on_hi[:50]:
+        j = np.nonzero((canon == canon[i]) & (m.verts[:, 0] == 0))[0]
+        assert j.size >= 1
+        for k in j:
+            assert m.verts[k, 2] == m.verts[i, 2] and (m.verts[k, 1] - m.verts[i, 1]) % 16 == 0
+
+
+def test_foam_seeded():
+    a = fg.make_grf_foam(10, 0.6, 2.0, seed=7)
+    b = fg.make_grf_foam(10, 0.6, 2.0, seed=7)
+    c = fg.make_grf_foam(10, 0.6, 2.0, seed=8)
+    assert np.array_equal(a.verts, b.verts) and np.array_equal(a.tris, b.tris)
+    assert a.verts.shape != c.verts.shape or not np.array_equal(a.verts, c.verts)
+
+
+def test_grf_covariance_length():
+    f = fg.grf_field(64, 64, 2.0, seed=1)
+    # covariance exp(-r^2 / (2 l^2)): at r = 2 it is exp(-1/2)
+    c2 = np.mean(f * np.roll(f, 2, axis=0))
+    assert abs(c2 - np.exp(-0.5)) < 0.03
+
+
+def test_chung_everhart_closed_forms():
+    xi = np.linspace(0.001, 0.999, 999)
+    E = fg.ce_inverse(xi)
+    assert np.allclose(fg.ce_cdf(E), xi, atol=1e-12)
+    assert fg.ce_inverse(0.5) == pytest.approx(4.5, rel=1e-12)
+    t = fg.make_tables("vaughan")
+    assert t.cdf_F[0] == 0 and t.cdf_F[-1] == 1 and np.all(np.diff(t.cdf_F) >= 0)

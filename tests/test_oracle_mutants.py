@@ -1,0 +1,135 @@
+"""Planted mistakes: every plausible slip in the oracle must trip a pin.
+
+Each case copies the oracle's C source with one change, builds the copy with
+gcc in a temporary directory and runs one of the independent pins against
+it.  The pin must reject the mutant (and, as a control, accept the real
+oracle in the pin tests).
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import foamgen as fg
+import oracle
+from tests.exact_hit import exact_first_hit
+from tests.philox_ref import load_kat
+
+SRC = os.path.join(os.path.dirname(oracle.__file__), "rtmc_oracle.c")
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _build_variant(tmp_path, old, new):
+    src = open(SRC).read()
+    assert src.count(old) == 1, old
+    path = tmp_path / "mutant.c"
+    path.write_text(src.replace(old, new))
+    so = str(tmp_path / "libmutant.so")
+    oracle.compile_source(str(path), so)
+    return oracle.Variant(so)
+
+
+# ---- pins, each returning True when the oracle under test passes
+
+def pin_exact_first_hit(o):
+    for seed in (0, 1):
+        m = fg.random_soup(48, seed=seed)
+        m.flags = 0
+        rng = np.random.default_rng(100 + seed)
+        lo, hi = np.array(m.box_lo), np.array(m.box_hi)
+        org = lo + (hi - lo) * (rng.integers(1, 64, size=(120, 3)) / 64.0)
+        d = rng.normal(size=(120, 3))
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        rays = np.concatenate([org, d], axis=1)
+        tri, t, _ = o.first_hit(m, rays)
+        for i in range(len(rays)):
+            eid, et = exact_first_hit(m.verts, m.tris, m.box_lo, m.box_hi, False, rays[i])
+            if tri[i] != eid or abs(t[i] - float(et)) > 1e-12 * max(1.0, float(et)):
+                return False
+    return True
+
+
+def pin_flat_yield(o):
+    tab = fg.make_tables("vaughan")
+    for E, th in ((500.0, 0.0), (100.0, 30.0), (1000.0, 60.0)):
+        n = 20000
+        r = o.trace(fg.flat_plane(), tab, E, th, n, seed=11, max_gen=6)
+        ref = float(fg.bilinear_reference(tab, E, th))
+        f = ref - math.floor(ref)
+        if abs(r["yield"] - ref) > 3.0 * math.sqrt(f * (1 - f) / n):
+            return False
+    return True
+
+
+def pin_cosine_law(o):
+    tab = fg.make_tables("constant", const=1.0)
+    n = 20000
+    r = o.trace(fg.flat_plane(), tab, 200.0, 0.0, n, seed=5, max_gen=1, n_abins=90)
+    b = np.deg2rad(np.linspace(0, 90, 91))
+    emp = np.concatenate([[0], np.cumsum(r["a_hist"])]) / n
+    return bool(np.max(np.abs(emp - np.sin(b) ** 2)) < 1.63 / math.sqrt(n))
+
+
+def pin_conservation(o):
+    m = fg.make_grf_foam(10, 0.6, 2.0, seed=3)
+    r = o.trace(m, fg.make_tables("vaughan"), 800.0, -80.0, 500, seed=9, per_primary=True)
+    pp = r["per_primary"]
+    return bool(np.allclose(pp["e_esc"] + pp["e_dep"], 800.0, rtol=1e-9, atol=0))
+
+
+def pin_trench(o):
+    tab = fg.make_tables("vaughan")
+    n = 20000
+    r = o.trace(fg.trench(), tab, 500.0, 0.0, n, seed=21, max_gen=1)
+    d0 = float(fg.bilinear_reference(tab, 500.0, 0.0))
+    F = math.sqrt(1 + 1.5 ** 2) - 1.5
+    expect = d0 * (1 / 3 + 2 / 3 * F)
+    return abs(r["yield"] - expect) <= 3.0 * max(r["yield_sigma"], 1e-9)
+
+
+def pin_philox(o):
+    return all(list(o.philox4x32_10(c, k)) == out for c, k, out in load_kat(os.path.join(GOLD, "philox4x32_10_kat.txt")))
+
+
+MUTANTS = [
+    ("cull the wrong side",
+     "if (det <= DET_EPS * norm3(L1) * norm3(L2) * dn) continue;",
+     "if (-det <= DET_EPS * norm3(L1) * norm3(L2) * dn) continue;", pin_exact_first_hit),
+    ("printed barycentric limit u^2 + v^2 <= 1",
+     "if (v < 0.0 || u + v > 1.0) continue;",
+     "if (v < 0.0 || u * u + v * v > 1.0) continue;", pin_exact_first_hit),
+    ("printed Cramer denominator (D x L2) . L2",
+     "double det = dot3(P, L1);", "double det = dot3(P, L2) + dot3(P, L1) * 1e-30;", pin_exact_first_hit),
+    ("keep the farthest hit",
+     "if (best < 0 || t < bt || (t == bt && T->id < m->t[best].id)) {",
+     "if (best < 0 || t > bt || (t == bt && T->id < m->t[best].id)) {", pin_exact_first_hit),
+    ("stochastic rounding inverted",
+     "int nd = (int)fl + (u1[0] < delta - fl ? 1 : 0);",
+     "int nd = (int)fl + (u1[0] >= delta - fl ? 1 : 0);", pin_flat_yield),
+    ("incidence angle as printed (obtuse)",
+     "double cosa = -dot3(ray.d, p.n);", "double cosa = dot3(ray.d, p.n);", pin_flat_yield),
+    ("bilinear term dropped",
+     "(1 - fx) * fy * y01 + fx * fy * y11;", "(1 - fx) * fy * y01;", pin_flat_yield),
+    ("sin(beta) uniform instead of sin^2(beta)",
+     "double sb = sqrt(u[1]), cb = sqrt(1.0 - u[1])", "double sb = u[1], cb = sqrt(1.0 - u[1] * u[1])",
+     pin_cosine_law),
+    ("daughter energy not taken from the parent",
+     "          Eav -= Ed;\n", "\n", pin_conservation),
+    ("periodic re-entry through the same face",
+     "p[a] = D[a] > 0.0 ? m->lo[a] : m->hi[a];", "p[a] = D[a] > 0.0 ? m->hi[a] - 1e-9 : m->lo[a] + 1e-9;",
+     pin_trench),
+    ("Philox key schedule dropped",
+     "      k[0] += 0x9E3779B9u;\n", "\n", pin_philox),
+]
+
+
+@pytest.mark.parametrize("name,old,new,pin", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_pin_rejects_planted_mistake(tmp_path, name, old, new, pin):
+    mutant = _build_variant(tmp_path, old, new)
+    assert not pin(mutant), f"pin {pin.__name__} did not catch: {name}"
+
+
+@pytest.mark.parametrize("pin", sorted({m[3] for m in MUTANTS}, key=lambda f: f.__name__))
+def test_pins_accept_the_oracle(oracle_lib, pin):
+    assert pin(oracle_lib)
