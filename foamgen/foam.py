@@ -103,8 +103,9 @@ def trench(w: float = 2.0, h: float = 3.0, tw: float = 1.0, Ly: float = 4.0) -> 
     """Infinite slot of width w and depth h between walls of thickness tw.
 
     The cell is x in [0, tw + w] (periodic), y in [0, Ly] (periodic), z in
-    [0, h + w].  The wall straddles the periodic x boundary (half of it at
-    each end of the cell) so that no surface lies on a cell face.  Surfaces:
+    [-1, h + w].  The wall straddles the periodic x boundary (half of it at
+    each end of the cell) and the floor sits above the cell bottom, so that
+    no surface lies on a cell face (a hit there would race the exit test).  Surfaces:
     wall tops (z = h), slot floor (z = 0, x in [tw/2, tw/2 + w]), the wall
     face at x = tw/2 facing +x and the face at x = tw/2 + w facing -x.  All
     normals point into the vacuum.
@@ -131,7 +132,7 @@ def trench(w: float = 2.0, h: float = 3.0, tw: float = 1.0, Ly: float = 4.0) -> 
         tris.append([base, base + 2, base + 3])
     v = np.array(verts, dtype=np.float32)
     t = np.array(tris, dtype=np.int32)
-    return Mesh(v, t, (0.0, 0.0, 0.0), (P, Ly, h + w), PERIODIC_XY,
+    return Mesh(v, t, (0.0, 0.0, -1.0), (P, Ly, h + w), PERIODIC_XY,
                 dict(kind="trench", w=w, h=h, tw=tw, Ly=Ly))
 
 

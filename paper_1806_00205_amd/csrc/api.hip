@@ -1,0 +1,893 @@
+// Host runtime behind the C interface of rtmc.h: contexts, scenes, tables,
+// the chunked generation-by-generation launch sequence of a trace, HIP graph
+// replay for batches, and the launch-shape autotuner.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/rtmc.h"
+#include "rtmc_internal.h"
+
+using namespace rtmc;
+
+namespace {
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Scene {
+  int64_t n_in = 0, n_tris = 0, dropped = 0;
+  double lo[3], hi[3];
+  uint32_t flags = 0;
+  DevBuf tris_in;  // compacted, caller order (freed after the build)
+  DevBuf tris;     // Morton order
+  DevBuf nodes;
+  int64_t n_nodes = 0;
+  int built = 0, depth = 0;
+  double build_ms = 0.0;
+};
+
+struct Tables {
+  DevBuf buf;  // yield | cdf_E | cdf_F
+  int32_t nE = 0, nth = 0, ncdf = 0;
+  double Emin = 0, Emax = 0, Ec = 0;
+  int max_d = 1;
+};
+
+}  // namespace
+
+struct rtmc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t gstream = nullptr;  // graph capture / replay
+  rtmc_allocator alloc{};
+  bool custom_alloc = false;
+  std::string err;
+  int n_cu = 0;
+  size_t lds_per_block = 0;
+  std::vector<Scene> scenes;
+  std::vector<Tables> tables;
+  rtmc_launch_cfg cfg{256, 3, 16, 1 << 21};
+  // trace work buffers, grown on demand
+  DevBuf queue[2];
+  uint32_t qcap = 0;
+  DevBuf gstack;
+  DevBuf counters, ppc, err_word, jobs, tally;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  std::vector<hipEvent_t> kev;  // per-launch timing events (eager traces)
+};
+
+namespace {
+
+rtmc_status fail(rtmc_ctx* c, rtmc_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIPCHK(c, expr)                                                                                 \
+  do {                                                                                                  \
+    hipError_t e_ = (expr);                                                                             \
+    if (e_ != hipSuccess) return fail((c), RTMC_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+void* dev_alloc(rtmc_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (c->custom_alloc) return c->alloc.alloc(bytes, c->alloc.user);
+  void* p = nullptr;
+  if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+  return p;
+}
+
+void dev_free(rtmc_ctx* c, DevBuf& b) {
+  if (!b.p) return;
+  if (c->custom_alloc)
+    c->alloc.free(b.p, c->alloc.user);
+  else
+    (void)hipFree(b.p);
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+rtmc_status ensure(rtmc_ctx* c, DevBuf& b, size_t bytes) {
+  if (b.p && b.bytes >= bytes) return RTMC_OK;
+  dev_free(c, b);
+  b.p = dev_alloc(c, bytes);
+  if (!b.p) return fail(c, RTMC_ENOMEM, "device allocation of %zu bytes failed", bytes);
+  b.bytes = bytes;
+  return RTMC_OK;
+}
+
+rtmc_status check_scene(rtmc_ctx* c, int32_t id, bool need_bvh) {
+  if (!c) return RTMC_EINVAL;
+  if (id < 0 || id >= (int32_t)c->scenes.size()) return fail(c, RTMC_EINVAL, "unknown scene id %d", id);
+  if (need_bvh && !c->scenes[id].built) return fail(c, RTMC_ESTATE, "scene %d has no BVH: call rtmc_build_bvh", id);
+  return RTMC_OK;
+}
+
+DevScene dev_scene(const Scene& s) {
+  DevScene d;
+  d.nodes = reinterpret_cast<const float4*>(s.nodes.p);
+  d.tris = reinterpret_cast<const float4*>(s.tris.p);
+  for (int a = 0; a < 3; ++a) {
+    d.lo[a] = (float)s.lo[a];
+    d.hi[a] = (float)s.hi[a];
+  }
+  d.n_tris = (int32_t)s.n_tris;
+  d.flags = s.flags;
+  return d;
+}
+
+DevTables dev_tables(const Tables& t) {
+  DevTables d;
+  const float* base = reinterpret_cast<const float*>(t.buf.p);
+  d.yld = base;
+  d.cdfE = base + (size_t)t.nE * t.nth;
+  d.cdfF = d.cdfE + t.ncdf;
+  d.nE = t.nE;
+  d.nth = t.nth;
+  d.ncdf = t.ncdf;
+  d.logEmin = (float)std::log(t.Emin);
+  d.invdlogE = (float)((t.nE - 1) / (std::log(t.Emax) - std::log(t.Emin)));
+  d.thscale = (float)((t.nth - 1) / 90.0);
+  d.Ec = (float)t.Ec;
+  return d;
+}
+
+int grid_of(const rtmc_ctx* c, const rtmc_launch_cfg& cfg) { return c->n_cu * cfg.wg_per_cu; }
+
+struct HostJob {
+  int32_t scene;
+  double E, theta;
+  uint64_t n, seed, pid0;
+  uint32_t* pp;
+};
+
+struct TraceOut {
+  std::vector<unsigned long long> tally;  // n_jobs blocks
+  int n_chunks = 0;
+  double ms = 0.0;
+  double kernel_ms = 0.0;
+  uint64_t launches = 0;
+};
+
+// Enqueue the launch sequence of a batch of jobs with a given chunk size.
+rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJob>& jobs, int max_gen,
+                          int n_ebins, int n_abins, const rtmc_launch_cfg& cfg, uint32_t chunk, hipStream_t s,
+                          uint64_t total, bool timed, uint64_t* n_launch) {
+  const int block = cfg.block;
+  const int grid = grid_of(c, cfg);
+  const int wpb = block / 64;
+  const uint64_t n_chunks = (total + chunk - 1) / chunk;
+  const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins;
+  const int ncnt = 2 * (kMaxGen + 2);
+  int gdepth = kGlobalStack;
+  for (auto& j : jobs) gdepth = std::max(gdepth, c->scenes[j.scene].depth + 2);
+
+  HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->tally.p), 0ull, tw * jobs.size(), s));
+  HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->counters.p), 0u, (size_t)ncnt * n_chunks, s));
+  HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->err_word.p), 0u, 1, s));
+
+  TraceArgs a{};
+  a.jobs = reinterpret_cast<const DevJob*>(c->jobs.p);
+  a.n_jobs = (int32_t)jobs.size();
+  a.tb = dev_tables(tb);
+  a.qcap = (uint32_t)std::min<uint64_t>((uint64_t)chunk * tb.max_d, c->qcap);
+  a.max_gen = max_gen;
+  a.n_ebins = n_ebins;
+  a.n_abins = n_abins;
+  a.gstack = reinterpret_cast<uint32_t*>(c->gstack.p);
+  a.lds_stack = cfg.lds_stack;
+  a.gstack_depth = gdepth;
+  a.err = reinterpret_cast<uint32_t*>(c->err_word.p);
+  a.ppc = reinterpret_cast<uint32_t*>(c->ppc.p);
+  RayQueue q[2];
+  for (int i = 0; i < 2; ++i) {
+    float* f = reinterpret_cast<float*>(c->queue[i].p);
+    const size_t Q = c->qcap;
+    q[i].ox = f;
+    q[i].oy = f + Q;
+    q[i].oz = f + 2 * Q;
+    q[i].dx = f + 3 * Q;
+    q[i].dy = f + 4 * Q;
+    q[i].dz = f + 5 * Q;
+    q[i].E = f + 6 * Q;
+    q[i].path = reinterpret_cast<uint32_t*>(f + 7 * Q);
+    q[i].ci = reinterpret_cast<uint32_t*>(f + 8 * Q);
+    q[i].meta = reinterpret_cast<uint32_t*>(f + 9 * Q);
+  }
+  (void)wpb;
+  for (uint64_t ch = 0; ch < n_chunks; ++ch) {
+    const uint64_t lo = ch * chunk;
+    const uint32_t n_here = (uint32_t)std::min<uint64_t>(chunk, total - lo);
+    uint32_t* cnt = reinterpret_cast<uint32_t*>(c->counters.p) + ch * ncnt;
+    HIPCHK(c, launch_fill_u32(a.ppc, 0u, n_here, s));
+    a.chunk_lo = lo;
+    a.n_gen0 = n_here;
+    for (int g = 0; g <= max_gen; ++g) {
+      a.gen = g;
+      a.qin = q[g & 1];
+      a.qout = q[(g + 1) & 1];
+      a.count_in = cnt + g;  // produced by generation g - 1
+      a.count_out = cnt + g + 1;
+      a.work = cnt + (kMaxGen + 2) + g;
+      if (timed) {
+        const size_t k = 2 * (size_t)(*n_launch);
+        while (c->kev.size() < k + 2) {
+          hipEvent_t e;
+          HIPCHK(c, hipEventCreate(&e));
+          c->kev.push_back(e);
+        }
+        HIPCHK(c, hipEventRecord(c->kev[k], s));
+        HIPCHK(c, launch_trace(a, grid, block, s));
+        HIPCHK(c, hipEventRecord(c->kev[k + 1], s));
+      } else {
+        HIPCHK(c, launch_trace(a, grid, block, s));
+      }
+      ++*n_launch;
+    }
+    HIPCHK(c, launch_chunk_reduce(a.jobs, a.n_jobs, a.ppc, n_here, lo, s));
+  }
+  return RTMC_OK;
+}
+
+rtmc_status prepare_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJob>& jobs, int n_ebins, int n_abins,
+                          const rtmc_launch_cfg& cfg, uint64_t* total_out) {
+  // job table
+  std::vector<DevJob> dj(jobs.size());
+  const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins;
+  rtmc_status st = ensure(c, c->tally, tw * jobs.size() * 8);
+  if (st) return st;
+  uint64_t g = 0;
+  for (size_t i = 0; i < jobs.size(); ++i) {
+    const Scene& sc = c->scenes[jobs[i].scene];
+    dj[i].sc = dev_scene(sc);
+    dj[i].E0 = (float)jobs[i].E;
+    dj[i].theta = (float)jobs[i].theta;
+    dj[i].seed = jobs[i].seed;
+    dj[i].pid0 = jobs[i].pid0;
+    dj[i].n_prim = jobs[i].n;
+    dj[i].gbase = g;
+    dj[i].tally = reinterpret_cast<unsigned long long*>(c->tally.p) + tw * i;
+    dj[i].pp_escaped = jobs[i].pp;
+    g += jobs[i].n;
+  }
+  *total_out = g;
+  st = ensure(c, c->jobs, sizeof(DevJob) * dj.size());
+  if (st) return st;
+  HIPCHK(c, hipMemcpyAsync(c->jobs.p, dj.data(), sizeof(DevJob) * dj.size(), hipMemcpyHostToDevice, c->stream));
+  const uint32_t chunk = (uint32_t)cfg.chunk;
+  const uint64_t need_q = (uint64_t)chunk * tb.max_d;
+  if (need_q > 0xFFFFFFF0ull) return fail(c, RTMC_EINVAL, "chunk too large for the queue index range");
+  if (c->qcap < need_q || !c->queue[0].p) {
+    for (int i = 0; i < 2; ++i) {
+      st = ensure(c, c->queue[i], (size_t)need_q * 40);
+      if (st) return st;
+    }
+    c->qcap = (uint32_t)need_q;
+  }
+  const uint64_t n_chunks = (g + chunk - 1) / chunk;
+  st = ensure(c, c->counters, (size_t)n_chunks * 2 * (kMaxGen + 2) * 4 + 16);
+  if (st) return st;
+  st = ensure(c, c->ppc, (size_t)chunk * 4);
+  if (st) return st;
+  st = ensure(c, c->err_word, 16);
+  if (st) return st;
+  int gdepth = kGlobalStack;
+  for (auto& j : jobs) gdepth = std::max(gdepth, c->scenes[j.scene].depth + 2);
+  const size_t waves = (size_t)grid_of(c, cfg) * (cfg.block / 64);
+  st = ensure(c, c->gstack, waves * gdepth * 64 * 4);
+  if (st) return st;
+  return RTMC_OK;
+}
+
+rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs, int max_gen, int n_ebins,
+                      int n_abins, bool use_graph, TraceOut& out) {
+  const Tables& tb = c->tables[table_id];
+  rtmc_launch_cfg cfg = c->cfg;
+  const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins;
+  for (int attempt = 0;; ++attempt) {
+    uint64_t total = 0;
+    rtmc_status st = prepare_trace(c, tb, jobs, n_ebins, n_abins, cfg, &total);
+    if (st) return st;
+    TraceArgs probe{};
+    probe.tb = dev_tables(tb);
+    probe.n_ebins = n_ebins;
+    probe.n_abins = n_abins;
+    probe.lds_stack = cfg.lds_stack;
+    const size_t lds = trace_lds_bytes(probe, cfg.block);
+    if (lds > c->lds_per_block)
+      return fail(c, RTMC_EINVAL, "launch shape needs %zu bytes of LDS per workgroup (device limit %zu)", lds,
+                  c->lds_per_block);
+    hipStream_t s = use_graph ? c->gstream : c->stream;
+    if (use_graph) {
+      HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+      HIPCHK(c, hipStreamWaitEvent(c->gstream, c->ev0, 0));
+      hipGraph_t graph = nullptr;
+      HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      uint64_t nl = 0;
+      st = enqueue_trace(c, tb, jobs, max_gen, n_ebins, n_abins, cfg, (uint32_t)cfg.chunk, s, total, false, &nl);
+      hipError_t ce = hipStreamEndCapture(s, &graph);
+      out.launches = nl;
+      out.kernel_ms = 0.0;
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      HIPCHK(c, ce);
+      hipGraphExec_t exec = nullptr;
+      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(c, ie);
+      HIPCHK(c, hipEventRecord(c->ev0, s));
+      hipError_t le = hipGraphLaunch(exec, s);
+      HIPCHK(c, hipEventRecord(c->ev1, s));
+      hipError_t se = hipStreamSynchronize(s);
+      (void)hipGraphExecDestroy(exec);
+      HIPCHK(c, le);
+      HIPCHK(c, se);
+    } else {
+      HIPCHK(c, hipEventRecord(c->ev0, s));
+      uint64_t nl = 0;
+      st = enqueue_trace(c, tb, jobs, max_gen, n_ebins, n_abins, cfg, (uint32_t)cfg.chunk, s, total, true, &nl);
+      if (st) return st;
+      HIPCHK(c, hipEventRecord(c->ev1, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      double kms = 0.0;
+      for (uint64_t i = 0; i < nl; ++i) {
+        float e = 0.f;
+        HIPCHK(c, hipEventElapsedTime(&e, c->kev[2 * i], c->kev[2 * i + 1]));
+        kms += e;
+      }
+      out.kernel_ms = kms;
+      out.launches = nl;
+    }
+    float ms = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
+    uint32_t errw = 0;
+    HIPCHK(c, hipMemcpy(&errw, c->err_word.p, 4, hipMemcpyDeviceToHost));
+    if (errw & 2u) return fail(c, RTMC_EOVERFLOW, "traversal stack overflow (BVH deeper than the stack)");
+    if (errw & 1u) {
+      if (cfg.chunk <= 1)
+        return fail(c, RTMC_EOVERFLOW, "one primary's ray tree does not fit the daughter queue");
+      cfg.chunk = std::max(1, cfg.chunk / 2);
+      continue;
+    }
+    out.tally.resize(tw * jobs.size());
+    HIPCHK(c, hipMemcpy(out.tally.data(), c->tally.p, out.tally.size() * 8, hipMemcpyDeviceToHost));
+    out.ms = ms;
+    uint64_t total_n = 0;
+    for (auto& j : jobs) total_n += j.n;
+    out.n_chunks = (int)((total_n + cfg.chunk - 1) / cfg.chunk);
+    (void)attempt;
+    return RTMC_OK;
+  }
+}
+
+void fill_result(const unsigned long long* t, const HostJob& j, int n_ebins, int n_abins, uint64_t* eh,
+                 uint64_t* ah, const TraceOut& to, rtmc_result* r) {
+  std::memset(r, 0, sizeof(*r));
+  r->n_primaries = j.n;
+  r->n_rays = t[T_RAYS];
+  r->n_escaped = t[T_ESCAPED];
+  r->n_absorbed = t[T_ABSORBED];
+  r->n_truncated = t[T_TRUNCATED];
+  r->n_lost = t[T_LOST];
+  r->n_substrate = t[T_SUBSTRATE];
+  r->n_wraps = t[T_WRAPS];
+  r->n_node_visits = t[T_VISITS];
+  r->n_tri_tests = t[T_TESTS];
+  r->n_spawned = t[T_SPAWNED];
+  r->e_escaped = (double)(long long)t[T_E_ESC_FX] / kFixScale;
+  r->e_deposited = (double)(long long)t[T_E_DEP_FX] / kFixScale;
+  const double N = (double)j.n;
+  if (N > 0) {
+    const double mean = (double)t[T_ESCAPED] / N;
+    r->yield = mean;
+    double var = N > 1 ? ((double)t[T_C2] - N * mean * mean) / (N - 1.0) : 0.0;
+    if (var < 0) var = 0;
+    r->yield_sigma = std::sqrt(var / N);
+  }
+  r->ms = to.ms;
+  r->kernel_ms = to.kernel_ms;
+  r->n_kernel_launches = to.launches;
+  r->n_chunks = to.n_chunks;
+  if (eh)
+    for (int b = 0; b < n_ebins; ++b) eh[b] = t[T_NCOUNT + b];
+  if (ah)
+    for (int b = 0; b < n_abins; ++b) ah[b] = t[T_NCOUNT + n_ebins + b];
+}
+
+bool finite_f(float x) { return std::isfinite(x); }
+
+}  // namespace
+
+extern "C" {
+
+rtmc_status rtmc_create(rtmc_ctx** out, int device, const rtmc_allocator* alloc, void* hip_stream) {
+  if (!out) return RTMC_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) return RTMC_EDEVICE;
+  if (device < 0 || device >= ndev) return RTMC_EINVAL;
+  if (alloc && (!alloc->alloc || !alloc->free)) return RTMC_EINVAL;
+  if (hipSetDevice(device) != hipSuccess) return RTMC_EDEVICE;
+  rtmc_ctx* c = new rtmc_ctx();
+  c->device = device;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (alloc) {
+    c->alloc = *alloc;
+    c->custom_alloc = true;
+  }
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess || hipStreamCreate(&c->gstream) != hipSuccess ||
+      hipEventCreate(&c->ev0) != hipSuccess || hipEventCreate(&c->ev1) != hipSuccess) {
+    rtmc_destroy(c);
+    return RTMC_EDEVICE;
+  }
+  c->n_cu = prop.multiProcessorCount;
+  c->lds_per_block = prop.sharedMemPerBlock;
+  *out = c;
+  return RTMC_OK;
+}
+
+void rtmc_destroy(rtmc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->gstream) (void)hipStreamSynchronize(c->gstream);
+  for (auto& s : c->scenes) {
+    dev_free(c, s.tris_in);
+    dev_free(c, s.tris);
+    dev_free(c, s.nodes);
+  }
+  for (auto& t : c->tables) dev_free(c, t.buf);
+  dev_free(c, c->queue[0]);
+  dev_free(c, c->queue[1]);
+  dev_free(c, c->gstack);
+  dev_free(c, c->counters);
+  dev_free(c, c->ppc);
+  dev_free(c, c->err_word);
+  dev_free(c, c->jobs);
+  dev_free(c, c->tally);
+  if (c->ev0) (void)hipEventDestroy(c->ev0);
+  if (c->ev1) (void)hipEventDestroy(c->ev1);
+  for (auto e : c->kev) (void)hipEventDestroy(e);
+  if (c->gstream) (void)hipStreamDestroy(c->gstream);
+  delete c;
+}
+
+const char* rtmc_last_error(const rtmc_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+rtmc_status rtmc_set_stream(rtmc_ctx* c, void* hip_stream) {
+  if (!c) return RTMC_EINVAL;
+  c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_load_mesh(rtmc_ctx* c, const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                           const double box_lo[3], const double box_hi[3], uint32_t flags, int32_t* scene_id) {
+  if (!c) return RTMC_EINVAL;
+  c->err.clear();
+  if (!scene_id || !box_lo || !box_hi || n_verts < 0 || n_tris < 0 || (n_verts > 0 && !verts) ||
+      (n_tris > 0 && !tris))
+    return fail(c, RTMC_EINVAL, "null pointer or negative size");
+  if (n_tris >= (int64_t)0x7fffffff) return fail(c, RTMC_EINVAL, "too many triangles (%lld)", (long long)n_tris);
+  if (flags & ~(RTMC_PERIODIC_XY | RTMC_SUBSTRATE)) return fail(c, RTMC_EINVAL, "unknown flag bits");
+  for (int a = 0; a < 3; ++a) {
+    if (!std::isfinite(box_lo[a]) || !std::isfinite(box_hi[a]) || !(box_hi[a] > box_lo[a]))
+      return fail(c, RTMC_EINVAL, "box axis %d is empty or not finite", a);
+  }
+  for (int64_t i = 0; i < n_verts * 3; ++i) {
+    const float x = verts[i];
+    const int a = (int)(i % 3);
+    if (!finite_f(x)) return fail(c, RTMC_EINVAL, "vertex %lld is not finite", (long long)(i / 3));
+    if ((double)x < box_lo[a] || (double)x > box_hi[a])
+      return fail(c, RTMC_EINVAL, "vertex %lld lies outside the box", (long long)(i / 3));
+  }
+  Scene s;
+  s.n_in = n_tris;
+  std::memcpy(s.lo, box_lo, sizeof(s.lo));
+  std::memcpy(s.hi, box_hi, sizeof(s.hi));
+  s.flags = flags;
+  std::vector<float> packed;
+  packed.reserve((size_t)n_tris * 12);
+  for (int64_t j = 0; j < n_tris; ++j) {
+    const int32_t* t = tris + 3 * j;
+    for (int k = 0; k < 3; ++k)
+      if (t[k] < 0 || t[k] >= n_verts)
+        return fail(c, RTMC_EINVAL, "triangle %lld has vertex index %d out of range", (long long)j, t[k]);
+    double v[3][3];
+    for (int k = 0; k < 3; ++k)
+      for (int a = 0; a < 3; ++a) v[k][a] = verts[3 * (int64_t)t[k] + a];
+    const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+    const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+    const double nx = e1[1] * e2[2] - e1[2] * e2[1];
+    const double ny = e1[2] * e2[0] - e1[0] * e2[2];
+    const double nz = e1[0] * e2[1] - e1[1] * e2[0];
+    if (nx == 0.0 && ny == 0.0 && nz == 0.0) {
+      s.dropped++;
+      continue;
+    }
+    for (int k = 0; k < 3; ++k) {
+      packed.push_back((float)v[k][0]);
+      packed.push_back((float)v[k][1]);
+      packed.push_back((float)v[k][2]);
+      float w = 0.0f;
+      if (k == 0) {
+        int32_t id = (int32_t)j;
+        std::memcpy(&w, &id, 4);
+      }
+      packed.push_back(w);
+    }
+  }
+  s.n_tris = (int64_t)packed.size() / 12;
+  HIPCHK(c, hipSetDevice(c->device));
+  s.tris_in.p = dev_alloc(c, packed.size() * 4);
+  if (!s.tris_in.p) return fail(c, RTMC_ENOMEM, "device allocation for %lld triangles failed", (long long)s.n_tris);
+  s.tris_in.bytes = packed.size() * 4;
+  if (!packed.empty()) {
+    hipError_t e = hipMemcpyAsync(s.tris_in.p, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) {
+      dev_free(c, s.tris_in);
+      return fail(c, RTMC_EDEVICE, "mesh upload: %s", hipGetErrorString(e));
+    }
+  }
+  c->scenes.push_back(s);
+  *scene_id = (int32_t)c->scenes.size() - 1;
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
+  rtmc_status st = check_scene(c, scene_id, false);
+  if (st) return st;
+  c->err.clear();
+  Scene& s = c->scenes[scene_id];
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t n = s.n_tris;
+  if (s.built) return RTMC_OK;
+  if (n == 0) {
+    s.built = 1;
+    s.n_nodes = 0;
+    return RTMC_OK;
+  }
+  const int64_t nn = std::max<int64_t>(n - 1, 1);
+  DevBuf tris, nodes, keys, vals, keys2, vals2, parent, flags, hist, depth;
+  auto cleanup = [&]() {
+    dev_free(c, keys);
+    dev_free(c, vals);
+    dev_free(c, keys2);
+    dev_free(c, vals2);
+    dev_free(c, parent);
+    dev_free(c, flags);
+    dev_free(c, hist);
+    dev_free(c, depth);
+  };
+  if (ensure(c, tris, (size_t)n * 48) || ensure(c, nodes, (size_t)nn * 64) || ensure(c, keys, (size_t)n * 8) ||
+      ensure(c, vals, (size_t)n * 4) || ensure(c, keys2, (size_t)n * 8) || ensure(c, vals2, (size_t)n * 4) ||
+      ensure(c, parent, (size_t)(nn + n) * 4) || ensure(c, flags, (size_t)nn * 4) ||
+      ensure(c, hist, radix_hist_words(n) * 4) || ensure(c, depth, 16)) {
+    cleanup();
+    dev_free(c, tris);
+    dev_free(c, nodes);
+    return RTMC_ENOMEM;
+  }
+  BvhBuild b;
+  b.tris_in = reinterpret_cast<const float4*>(s.tris_in.p);
+  b.tris_out = reinterpret_cast<float4*>(tris.p);
+  b.nodes = reinterpret_cast<float4*>(nodes.p);
+  b.keys = reinterpret_cast<uint64_t*>(keys.p);
+  b.vals = reinterpret_cast<uint32_t*>(vals.p);
+  b.keys_alt = reinterpret_cast<uint64_t*>(keys2.p);
+  b.vals_alt = reinterpret_cast<uint32_t*>(vals2.p);
+  b.parent = reinterpret_cast<int32_t*>(parent.p);
+  b.flags = reinterpret_cast<uint32_t*>(flags.p);
+  b.hist = reinterpret_cast<uint32_t*>(hist.p);
+  b.depth = reinterpret_cast<uint32_t*>(depth.p);
+  b.n = (int32_t)n;
+  for (int a = 0; a < 3; ++a) {
+    b.lo[a] = (float)s.lo[a];
+    b.hi[a] = (float)s.hi[a];
+  }
+  hipError_t e = hipEventRecord(c->ev0, c->stream);
+  if (e == hipSuccess) e = build_bvh(b, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  uint32_t d = 1;
+  if (e == hipSuccess && n > 1) e = hipMemcpy(&d, depth.p, 4, hipMemcpyDeviceToHost);
+  float ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
+  cleanup();
+  if (e != hipSuccess) {
+    dev_free(c, tris);
+    dev_free(c, nodes);
+    return fail(c, RTMC_EDEVICE, "BVH build: %s", hipGetErrorString(e));
+  }
+  dev_free(c, s.tris_in);
+  s.tris = tris;
+  s.nodes = nodes;
+  s.n_nodes = nn;
+  s.depth = (int)d;
+  s.build_ms = ms;
+  s.built = 1;
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_get_scene_info(rtmc_ctx* c, int32_t scene_id, rtmc_scene_info* out) {
+  rtmc_status st = check_scene(c, scene_id, false);
+  if (st) return st;
+  if (!out) return fail(c, RTMC_EINVAL, "null output");
+  const Scene& s = c->scenes[scene_id];
+  out->n_tris_in = s.n_in;
+  out->n_tris = s.n_tris;
+  out->n_dropped = s.dropped;
+  out->n_nodes = s.n_nodes;
+  out->bvh_built = s.built;
+  out->bvh_depth = s.depth;
+  std::memcpy(out->lo, s.lo, sizeof(s.lo));
+  std::memcpy(out->hi, s.hi, sizeof(s.hi));
+  out->flags = s.flags;
+  out->build_ms = s.build_ms;
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_bvh_download(rtmc_ctx* c, int32_t scene_id, float* nodes, float* tris) {
+  rtmc_status st = check_scene(c, scene_id, true);
+  if (st) return st;
+  const Scene& s = c->scenes[scene_id];
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (nodes && s.n_nodes) HIPCHK(c, hipMemcpy(nodes, s.nodes.p, (size_t)s.n_nodes * 64, hipMemcpyDeviceToHost));
+  if (tris && s.n_tris) HIPCHK(c, hipMemcpy(tris, s.tris.p, (size_t)s.n_tris * 48, hipMemcpyDeviceToHost));
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_load_tables(rtmc_ctx* c, const rtmc_tables* t, int32_t* table_id) {
+  if (!c) return RTMC_EINVAL;
+  c->err.clear();
+  if (!t || !table_id || !t->yield || !t->cdf_E || !t->cdf_F) return fail(c, RTMC_EINVAL, "null pointer");
+  if (t->n_E < 2 || t->n_theta < 2 || (int64_t)t->n_E * t->n_theta > kMaxYield)
+    return fail(c, RTMC_EINVAL, "yield grid %d x %d out of range", t->n_E, t->n_theta);
+  if (t->n_cdf < 2 || t->n_cdf > kMaxCdf) return fail(c, RTMC_EINVAL, "n_cdf %d out of range", t->n_cdf);
+  if (!(t->E_min > 0.0) || !(t->E_max > t->E_min) || !std::isfinite(t->E_max) || !std::isfinite(t->Ec) ||
+      t->Ec < 0.0)
+    return fail(c, RTMC_EINVAL, "bad energy axis or cut-off");
+  float ymax = 0.f;
+  for (int64_t i = 0; i < (int64_t)t->n_E * t->n_theta; ++i) {
+    const float y = t->yield[i];
+    if (!finite_f(y) || y < 0.f || y >= 7.f) return fail(c, RTMC_EINVAL, "yield value %lld not in [0, 7)", (long long)i);
+    ymax = std::max(ymax, y);
+  }
+  if (t->cdf_E[0] != 0.f || t->cdf_F[0] != 0.f || t->cdf_F[t->n_cdf - 1] != 1.f)
+    return fail(c, RTMC_EINVAL, "CDF must start at (0, 0) and end at F = 1");
+  for (int k = 1; k < t->n_cdf; ++k) {
+    if (!finite_f(t->cdf_E[k]) || !(t->cdf_E[k] > t->cdf_E[k - 1]))
+      return fail(c, RTMC_EINVAL, "cdf_E must increase strictly (index %d)", k);
+    if (!finite_f(t->cdf_F[k]) || t->cdf_F[k] < t->cdf_F[k - 1])
+      return fail(c, RTMC_EINVAL, "cdf_F must not decrease (index %d)", k);
+  }
+  Tables tb;
+  tb.nE = t->n_E;
+  tb.nth = t->n_theta;
+  tb.ncdf = t->n_cdf;
+  tb.Emin = t->E_min;
+  tb.Emax = t->E_max;
+  tb.Ec = t->Ec;
+  tb.max_d = std::max(1, (int)std::ceil(ymax));
+  std::vector<float> h((size_t)tb.nE * tb.nth + 2 * (size_t)tb.ncdf);
+  std::memcpy(h.data(), t->yield, sizeof(float) * tb.nE * tb.nth);
+  std::memcpy(h.data() + (size_t)tb.nE * tb.nth, t->cdf_E, sizeof(float) * tb.ncdf);
+  std::memcpy(h.data() + (size_t)tb.nE * tb.nth + tb.ncdf, t->cdf_F, sizeof(float) * tb.ncdf);
+  HIPCHK(c, hipSetDevice(c->device));
+  if (ensure(c, tb.buf, h.size() * 4)) return RTMC_ENOMEM;
+  HIPCHK(c, hipMemcpyAsync(tb.buf.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->tables.push_back(tb);
+  *table_id = (int32_t)c->tables.size() - 1;
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_trace(rtmc_ctx* c, int32_t scene_id, int32_t table_id, double E_eV, double theta_deg,
+                       uint64_t n_primaries, uint64_t seed, const rtmc_trace_opts* opts, rtmc_result* out) {
+  rtmc_status st = check_scene(c, scene_id, true);
+  if (st) return st;
+  c->err.clear();
+  if (table_id < 0 || table_id >= (int32_t)c->tables.size()) return fail(c, RTMC_EINVAL, "unknown table id %d", table_id);
+  if (!out) return fail(c, RTMC_EINVAL, "null result");
+  rtmc_trace_opts o{6, 256, 90, 0, nullptr, nullptr, nullptr};
+  if (opts) {
+    o = *opts;
+    if (o.n_ebins == 0) o.n_ebins = 256;
+    if (o.n_abins == 0) o.n_abins = 90;
+  }
+  if (o.max_gen < 0 || o.max_gen > kMaxGen) return fail(c, RTMC_EINVAL, "max_gen %d not in [0, 10]", o.max_gen);
+  if (o.n_ebins < 1 || o.n_ebins > kMaxEbins || o.n_abins < 1 || o.n_abins > kMaxAbins)
+    return fail(c, RTMC_EINVAL, "histogram bins out of range");
+  if (!(E_eV > 0.0) || !std::isfinite(E_eV) || !std::isfinite(theta_deg) || theta_deg > 90.0 || theta_deg < -90.0)
+    return fail(c, RTMC_EINVAL, "bad energy or angle");
+  if (o.pid0 + n_primaries > 0xFFFFFFFFull) return fail(c, RTMC_EINVAL, "pid0 + n_primaries must stay below 2^32");
+  HIPCHK(c, hipSetDevice(c->device));
+  std::vector<HostJob> jobs{{scene_id, E_eV, theta_deg, n_primaries, seed, o.pid0, o.pp_escaped}};
+  if (n_primaries == 0) {
+    std::memset(out, 0, sizeof(*out));
+    if (o.e_hist) std::memset(o.e_hist, 0, 8 * (size_t)o.n_ebins);
+    if (o.a_hist) std::memset(o.a_hist, 0, 8 * (size_t)o.n_abins);
+    return RTMC_OK;
+  }
+  TraceOut to;
+  st = run_trace(c, table_id, jobs, o.max_gen, o.n_ebins, o.n_abins, false, to);
+  if (st) return st;
+  fill_result(to.tally.data(), jobs[0], o.n_ebins, o.n_abins, o.e_hist, o.a_hist, to, out);
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_trace_batch(rtmc_ctx* c, int32_t table_id, const rtmc_job* jobs, int64_t n_jobs, int32_t max_gen,
+                             rtmc_result* outs) {
+  if (!c) return RTMC_EINVAL;
+  c->err.clear();
+  if (!jobs || !outs || n_jobs <= 0 || n_jobs > (1 << 27)) return fail(c, RTMC_EINVAL, "bad job list");
+  if (table_id < 0 || table_id >= (int32_t)c->tables.size()) return fail(c, RTMC_EINVAL, "unknown table id %d", table_id);
+  if (max_gen < 0 || max_gen > kMaxGen) return fail(c, RTMC_EINVAL, "max_gen %d not in [0, 10]", max_gen);
+  std::vector<HostJob> hj;
+  uint64_t total = 0;
+  for (int64_t i = 0; i < n_jobs; ++i) {
+    rtmc_status st = check_scene(c, jobs[i].scene_id, true);
+    if (st) return st;
+    const rtmc_job& j = jobs[i];
+    if (!(j.E_eV > 0.0) || !std::isfinite(j.E_eV) || !(std::fabs(j.theta_deg) <= 90.0) ||
+        j.n_primaries > 0xFFFFFFFFull)
+      return fail(c, RTMC_EINVAL, "job %lld: bad energy, angle or size", (long long)i);
+    hj.push_back({j.scene_id, j.E_eV, j.theta_deg, j.n_primaries, j.seed, 0, nullptr});
+    total += j.n_primaries;
+  }
+  HIPCHK(c, hipSetDevice(c->device));
+  if (total == 0) {
+    for (int64_t i = 0; i < n_jobs; ++i) std::memset(&outs[i], 0, sizeof(rtmc_result));
+    return RTMC_OK;
+  }
+  TraceOut to;
+  rtmc_status st = run_trace(c, table_id, hj, max_gen, 256, 90, true, to);
+  if (st) return st;
+  const size_t tw = (size_t)T_NCOUNT + 256 + 90;
+  for (int64_t i = 0; i < n_jobs; ++i)
+    fill_result(to.tally.data() + tw * i, hj[i], 256, 90, nullptr, nullptr, to, &outs[i]);
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_first_hit(rtmc_ctx* c, int32_t scene_id, const float* rays, int64_t n, int32_t* tri_out,
+                           float* t_out) {
+  rtmc_status st = check_scene(c, scene_id, true);
+  if (st) return st;
+  c->err.clear();
+  if (n < 0 || (n > 0 && (!rays || !tri_out || !t_out))) return fail(c, RTMC_EINVAL, "bad ray arrays");
+  if (n == 0) return RTMC_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  const Scene& s = c->scenes[scene_id];
+  const int gdepth = std::max(kGlobalStack, s.depth + 2);
+  const int block = c->cfg.block;
+  const int grid = grid_of(c, c->cfg);
+  const size_t waves = (size_t)grid * (block / 64);
+  st = ensure(c, c->gstack, waves * gdepth * 64 * 4);
+  if (st) return st;
+  HIPCHK(c, launch_first_hit(dev_scene(s), rays, n, tri_out, t_out, reinterpret_cast<uint32_t*>(c->gstack.p),
+                             c->cfg.lds_stack, gdepth, grid, block, c->stream));
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_sort_pairs_u64(rtmc_ctx* c, uint64_t* keys, uint32_t* vals, int64_t n, int32_t key_bits) {
+  if (!c) return RTMC_EINVAL;
+  c->err.clear();
+  if (n < 0 || (n > 0 && (!keys || !vals)) || key_bits < 1 || key_bits > 64 || n >= (int64_t)0xFFFFFFFF)
+    return fail(c, RTMC_EINVAL, "bad sort arguments");
+  if (n <= 1) return RTMC_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  DevBuf k2, v2, h;
+  if (ensure(c, k2, (size_t)n * 8) || ensure(c, v2, (size_t)n * 4) || ensure(c, h, radix_hist_words(n) * 4)) {
+    dev_free(c, k2);
+    dev_free(c, v2);
+    dev_free(c, h);
+    return RTMC_ENOMEM;
+  }
+  bool alt = false;
+  hipError_t e = radix_sort_pairs(keys, vals, reinterpret_cast<uint64_t*>(k2.p), reinterpret_cast<uint32_t*>(v2.p),
+                                  reinterpret_cast<uint32_t*>(h.p), n, key_bits, c->stream, &alt);
+  if (e == hipSuccess && alt) {
+    e = hipMemcpyAsync(keys, k2.p, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(vals, v2.p, (size_t)n * 4, hipMemcpyDeviceToDevice, c->stream);
+  }
+  // scratch is released only after the work that uses it has finished
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(c, k2);
+  dev_free(c, v2);
+  dev_free(c, h);
+  if (e != hipSuccess) return fail(c, RTMC_EDEVICE, "sort: %s", hipGetErrorString(e));
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_set_launch(rtmc_ctx* c, const rtmc_launch_cfg* cfg) {
+  if (!c) return RTMC_EINVAL;
+  if (!cfg || cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 || cfg->wg_per_cu < 1 || cfg->wg_per_cu > 64 ||
+      cfg->lds_stack < 4 || cfg->lds_stack > 64 || cfg->chunk < 1)
+    return fail(c, RTMC_EINVAL, "bad launch shape");
+  c->cfg = *cfg;
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_get_launch(rtmc_ctx* c, rtmc_launch_cfg* cfg) {
+  if (!c || !cfg) return RTMC_EINVAL;
+  *cfg = c->cfg;
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, double E_eV, double theta_deg,
+                          uint64_t n_primaries, rtmc_launch_cfg* best) {
+  rtmc_status st = check_scene(c, scene_id, true);
+  if (st) return st;
+  const rtmc_launch_cfg keep = c->cfg;
+  const int blocks[] = {256, 512};
+  const int wgs[] = {1, 2, 3, 4, 6, 8};
+  const int stacks[] = {8, 12, 16, 24};
+  double best_ms = 1e30;
+  rtmc_launch_cfg bestc = keep;
+  for (int b : blocks)
+    for (int w : wgs)
+      for (int sd : stacks) {
+        rtmc_launch_cfg cf{b, w, sd, keep.chunk};
+        TraceArgs probe{};
+        probe.tb = dev_tables(c->tables[table_id]);
+        probe.n_ebins = 256;
+        probe.n_abins = 90;
+        probe.lds_stack = sd;
+        if (trace_lds_bytes(probe, b) > c->lds_per_block) continue;
+        if (b / 64 * w > 32) continue;  // more waves per CU than the hardware holds
+        c->cfg = cf;
+        rtmc_result r;
+        st = rtmc_trace(c, scene_id, table_id, E_eV, theta_deg, n_primaries, 12345, nullptr, &r);
+        if (st) {
+          c->cfg = keep;
+          return st;
+        }
+        if (r.ms < best_ms) {
+          best_ms = r.ms;
+          bestc = cf;
+        }
+      }
+  c->cfg = bestc;
+  if (best) *best = bestc;
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_copy_probe(rtmc_ctx* c, void* dst, const void* src, size_t bytes, int32_t reps, double* ms) {
+  if (!c) return RTMC_EINVAL;
+  if (!dst || !src || bytes < 16 || bytes % 16 || reps < 1 || !ms) return fail(c, RTMC_EINVAL, "bad probe arguments");
+  HIPCHK(c, hipSetDevice(c->device));
+  const int grid = c->n_cu * 16;
+  HIPCHK(c, launch_copy_probe(reinterpret_cast<float4*>(dst), reinterpret_cast<const float4*>(src), bytes / 16, grid,
+                              c->stream));
+  HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+  for (int r = 0; r < reps; ++r)
+    HIPCHK(c, launch_copy_probe(reinterpret_cast<float4*>(dst), reinterpret_cast<const float4*>(src), bytes / 16,
+                                grid, c->stream));
+  HIPCHK(c, hipEventRecord(c->ev1, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  float t = 0.f;
+  HIPCHK(c, hipEventElapsedTime(&t, c->ev0, c->ev1));
+  *ms = t / reps;
+  return RTMC_OK;
+}
+
+}  // extern "C"

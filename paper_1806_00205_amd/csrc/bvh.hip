@@ -1,0 +1,331 @@
+// Linear BVH construction on the device.
+//
+// The paper tests every ray against every surface element and notes that this
+// scan becomes prohibitive for large meshes (section 2.1).  The library
+// replaces the scan with a binary BVH built in four device passes:
+//   1. Morton code of each triangle centroid (21 bits per axis, 63 bits);
+//   2. LSD radix sort of (code, triangle) pairs, 8 bits per pass;
+//   3. the hierarchy of Karras (HPG 2012): internal node i covers the sorted
+//      range decided by the longest common prefix of neighbouring codes, equal
+//      codes being told apart by their indices;
+//   4. bounds, bottom up: each leaf climbs towards the root and the second
+//      child to arrive at a node merges both child boxes.
+// Child boxes are stored in the parent (64-byte node record) so a traversal
+// step reads one record and tests both children.
+#include "rtmc_internal.h"
+
+namespace rtmc {
+
+namespace {
+
+constexpr int kSortBlock = 256;
+constexpr int kSortWaves = kSortBlock / 64;
+constexpr int kSortRounds = 16;
+constexpr int kSortTile = kSortBlock * kSortRounds;  // keys per workgroup
+
+__device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// ---------------------------------------------------------------- radix sort
+
+__global__ __launch_bounds__(kSortBlock) void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n,
+                                                            int shift, uint32_t* __restrict__ hist,
+                                                            int nblocks) {
+  __shared__ uint32_t h[256];
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  for (int r = 0; r < kSortRounds; ++r) {
+    int64_t k = base + (int64_t)r * kSortBlock + threadIdx.x;
+    if (k < n) atomicAdd(&h[(uint32_t)(keys[k] >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  hist[(size_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+}
+
+// Exclusive scan of len words by one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* __restrict__ a, int64_t len) {
+  __shared__ uint32_t sums[1024];
+  const int64_t per = (len + 1023) / 1024;
+  const int64_t b = (int64_t)threadIdx.x * per;
+  const int64_t e = b + per < len ? b + per : len;
+  uint32_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += a[i];
+  sums[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    uint32_t v = threadIdx.x >= (unsigned)off ? sums[threadIdx.x - off] : 0u;
+    __syncthreads();
+    sums[threadIdx.x] += v;
+    __syncthreads();
+  }
+  uint32_t run = threadIdx.x ? sums[threadIdx.x - 1] : 0u;
+  for (int64_t i = b; i < e; ++i) {
+    uint32_t v = a[i];
+    a[i] = run;
+    run += v;
+  }
+}
+
+// Stable scatter: each wave owns kSortRounds * 64 consecutive keys of the
+// tile; ranks inside a round come from ballots over the 8 digit bits.
+__global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const uint64_t* __restrict__ kin,
+                                                               const uint32_t* __restrict__ vin,
+                                                               uint64_t* __restrict__ kout,
+                                                               uint32_t* __restrict__ vout, int64_t n, int shift,
+                                                               const uint32_t* __restrict__ hist, int nblocks) {
+  __shared__ uint32_t goff[256];
+  __shared__ uint32_t woff[kSortWaves][256];
+  const int w = threadIdx.x / 64;
+  const uint32_t lane = lane_id();
+  goff[threadIdx.x] = hist[(size_t)threadIdx.x * nblocks + blockIdx.x];
+  for (int i = 0; i < kSortWaves; ++i) woff[i][threadIdx.x] = 0;
+  __syncthreads();
+  const int64_t seg = (int64_t)blockIdx.x * kSortTile + (int64_t)w * (kSortRounds * 64);
+  for (int r = 0; r < kSortRounds; ++r) {
+    int64_t k = seg + r * 64 + lane;
+    if (k < n) atomicAdd(&woff[w][(uint32_t)(kin[k] >> shift) & 0xFFu], 1u);
+  }
+  __syncthreads();
+  {
+    const int d = threadIdx.x;
+    uint32_t run = 0;
+    for (int i = 0; i < kSortWaves; ++i) {
+      uint32_t c = woff[i][d];
+      woff[i][d] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  for (int r = 0; r < kSortRounds; ++r) {
+    int64_t k = seg + r * 64 + lane;
+    bool valid = k < n;
+    uint64_t key = valid ? kin[k] : 0ull;
+    uint32_t val = valid ? vin[k] : 0u;
+    uint32_t d = (uint32_t)(key >> shift) & 0xFFu;
+    uint64_t peers = __ballot(valid);
+    for (int b = 0; b < 8; ++b) {
+      uint64_t m = __ballot((d >> b) & 1u);
+      peers &= ((d >> b) & 1u) ? m : ~m;
+    }
+    if (valid) {
+      uint32_t rank = (uint32_t)__popcll(peers & lt);
+      uint32_t pos = goff[d] + woff[w][d] + rank;
+      kout[pos] = key;
+      vout[pos] = val;
+    }
+    __syncthreads();
+    // the highest lane of each digit group advances that digit's offset
+    if (valid && (peers >> lane) == 1ull) woff[w][d] += (uint32_t)__popcll(peers);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- Morton
+
+__device__ inline uint64_t spread3(uint32_t v) {
+  uint64_t x = 0;
+  for (int i = 0; i < 21; ++i) x |= (uint64_t)((v >> i) & 1u) << (3 * i);
+  return x;
+}
+
+__global__ void k_morton(const float4* __restrict__ tris, int32_t n, float lox, float loy, float loz, float sx,
+                         float sy, float sz, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float4 a = tris[3 * (int64_t)i], b = tris[3 * (int64_t)i + 1], c = tris[3 * (int64_t)i + 2];
+  float cx = (a.x + b.x + c.x) * (1.0f / 3.0f);
+  float cy = (a.y + b.y + c.y) * (1.0f / 3.0f);
+  float cz = (a.z + b.z + c.z) * (1.0f / 3.0f);
+  const float q = 2097152.0f;  // 2^21
+  uint32_t qx = (uint32_t)fminf(fmaxf((cx - lox) * sx * q, 0.0f), q - 1.0f);
+  uint32_t qy = (uint32_t)fminf(fmaxf((cy - loy) * sy * q, 0.0f), q - 1.0f);
+  uint32_t qz = (uint32_t)fminf(fmaxf((cz - loz) * sz * q, 0.0f), q - 1.0f);
+  keys[i] = spread3(qx) | (spread3(qy) << 1) | (spread3(qz) << 2);
+  vals[i] = (uint32_t)i;
+}
+
+__global__ void k_gather_tris(const float4* __restrict__ in, const uint32_t* __restrict__ perm, int32_t n,
+                              float4* __restrict__ out) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t s = 3 * (int64_t)perm[i];
+  out[3 * (int64_t)i] = in[s];
+  out[3 * (int64_t)i + 1] = in[s + 1];
+  out[3 * (int64_t)i + 2] = in[s + 2];
+}
+
+// ---------------------------------------------------------------- Karras
+
+__device__ inline int prefix_len(const uint64_t* keys, int32_t n, int32_t i, int32_t j) {
+  if (j < 0 || j >= n) return -1;
+  uint64_t a = keys[i], b = keys[j];
+  if (a == b) return 64 + __clz((uint32_t)(i ^ j));
+  return __clzll(a ^ b);
+}
+
+__global__ void k_karras(const uint64_t* __restrict__ keys, int32_t n, float4* __restrict__ nodes,
+                         int32_t* __restrict__ parent) {
+  int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n - 1) return;
+  const int d = prefix_len(keys, n, i, i + 1) - prefix_len(keys, n, i, i - 1) > 0 ? 1 : -1;
+  const int dmin = prefix_len(keys, n, i, i - d);
+  int32_t lmax = 2;
+  while (prefix_len(keys, n, i, i + lmax * d) > dmin) lmax <<= 1;
+  int32_t l = 0;
+  for (int32_t t = lmax >> 1; t >= 1; t >>= 1)
+    if (prefix_len(keys, n, i, i + (l + t) * d) > dmin) l += t;
+  const int32_t j = i + l * d;
+  const int dnode = prefix_len(keys, n, i, j);
+  int32_t s = 0, step = l;
+  do {
+    step = (step + 1) >> 1;
+    if (prefix_len(keys, n, i, i + (s + step) * d) > dnode) s += step;
+  } while (step > 1);
+  const int32_t g = i + s * d + (d < 0 ? -1 : 0);
+  const int32_t lo = i < j ? i : j, hi = i < j ? j : i;
+  uint32_t left, right;
+  if (lo == g) {
+    left = (uint32_t)g | kLeafBit;
+    parent[(n - 1) + g] = i;
+  } else {
+    left = (uint32_t)g;
+    parent[g] = i;
+  }
+  if (hi == g + 1) {
+    right = (uint32_t)(g + 1) | kLeafBit;
+    parent[(n - 1) + g + 1] = i;
+  } else {
+    right = (uint32_t)(g + 1);
+    parent[g + 1] = i;
+  }
+  nodes[4 * (int64_t)i + 3] = make_float4(__uint_as_float(left), __uint_as_float(right), 0.0f, 0.0f);
+  if (i == 0) parent[0] = -1;
+}
+
+__device__ inline void tri_box(const float4* tris, int32_t k, float b[6]) {
+  float4 a = tris[3 * (int64_t)k], c = tris[3 * (int64_t)k + 1], e = tris[3 * (int64_t)k + 2];
+  b[0] = fminf(fminf(a.x, c.x), e.x);
+  b[1] = fminf(fminf(a.y, c.y), e.y);
+  b[2] = fminf(fminf(a.z, c.z), e.z);
+  b[3] = fmaxf(fmaxf(a.x, c.x), e.x);
+  b[4] = fmaxf(fmaxf(a.y, c.y), e.y);
+  b[5] = fmaxf(fmaxf(a.z, c.z), e.z);
+}
+
+__device__ inline void store_slot(float4* nodes, int32_t p, int slot, const float b[6]) {
+  float* f = reinterpret_cast<float*>(nodes + 4 * (int64_t)p);
+  const int o = slot * 6;
+  for (int q = 0; q < 6; ++q) f[o + q] = b[q];
+}
+
+__global__ void k_refit(const float4* __restrict__ tris, int32_t n, float4* nodes, const int32_t* __restrict__ parent,
+                        uint32_t* flags) {
+  int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  float b[6];
+  tri_box(tris, k, b);
+  uint32_t child = (uint32_t)k | kLeafBit;
+  int32_t p = parent[(n - 1) + k];
+  while (p >= 0) {
+    float4 links = nodes[4 * (int64_t)p + 3];
+    int slot = __float_as_uint(links.x) == child ? 0 : 1;
+    store_slot(nodes, p, slot, b);
+    uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (old == 0u) return;
+    const float* f = reinterpret_cast<const float*>(nodes + 4 * (int64_t)p);
+    float o[12];
+    for (int q = 0; q < 12; ++q) o[q] = __hip_atomic_load(f + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    b[0] = fminf(o[0], o[6]);
+    b[1] = fminf(o[1], o[7]);
+    b[2] = fminf(o[2], o[8]);
+    b[3] = fmaxf(o[3], o[9]);
+    b[4] = fmaxf(o[4], o[10]);
+    b[5] = fmaxf(o[5], o[11]);
+    child = (uint32_t)p;
+    p = parent[p];
+  }
+}
+
+// One triangle: a single node whose two children are that triangle.
+__global__ void k_single(const float4* __restrict__ tris, float4* nodes) {
+  float b[6];
+  tri_box(tris, 0, b);
+  store_slot(nodes, 0, 0, b);
+  store_slot(nodes, 0, 1, b);
+  nodes[3] = make_float4(__uint_as_float(kLeafBit), __uint_as_float(kLeafBit), 0.0f, 0.0f);
+}
+
+__global__ void k_depth(const int32_t* __restrict__ parent, int32_t n, uint32_t* depth) {
+  int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= n) return;
+  uint32_t d = 1;
+  int32_t p = parent[(n - 1) + k];
+  while (p > 0) {
+    p = parent[p];
+    ++d;
+  }
+  atomicMax(depth, d);
+}
+
+}  // namespace
+
+size_t radix_hist_words(int64_t n) {
+  int64_t nb = (n + kSortTile - 1) / kSortTile;
+  if (nb < 1) nb = 1;
+  return (size_t)nb * 256;
+}
+
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, uint32_t* hist,
+                            int64_t n, int key_bits, hipStream_t s, bool* result_in_alt) {
+  *result_in_alt = false;
+  if (n <= 1) return hipSuccess;
+  const int nb = (int)((n + kSortTile - 1) / kSortTile);
+  uint64_t* ka = keys;
+  uint32_t* va = vals;
+  uint64_t* kb = keys_alt;
+  uint32_t* vb = vals_alt;
+  for (int shift = 0; shift < key_bits; shift += 8) {
+    k_radix_hist<<<nb, kSortBlock, 0, s>>>(ka, n, shift, hist, nb);
+    k_scan_excl<<<1, 1024, 0, s>>>(hist, (int64_t)nb * 256);
+    k_radix_scatter<<<nb, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist, nb);
+    uint64_t* tk = ka;
+    ka = kb;
+    kb = tk;
+    uint32_t* tv = va;
+    va = vb;
+    vb = tv;
+    *result_in_alt = !*result_in_alt;
+  }
+  return hipGetLastError();
+}
+
+hipError_t build_bvh(BvhBuild& b, hipStream_t s) {
+  const int32_t n = b.n;
+  if (n <= 0) return hipSuccess;
+  const int TB = 256;
+  const int g = (n + TB - 1) / TB;
+  float sx = 1.0f / (b.hi[0] - b.lo[0]), sy = 1.0f / (b.hi[1] - b.lo[1]), sz = 1.0f / (b.hi[2] - b.lo[2]);
+  k_morton<<<g, TB, 0, s>>>(b.tris_in, n, b.lo[0], b.lo[1], b.lo[2], sx, sy, sz, b.keys, b.vals);
+  bool alt = false;
+  hipError_t e = radix_sort_pairs(b.keys, b.vals, b.keys_alt, b.vals_alt, b.hist, n, 63, s, &alt);
+  if (e != hipSuccess) return e;
+  uint64_t* keys = alt ? b.keys_alt : b.keys;
+  uint32_t* perm = alt ? b.vals_alt : b.vals;
+  k_gather_tris<<<g, TB, 0, s>>>(b.tris_in, perm, n, b.tris_out);
+  if (n == 1) {
+    k_single<<<1, 1, 0, s>>>(b.tris_out, b.nodes);
+    return hipGetLastError();
+  }
+  const int gi = (n - 1 + TB - 1) / TB;
+  k_karras<<<gi, TB, 0, s>>>(keys, n, b.nodes, b.parent);
+  e = launch_fill_u32(b.flags, 0u, (size_t)(n - 1), s);
+  if (e != hipSuccess) return e;
+  e = launch_fill_u32(b.depth, 0u, 1, s);
+  if (e != hipSuccess) return e;
+  k_refit<<<g, TB, 0, s>>>(b.tris_out, n, b.nodes, b.parent, b.flags);
+  k_depth<<<g, TB, 0, s>>>(b.parent, n, b.depth);
+  return hipGetLastError();
+}
+
+}  // namespace rtmc

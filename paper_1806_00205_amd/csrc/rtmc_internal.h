@@ -1,0 +1,140 @@
+// Internal structures shared by the library's HIP sources (not installed).
+//
+// Device data layout (all in HBM):
+//   triangles  float4 [3 * n_tris], Morton order after the BVH build: V0, V1,
+//              V2 of one triangle in 48 consecutive bytes; V0.w holds the
+//              caller's triangle index (int32 bits).
+//   BVH nodes  float4 [4 * n_nodes]: one 64-byte record per internal node
+//              (both child boxes and both child links), read with four
+//              16-byte loads from one cache line.
+//   ray queue  structure of arrays, ten 32-bit streams, written and read
+//              coalesced by whole waves.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace rtmc {
+
+constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr int kMaxGen = 10;
+constexpr int kWrapMax = 10000;
+constexpr float kSpawnEps = 1e-4f;
+constexpr int kMaxEbins = 1024;
+constexpr int kMaxAbins = 360;
+constexpr int kMaxYield = 8192;
+constexpr int kMaxCdf = 1024;
+constexpr int kGlobalStack = 64;  // minimum traversal stack entries per lane beyond the LDS part
+
+// tally counter slots (u64 each), followed by the energy and angle histograms
+enum TallySlot {
+  T_RAYS = 0,
+  T_ESCAPED,
+  T_ABSORBED,
+  T_TRUNCATED,
+  T_LOST,
+  T_SUBSTRATE,
+  T_WRAPS,
+  T_VISITS,
+  T_TESTS,
+  T_E_ESC_FX,  // escaped energy, 2^-20 eV fixed point
+  T_E_DEP_FX,  // deposited energy, same units (two's complement sums)
+  T_SPAWNED,
+  T_C2,        // sum over primaries of (escape count)^2
+  T_DROPPED,   // daughters that did not fit the queue
+  T_STACKOVF,  // rays whose traversal stack overflowed
+  T_SPARE,
+  T_NCOUNT
+};
+
+constexpr double kFixScale = 1048576.0;  // 2^20
+
+struct DevScene {
+  const float4* nodes;
+  const float4* tris;
+  float lo[3], hi[3];
+  int32_t n_tris;
+  uint32_t flags;
+};
+
+struct DevTables {
+  const float* yld;
+  const float* cdfE;
+  const float* cdfF;
+  int32_t nE, nth, ncdf;
+  float logEmin, invdlogE, thscale, Ec;
+};
+
+// One job: a scene traced at one (E, theta) point.
+struct DevJob {
+  DevScene sc;
+  float E0;
+  float theta;  // >= 0 fixed; < 0 uniform in [0, -theta]
+  uint64_t seed;
+  uint64_t pid0;   // primary id of the job's first primary
+  uint64_t n_prim;
+  uint64_t gbase;  // index of the job's first primary in the concatenated primary space
+  unsigned long long* tally;
+  uint32_t* pp_escaped;  // optional, indexed by primary id - pid0
+};
+
+struct RayQueue {
+  float *ox, *oy, *oz, *dx, *dy, *dz, *E;
+  uint32_t* path;
+  uint32_t* ci;    // primary's index within the current chunk
+  uint32_t* meta;  // gen (4 bits) | job << 4
+};
+
+struct TraceArgs {
+  const DevJob* jobs;
+  int32_t n_jobs;
+  DevTables tb;
+  RayQueue qin, qout;
+  uint32_t qcap;
+  const uint32_t* count_in;  // generation > 0: queue length in device memory
+  uint32_t n_gen0;           // generation 0: primaries in this chunk
+  uint64_t chunk_lo;         // first concatenated primary index of the chunk
+  uint32_t* count_out;
+  uint32_t* work;            // work counter of this launch
+  uint32_t* ppc;             // per-primary escape counts of the chunk
+  int32_t gen, max_gen;
+  int32_t n_ebins, n_abins;
+  uint32_t* gstack;
+  int32_t lds_stack;
+  int32_t gstack_depth;
+  uint32_t* err;  // bit 0: queue overflow, bit 1: stack overflow
+};
+
+// host-side launchers (defined in the .hip files)
+size_t trace_lds_bytes(const TraceArgs& a, int block);
+hipError_t launch_trace(const TraceArgs& a, int grid, int block, hipStream_t s);
+hipError_t launch_first_hit(DevScene sc, const float* rays, int64_t n, int32_t* tri_out, float* t_out,
+                            uint32_t* gstack, int lds_stack, int gstack_depth, int grid, int block, hipStream_t s);
+hipError_t launch_chunk_reduce(const DevJob* jobs, int32_t n_jobs, const uint32_t* ppc, uint32_t n,
+                               uint64_t chunk_lo, hipStream_t s);
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t s);
+hipError_t launch_copy_probe(float4* dst, const float4* src, size_t n16, int grid, hipStream_t s);
+
+// BVH builder pieces
+struct BvhBuild {
+  const float4* tris_in;  // [3 n] unsorted, compacted
+  float4* tris_out;       // [3 n] sorted
+  float4* nodes;          // [4 max(n - 1, 1)]
+  uint64_t* keys;         // [n]
+  uint32_t* vals;         // [n]
+  uint64_t* keys_alt;     // [n]
+  uint32_t* vals_alt;     // [n]
+  int32_t* parent;        // [max(n - 1, 1) + n]: internal nodes then leaves
+  uint32_t* flags;        // [max(n - 1, 1)]
+  uint32_t* hist;         // radix histogram scratch
+  uint32_t* depth;        // [1]
+  int32_t n;
+  float lo[3], hi[3];
+};
+size_t radix_hist_words(int64_t n);
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                            uint32_t* hist, int64_t n, int key_bits, hipStream_t s, bool* result_in_alt);
+hipError_t build_bvh(BvhBuild& b, hipStream_t s);
+
+}  // namespace rtmc

@@ -1,0 +1,304 @@
+"""GPU path against the FP64 oracle (run on an MI355X through the C interface)."""
+import math
+
+import numpy as np
+import pytest
+
+import foamgen as fg
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1806_00205_amd as rt
+    c = rt.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch as t
+    return t
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    """The 16^3 foam at porosity 0.5 (about 4k triangles)."""
+    return fg.make_grf_foam(16, 0.5, 2.0, seed=0)
+
+
+@pytest.fixture(scope="module")
+def vaughan():
+    return fg.make_tables("vaughan")
+
+
+# ---------------------------------------------------------------- sort + BVH
+
+@pytest.mark.parametrize("n,bits", [(1, 64), (1000, 63), (4097, 16), (300001, 63), (65536 * 3 + 17, 64)])
+def test_radix_sort_matches_torch(ctx, torch, n, bits):
+    g = torch.Generator().manual_seed(n)
+    keys = torch.randint(-(2 ** 62), 2 ** 62, (n,), generator=g, dtype=torch.int64)
+    if bits < 64:
+        keys = keys & ((1 << bits) - 1)
+    if n > 3:
+        keys[: n // 3] = keys[n // 2]  # many equal keys: stability matters
+    vals = torch.arange(n, dtype=torch.int32)
+    kd, vd = keys.cuda(), vals.cuda()
+    ctx.sort_pairs(kd, vd, bits)
+    torch.cuda.synchronize()
+    # unsigned order: flip the sign bit to sort as signed
+    ku = keys ^ (-(2 ** 63)) if bits == 64 else keys
+    ref_k, ref_i = torch.sort(ku, stable=True)
+    if bits == 64:
+        ref_k = ref_k ^ (-(2 ** 63))
+    assert torch.equal(kd.cpu(), ref_k)
+    assert torch.equal(vd.cpu(), ref_i.to(torch.int32))
+
+
+def _check_bvh(nodes, tris, n):
+    assert nodes.shape[0] == max(n - 1, 1)
+    links = nodes[:, 12:14].view(np.int32).view(np.uint32)
+    LEAF = np.uint32(0x80000000)
+    seen_leaf = np.zeros(n, dtype=np.int64)
+    seen_node = np.zeros(nodes.shape[0], dtype=np.int64)
+    V = tris.reshape(-1, 3, 4)[:, :, :3]
+    tlo, thi = V.min(axis=1), V.max(axis=1)
+    for p in range(nodes.shape[0]):
+        for side in range(2):
+            c = links[p, side]
+            box = nodes[p, side * 6: side * 6 + 6]
+            if c & LEAF:
+                k = int(c & ~LEAF)
+                seen_leaf[k] += 1
+                assert np.all(box[:3] == tlo[k]) and np.all(box[3:] == thi[k])
+            else:
+                seen_node[int(c)] += 1
+                child = nodes[int(c)]
+                lo = np.minimum(child[0:3], child[6:9])
+                hi = np.maximum(child[3:6], child[9:12])
+                assert np.all(box[:3] == lo) and np.all(box[3:] == hi)
+    if n > 1:
+        assert np.all(seen_leaf == 1)
+        assert seen_node[0] == 0 and np.all(seen_node[1:] == 1)
+
+
+@pytest.mark.parametrize("n,p,seed", [(8, 0.5, 1), (16, 0.5, 0), (24, 0.7, 2)])
+def test_bvh_structure(ctx, n, p, seed):
+    m = fg.make_grf_foam(n, p, 2.0, seed=seed)
+    sid = ctx.load_scene(m)
+    info = ctx.scene_info(sid)
+    assert info["n_tris"] == m.n_tris and info["n_dropped"] == 0
+    nodes, tris = ctx.bvh_download(sid)
+    _check_bvh(nodes, tris, m.n_tris)
+    # every caller triangle appears once in the sorted array, unchanged
+    oid = tris[:, 3].view(np.int32)
+    assert np.array_equal(np.sort(oid), np.arange(m.n_tris))
+    assert np.array_equal(tris.reshape(-1, 3, 4)[:, :, :3], m.verts[m.tris[oid]])
+    assert 1 <= info["bvh_depth"] < 100
+
+
+def test_bvh_single_and_empty(ctx):
+    m = fg.flat_plane()
+    one = fg.Mesh(m.verts, m.tris[:1], m.box_lo, m.box_hi, m.flags, {})
+    sid = ctx.load_scene(one)
+    nodes, tris = ctx.bvh_download(sid)
+    assert nodes.shape[0] == 1
+    empty = fg.Mesh(m.verts, m.tris[:0], m.box_lo, m.box_hi, m.flags, {})
+    ctx.load_scene(empty)
+
+
+# ---------------------------------------------------------------- first hit
+
+def _first_hit_parity(ctx, torch, oracle_lib, mesh, rays64, min_agree):
+    rays32 = rays64.astype(np.float32)
+    sid = ctx.load_scene(mesh)
+    tri_g, t_g = ctx.first_hit(sid, torch.from_numpy(rays32).cuda())
+    tri_g = tri_g.cpu().numpy()
+    t_g = t_g.cpu().numpy().astype(np.float64)
+    tri_o, t_o, _ = oracle_lib.first_hit(mesh, rays32.astype(np.float64))
+    agree = tri_g == tri_o
+    frac = agree.mean()
+    assert frac >= min_agree, (frac, np.nonzero(~agree)[0][:10])
+    # Distance tolerance: 1e-5 relative, floored by the FP32 coordinate
+    # quantum of the cell (16 half-ulps of its largest extent) for short hits.
+    L = max(h - l for l, h in zip(mesh.box_lo, mesh.box_hi))
+    tol = np.maximum(1e-5 * t_o, 16 * 2.0 ** -24 * L)
+    err = np.abs(t_g - t_o)
+    bad = agree & (err > tol)
+    assert not bad.any(), list(zip(t_o[bad][:5], t_g[bad][:5]))
+    # disagreements must be near-ties: both found a surface at the same distance
+    dis = ~agree
+    assert not (dis & (err > tol)).any(), list(zip(tri_g[dis][:5], tri_o[dis][:5], t_g[dis][:5], t_o[dis][:5]))
+    return frac
+
+
+def test_first_hit_primaries_tiny_foam(ctx, torch, oracle_lib, tiny):
+    rays = fg.top_rays(tiny, 20000, seed=7, theta_max_deg=80.0)
+    _first_hit_parity(ctx, torch, oracle_lib, tiny, rays, 0.9999)
+
+
+def test_first_hit_surface_rays_tiny_foam(ctx, torch, oracle_lib, tiny):
+    rays = fg.surface_rays(tiny, 20000, seed=8)
+    _first_hit_parity(ctx, torch, oracle_lib, tiny, rays, 0.9999)
+
+
+def test_first_hit_soup_and_plane(ctx, torch, oracle_lib):
+    m = fg.random_soup(200, seed=3)
+    rng = np.random.default_rng(4)
+    o = rng.uniform(0.1, 3.9, size=(5000, 3))
+    d = rng.normal(size=(5000, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    _first_hit_parity(ctx, torch, oracle_lib, m, np.concatenate([o, d], 1), 0.9999)
+    _first_hit_parity(ctx, torch, oracle_lib, fg.trench(), fg.top_rays(fg.trench(), 4000, seed=5), 0.9999)
+
+
+@pytest.mark.slow
+def test_first_hit_sample_of_128_foam(ctx, torch, oracle_lib):
+    """Subsample of rays on the 128^3, porosity 0.6 foam (about 1.9M triangles)."""
+    m = fg.make_grf_foam(128, 0.6, 2.0, seed=1)
+    rays = np.concatenate([fg.top_rays(m, 1500, seed=11), fg.surface_rays(m, 1500, seed=12)])
+    _first_hit_parity(ctx, torch, oracle_lib, m, rays, 0.999)
+
+
+# ---------------------------------------------------------------- cascades
+
+def test_flat_plane_yield_is_the_table(ctx, vaughan):
+    sid = ctx.load_scene(fg.flat_plane())
+    tid = ctx.load_tables(vaughan)
+    for E, th in [(500.0, 0.0), (100.0, 30.0), (1000.0, 60.0), (60.0, 80.0)]:
+        n = 200000
+        r = ctx.trace(sid, tid, E, th, n, seed=11)
+        ref = float(fg.bilinear_reference(vaughan, E, th))
+        f = ref - math.floor(ref)
+        assert abs(r["yield"] - ref) <= 3 * math.sqrt(f * (1 - f) / n), (E, th, r["yield"], ref)
+        assert r["n_escaped"] == r["n_rays"] - n
+
+
+@pytest.mark.parametrize("const", [0.0, 1.0, 2.0])
+def test_flat_plane_integral_yields(ctx, const):
+    sid = ctx.load_scene(fg.flat_plane())
+    tid = ctx.load_tables(fg.make_tables("constant", const=const))
+    n = 50000
+    r = ctx.trace(sid, tid, 300.0, 20.0, n, seed=3)
+    assert r["n_escaped"] == int(const) * n and r["yield_sigma"] == 0.0
+
+
+def test_trench_view_factor(ctx, vaughan):
+    sid = ctx.load_scene(fg.trench())
+    tid = ctx.load_tables(vaughan)
+    r = ctx.trace(sid, tid, 500.0, 0.0, 400000, seed=21, max_gen=1)
+    d0 = float(fg.bilinear_reference(vaughan, 500.0, 0.0))
+    F = math.sqrt(1 + 1.5 ** 2) - 1.5
+    expect = d0 * (1 / 3 + 2 / 3 * F)
+    assert abs(r["yield"] - expect) <= 3 * r["yield_sigma"], (r["yield"], expect)
+
+
+def test_yield_parity_tiny_foam(ctx, torch, oracle_lib, tiny, vaughan):
+    """The 16^3 foam, 1e4 primaries at 500 eV, normal incidence: paired and unpaired."""
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    n = 10000
+    pp = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    g = ctx.trace(sid, tid, 500.0, 0.0, n, seed=1, per_primary=pp)
+    o = oracle_lib.trace(tiny, vaughan, 500.0, 0.0, n, seed=1, per_primary=True)
+    sig = math.sqrt(g["yield_sigma"] ** 2 + o["yield_sigma"] ** 2)
+    assert abs(g["yield"] - o["yield"]) <= 3 * sig
+    ppg = pp.cpu().numpy().astype(np.int64)
+    ppo = o["per_primary"]["escaped"].astype(np.int64)
+    assert int(ppg.sum()) == g["n_escaped"]
+    same = (ppg == ppo).mean()
+    assert same >= 0.995, same
+    diff = ppg - ppo
+    assert abs(diff.mean()) <= 3 * diff.std(ddof=1) / math.sqrt(n) + 1e-12
+
+
+@pytest.mark.parametrize("E,theta", [(100.0, 0.0), (800.0, 40.0), (250.0, -80.0)])
+def test_yield_parity_points(ctx, oracle_lib, tiny, vaughan, E, theta):
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    n = 6000
+    g = ctx.trace(sid, tid, E, theta, n, seed=2)
+    o = oracle_lib.trace(tiny, vaughan, E, theta, n, seed=2)
+    sig = math.sqrt(g["yield_sigma"] ** 2 + o["yield_sigma"] ** 2)
+    assert abs(g["yield"] - o["yield"]) <= 3 * sig
+
+
+def test_conservation_and_counts(ctx, tiny, vaughan):
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    n = 50000
+    r = ctx.trace(sid, tid, 700.0, -80.0, n, seed=5, max_gen=6)
+    assert r["e_escaped"] + r["e_deposited"] == pytest.approx(700.0 * n, rel=1e-12)
+    assert r["n_rays"] == r["n_escaped"] + r["n_absorbed"] + r["n_truncated"] + r["n_lost"]
+    assert r["n_rays"] == n + r["n_spawned"]
+    assert int(r["e_hist"].sum()) == r["n_escaped"] == int(r["a_hist"].sum())
+
+
+def test_resume_and_determinism(ctx, torch, tiny, vaughan):
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    n, k = 30000, 12345
+    full = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    a = torch.zeros(k, dtype=torch.int32, device="cuda:0")
+    b = torch.zeros(n - k, dtype=torch.int32, device="cuda:0")
+    r = ctx.trace(sid, tid, 400.0, 30.0, n, seed=9, per_primary=full)
+    ra = ctx.trace(sid, tid, 400.0, 30.0, k, seed=9, per_primary=a)
+    rb = ctx.trace(sid, tid, 400.0, 30.0, n - k, seed=9, pid0=k, per_primary=b)
+    assert torch.equal(full, torch.cat([a, b]))
+    assert r["n_escaped"] == ra["n_escaped"] + rb["n_escaped"]
+    assert np.array_equal(r["e_hist"], ra["e_hist"] + rb["e_hist"])
+    r2 = ctx.trace(sid, tid, 400.0, 30.0, n, seed=9)
+    for key in ("n_rays", "n_escaped", "n_node_visits", "n_tri_tests", "e_escaped"):
+        assert r2[key] == r[key]
+
+
+def test_chunking_does_not_change_results(ctx, tiny, vaughan):
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    cfg = ctx.get_launch()
+    r1 = ctx.trace(sid, tid, 500.0, 0.0, 20000, seed=4)
+    ctx.set_launch(cfg["block"], cfg["wg_per_cu"], cfg["lds_stack"], 3000)
+    try:
+        r2 = ctx.trace(sid, tid, 500.0, 0.0, 20000, seed=4)
+    finally:
+        ctx.set_launch(**cfg)
+    assert r2["n_chunks"] == 7
+    for key in ("n_rays", "n_escaped", "n_absorbed", "e_escaped", "n_tri_tests"):
+        assert r1[key] == r2[key]
+    assert np.array_equal(r1["e_hist"], r2["e_hist"])
+
+
+def test_batch_equals_single_jobs(ctx, tiny, vaughan):
+    s1 = ctx.load_scene(tiny)
+    s2 = ctx.load_scene(fg.make_grf_foam(12, 0.7, 2.0, seed=5))
+    tid = ctx.load_tables(vaughan)
+    jobs = [(s1, 500.0, 0.0, 7000, 1), (s2, 100.0, 40.0, 3000, 2), (s1, 250.0, -80.0, 5000, 3),
+            (s2, 1000.0, 60.0, 1, 4)]
+    outs = ctx.trace_batch(tid, jobs, max_gen=6)
+    for (s, E, th, n, sd), b in zip(jobs, outs):
+        r = ctx.trace(s, tid, E, th, n, seed=sd, max_gen=6)
+        for key in ("n_rays", "n_escaped", "n_absorbed", "n_truncated", "n_lost", "n_tri_tests", "n_node_visits",
+                    "e_escaped"):
+            assert b[key] == r[key], (key, b[key], r[key])
+
+
+def test_errors_are_reported(ctx, vaughan):
+    import paper_1806_00205_amd as rt
+    m = fg.flat_plane()
+    sid = ctx.load_mesh(m.verts, m.tris, m.box_lo, m.box_hi, m.flags)
+    tid = ctx.load_tables(vaughan)
+    with pytest.raises(rt.RtmcError) as e:
+        ctx.trace(sid, tid, 500.0, 0.0, 10, seed=1)
+    assert e.value.status == -4  # no BVH yet
+    bad = m.verts.copy()
+    bad[0, 0] = np.nan
+    with pytest.raises(rt.RtmcError):
+        ctx.load_mesh(bad, m.tris, m.box_lo, m.box_hi, m.flags)
+    with pytest.raises(rt.RtmcError):
+        ctx.load_mesh(m.verts, m.tris + 10, m.box_lo, m.box_hi, m.flags)
+    zero = fg.Mesh(np.concatenate([m.verts, m.verts[:1]]), np.concatenate([m.tris, [[4, 4, 0]]]).astype(np.int32),
+                   m.box_lo, m.box_hi, m.flags, {})
+    s2 = ctx.load_scene(zero)
+    assert ctx.scene_info(s2)["n_dropped"] == 1
