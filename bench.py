@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBPS = 8000.0  # MI355X published HBM3E bandwidth
-Q_BYTES = 40  # one queued ray: 10 x 32-bit streams
+Q_READ_BYTES = 24  # traversal reads origin + direction of a queued ray (6 x 32-bit streams)
+HIT_BYTES = 28  # one hit record: 7 x 32-bit streams
 NODE_BYTES = 64
 TRI_BYTES = 48
 
@@ -51,7 +52,7 @@ def kernel_hash() -> str:
 
 def load_traffic(cfg_name: str):
     """Measured HBM bytes per algorithmic byte from a committed counter summary, if current."""
-    path = os.path.join(ROOT, "profiles", f"k_trace_{cfg_name}_traffic.json")
+    path = os.path.join(ROOT, "profiles", f"k_traverse_{cfg_name}_traffic.json")
     if not os.path.exists(path):
         return None
     d = json.load(open(path))
@@ -106,7 +107,7 @@ def main():
         step()
         print(f"[bench] warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
-    tot = dict(prim=0, rays=0, tests=0, visits=0, spawned=0, kms=0.0, launches=0)
+    tot = dict(prim=0, rays=0, tests=0, visits=0, spawned=0, kms=0.0, sms=0.0, launches=0)
     t_start = time.perf_counter()
     last = None
     for s in range(args.steps):
@@ -118,6 +119,7 @@ def main():
             tot["visits"] += r["n_node_visits"]
             tot["spawned"] += r["n_spawned"]
             tot["kms"] += r["kernel_ms"]
+            tot["sms"] += r["shade_ms"]
             tot["launches"] += r["n_kernel_launches"]
         print(f"[bench] step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
@@ -125,9 +127,9 @@ def main():
     ms_per_step = wall * 1e3 / args.steps
     prim_s = tot["prim"] / wall
     # algorithmic bytes of the traversal kernel: node and triangle fetches,
-    # queue reads of secondary rays, queue writes of daughters
+    # origin + direction reads of queued (secondary) rays, hit-record writes
     alg_bytes = (NODE_BYTES * tot["visits"] + TRI_BYTES * tot["tests"] +
-                 Q_BYTES * (tot["rays"] - tot["prim"]) + Q_BYTES * tot["spawned"])
+                 Q_READ_BYTES * (tot["rays"] - tot["prim"]) + HIT_BYTES * tot["rays"])
     achieved = alg_bytes / (tot["kms"] * 1e-3) / 1e9 if tot["kms"] > 0 else 0.0
     achievable = ctx.copy_probe(1 << 32, reps=5)
     traffic = load_traffic(args.config)
@@ -162,8 +164,9 @@ def main():
             "frac": achieved / PEAK_HBM_GBPS,
             "traffic": (traffic["fetch_plus_write_bytes_per_alg_byte"] * alg_bytes / max(tot["launches"], 1)
                         if traffic else None),
-            "kernel": "k_trace",
+            "kernel": "k_traverse",
             "kernel_ms_total": tot["kms"],
+            "shade_ms_total": tot["sms"],
             "kernel_launches": tot["launches"],
             "alg_bytes_per_launch": alg_bytes / max(tot["launches"], 1),
             "achievable_copy_gbps": achievable,

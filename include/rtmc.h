@@ -110,16 +110,18 @@ typedef struct {
   double ms;           /* elapsed device time of the whole launch sequence */
   double kernel_ms;    /* summed duration of the traversal-kernel launches (HIP events around
                           each launch; 0 for rtmc_trace_batch, which replays a graph) */
+  double shade_ms;     /* summed duration of the shading-kernel launches (same rules) */
   uint64_t n_kernel_launches;
   int32_t n_chunks;    /* primary chunks used (grows when a queue would overflow) */
 } rtmc_result;
 
-/* Launch shape of the trace kernels (rtmc_autotune picks one). */
+/* Launch shape of the traversal kernel (rtmc_autotune picks one). */
 typedef struct {
-  int32_t block;     /* threads per workgroup: 64..1024, multiple of 64 */
+  int32_t block;     /* threads per workgroup: 64..256, multiple of 64 */
   int32_t wg_per_cu; /* persistent workgroups per compute unit, >= 1 */
   int32_t lds_stack; /* traversal stack entries per lane held in LDS, 4..64 */
   int32_t chunk;     /* primaries per chunk; sizes the daughter queues */
+  int32_t refill;    /* a wave fetches new rays once this many of its 64 lanes are idle, 1..64 */
 } rtmc_launch_cfg;
 
 typedef struct {

@@ -61,14 +61,16 @@ class Result(C.Structure):
                                           "n_lost", "n_substrate", "n_wraps", "n_node_visits", "n_tri_tests",
                                           "n_spawned")] + \
                [("e_escaped", C.c_double), ("e_deposited", C.c_double), ("ms", C.c_double),
-                ("kernel_ms", C.c_double), ("n_kernel_launches", C.c_uint64), ("n_chunks", C.c_int32)]
+                ("kernel_ms", C.c_double), ("shade_ms", C.c_double), ("n_kernel_launches", C.c_uint64),
+                ("n_chunks", C.c_int32)]
 
     def to_dict(self):
         return {f[0].rstrip("_"): getattr(self, f[0]) for f in self._fields_}
 
 
 class LaunchCfg(C.Structure):
-    _fields_ = [("block", C.c_int32), ("wg_per_cu", C.c_int32), ("lds_stack", C.c_int32), ("chunk", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("wg_per_cu", C.c_int32), ("lds_stack", C.c_int32), ("chunk", C.c_int32),
+                ("refill", C.c_int32)]
 
 
 class SceneInfo(C.Structure):
@@ -265,8 +267,8 @@ class Context:
         self._chk(self.lib.rtmc_sort_pairs_u64(self.h, C.c_void_p(keys.data_ptr()), C.c_void_p(vals.data_ptr()),
                                                keys.numel(), int(key_bits)))
 
-    def set_launch(self, block: int, wg_per_cu: int, lds_stack: int, chunk: int):
-        self._chk(self.lib.rtmc_set_launch(self.h, C.byref(LaunchCfg(block, wg_per_cu, lds_stack, chunk))))
+    def set_launch(self, block: int, wg_per_cu: int, lds_stack: int, chunk: int, refill: int = 16):
+        self._chk(self.lib.rtmc_set_launch(self.h, C.byref(LaunchCfg(block, wg_per_cu, lds_stack, chunk, refill))))
 
     def get_launch(self) -> dict:
         c = LaunchCfg()

@@ -56,9 +56,10 @@ struct rtmc_ctx {
   size_t lds_per_block = 0;
   std::vector<Scene> scenes;
   std::vector<Tables> tables;
-  rtmc_launch_cfg cfg{256, 3, 16, 1 << 21};
+  rtmc_launch_cfg cfg{256, 8, 16, 1 << 21, 16};
   // trace work buffers, grown on demand
   DevBuf queue[2];
+  DevBuf hits;  // hit records, qcap entries
   uint32_t qcap = 0;
   DevBuf gstack;
   DevBuf counters, ppc, err_word, jobs, tally;
@@ -161,39 +162,47 @@ struct TraceOut {
   int n_chunks = 0;
   double ms = 0.0;
   double kernel_ms = 0.0;
+  double shade_ms = 0.0;
   uint64_t launches = 0;
 };
 
-// Enqueue the launch sequence of a batch of jobs with a given chunk size.
+HitRecs hit_recs(void* base, size_t cap) {
+  HitRecs h;
+  uint32_t* u = reinterpret_cast<uint32_t*>(base);
+  h.code = reinterpret_cast<int32_t*>(u);
+  h.f0 = reinterpret_cast<float*>(u + cap);
+  h.f1 = reinterpret_cast<float*>(u + 2 * cap);
+  h.t = reinterpret_cast<float*>(u + 3 * cap);
+  h.visits = u + 4 * cap;
+  h.tests = u + 5 * cap;
+  h.wraps = u + 6 * cap;
+  return h;
+}
+
+constexpr int kShadeBlock = 256;
+
+// Enqueue the launch sequence of a batch of jobs with a given chunk size:
+// per chunk and generation, traversal then shading.
 rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJob>& jobs, int max_gen,
                           int n_ebins, int n_abins, const rtmc_launch_cfg& cfg, uint32_t chunk, hipStream_t s,
                           uint64_t total, bool timed, uint64_t* n_launch) {
   const int block = cfg.block;
   const int grid = grid_of(c, cfg);
-  const int wpb = block / 64;
+  const int sgrid = c->n_cu * 4;
   const uint64_t n_chunks = (total + chunk - 1) / chunk;
   const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins;
   const int ncnt = 2 * (kMaxGen + 2);
   int gdepth = kGlobalStack;
   for (auto& j : jobs) gdepth = std::max(gdepth, c->scenes[j.scene].depth + 2);
+  bool multi = false;
+  for (auto& j : jobs) multi = multi || j.scene != jobs[0].scene;
+  multi = multi || jobs.size() > 1;
 
   HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->tally.p), 0ull, tw * jobs.size(), s));
   HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->counters.p), 0u, (size_t)ncnt * n_chunks, s));
   HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->err_word.p), 0u, 1, s));
 
-  TraceArgs a{};
-  a.jobs = reinterpret_cast<const DevJob*>(c->jobs.p);
-  a.n_jobs = (int32_t)jobs.size();
-  a.tb = dev_tables(tb);
-  a.qcap = (uint32_t)std::min<uint64_t>((uint64_t)chunk * tb.max_d, c->qcap);
-  a.max_gen = max_gen;
-  a.n_ebins = n_ebins;
-  a.n_abins = n_abins;
-  a.gstack = reinterpret_cast<uint32_t*>(c->gstack.p);
-  a.lds_stack = cfg.lds_stack;
-  a.gstack_depth = gdepth;
-  a.err = reinterpret_cast<uint32_t*>(c->err_word.p);
-  a.ppc = reinterpret_cast<uint32_t*>(c->ppc.p);
+  const uint32_t qcap = (uint32_t)std::min<uint64_t>((uint64_t)chunk * tb.max_d, c->qcap);
   RayQueue q[2];
   for (int i = 0; i < 2; ++i) {
     float* f = reinterpret_cast<float*>(c->queue[i].p);
@@ -209,37 +218,75 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
     q[i].ci = reinterpret_cast<uint32_t*>(f + 8 * Q);
     q[i].meta = reinterpret_cast<uint32_t*>(f + 9 * Q);
   }
-  (void)wpb;
+  const HitRecs hr = hit_recs(c->hits.p, c->qcap);
+  uint32_t* errw = reinterpret_cast<uint32_t*>(c->err_word.p);
+
+  TraverseArgs ta{};
+  ta.jobs = reinterpret_cast<const DevJob*>(c->jobs.p);
+  ta.n_jobs = (int32_t)jobs.size();
+  ta.qcap = qcap;
+  ta.hit = hr;
+  ta.gstack = reinterpret_cast<uint32_t*>(c->gstack.p);
+  ta.lds_stack = cfg.lds_stack;
+  ta.gstack_depth = gdepth;
+  ta.refill = cfg.refill;
+  ta.err = errw;
+
+  ShadeArgs sa{};
+  sa.jobs = ta.jobs;
+  sa.n_jobs = ta.n_jobs;
+  sa.tb = dev_tables(tb);
+  sa.qcap = qcap;
+  sa.ppc = reinterpret_cast<uint32_t*>(c->ppc.p);
+  sa.max_gen = max_gen;
+  sa.n_ebins = n_ebins;
+  sa.n_abins = n_abins;
+  sa.hit = hr;
+  sa.err = errw;
+
+  auto ev = [&](size_t k) -> hipEvent_t {
+    while (c->kev.size() <= k) {
+      hipEvent_t e;
+      if (hipEventCreate(&e) != hipSuccess) return nullptr;
+      c->kev.push_back(e);
+    }
+    return c->kev[k];
+  };
   for (uint64_t ch = 0; ch < n_chunks; ++ch) {
     const uint64_t lo = ch * chunk;
     const uint32_t n_here = (uint32_t)std::min<uint64_t>(chunk, total - lo);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(c->counters.p) + ch * ncnt;
-    HIPCHK(c, launch_fill_u32(a.ppc, 0u, n_here, s));
-    a.chunk_lo = lo;
-    a.n_gen0 = n_here;
+    HIPCHK(c, launch_fill_u32(sa.ppc, 0u, n_here, s));
+    ta.chunk_lo = sa.chunk_lo = lo;
+    sa.n_gen0 = n_here;
     for (int g = 0; g <= max_gen; ++g) {
-      a.gen = g;
-      a.qin = q[g & 1];
-      a.qout = q[(g + 1) & 1];
-      a.count_in = cnt + g;  // produced by generation g - 1
-      a.count_out = cnt + g + 1;
-      a.work = cnt + (kMaxGen + 2) + g;
+      ta.src = g == 0 ? 0 : 1;
+      ta.count = n_here;
+      ta.qin = q[g & 1];
+      ta.count_in = cnt + g;  // produced by generation g - 1
+      ta.work = cnt + (kMaxGen + 2) + g;
+      sa.gen = g;
+      sa.qin = q[g & 1];
+      sa.qout = q[(g + 1) & 1];
+      sa.count_in = cnt + g;
+      sa.count_out = cnt + g + 1;
       if (timed) {
-        const size_t k = 2 * (size_t)(*n_launch);
-        while (c->kev.size() < k + 2) {
-          hipEvent_t e;
-          HIPCHK(c, hipEventCreate(&e));
-          c->kev.push_back(e);
-        }
-        HIPCHK(c, hipEventRecord(c->kev[k], s));
-        HIPCHK(c, launch_trace(a, grid, block, s));
-        HIPCHK(c, hipEventRecord(c->kev[k + 1], s));
+        const size_t k = 4 * (size_t)(*n_launch);
+        hipEvent_t e0 = ev(k), e1 = ev(k + 1), e2 = ev(k + 2), e3 = ev(k + 3);
+        if (!e0 || !e1 || !e2 || !e3) return fail(c, RTMC_EDEVICE, "event creation failed");
+        HIPCHK(c, hipEventRecord(e0, s));
+        HIPCHK(c, launch_traverse(ta, multi, grid, block, s));
+        HIPCHK(c, hipEventRecord(e1, s));
+        HIPCHK(c, hipEventRecord(e2, s));
+        HIPCHK(c, launch_shade(sa, sgrid, kShadeBlock, s));
+        HIPCHK(c, hipEventRecord(e3, s));
       } else {
-        HIPCHK(c, launch_trace(a, grid, block, s));
+        HIPCHK(c, launch_traverse(ta, multi, grid, block, s));
+        HIPCHK(c, launch_shade(sa, sgrid, kShadeBlock, s));
       }
       ++*n_launch;
     }
-    HIPCHK(c, launch_chunk_reduce(a.jobs, a.n_jobs, a.ppc, n_here, lo, s));
+    HIPCHK(c, launch_chunk_reduce(ta.jobs, ta.n_jobs, sa.ppc, n_here, lo, s));
   }
   return RTMC_OK;
 }
@@ -277,6 +324,8 @@ rtmc_status prepare_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
       st = ensure(c, c->queue[i], (size_t)need_q * 40);
       if (st) return st;
     }
+    st = ensure(c, c->hits, (size_t)need_q * 28);
+    if (st) return st;
     c->qcap = (uint32_t)need_q;
   }
   const uint64_t n_chunks = (g + chunk - 1) / chunk;
@@ -303,15 +352,11 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
     uint64_t total = 0;
     rtmc_status st = prepare_trace(c, tb, jobs, n_ebins, n_abins, cfg, &total);
     if (st) return st;
-    TraceArgs probe{};
-    probe.tb = dev_tables(tb);
-    probe.n_ebins = n_ebins;
-    probe.n_abins = n_abins;
-    probe.lds_stack = cfg.lds_stack;
-    const size_t lds = trace_lds_bytes(probe, cfg.block);
-    if (lds > c->lds_per_block)
-      return fail(c, RTMC_EINVAL, "launch shape needs %zu bytes of LDS per workgroup (device limit %zu)", lds,
-                  c->lds_per_block);
+    const size_t lds_t = traverse_lds_bytes(cfg.lds_stack, cfg.block);
+    const size_t lds_s = shade_lds_bytes(dev_tables(tb), n_ebins, n_abins, kShadeBlock);
+    if (lds_t > c->lds_per_block || lds_s > c->lds_per_block)
+      return fail(c, RTMC_EINVAL, "launch needs %zu / %zu bytes of LDS per workgroup (device limit %zu)", lds_t,
+                  lds_s, c->lds_per_block);
     hipStream_t s = use_graph ? c->gstream : c->stream;
     if (use_graph) {
       HIPCHK(c, hipEventRecord(c->ev0, c->stream));
@@ -346,13 +391,16 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
       if (st) return st;
       HIPCHK(c, hipEventRecord(c->ev1, s));
       HIPCHK(c, hipStreamSynchronize(s));
-      double kms = 0.0;
+      double kms = 0.0, sms = 0.0;
       for (uint64_t i = 0; i < nl; ++i) {
         float e = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&e, c->kev[2 * i], c->kev[2 * i + 1]));
+        HIPCHK(c, hipEventElapsedTime(&e, c->kev[4 * i], c->kev[4 * i + 1]));
         kms += e;
+        HIPCHK(c, hipEventElapsedTime(&e, c->kev[4 * i + 2], c->kev[4 * i + 3]));
+        sms += e;
       }
       out.kernel_ms = kms;
+      out.shade_ms = sms;
       out.launches = nl;
     }
     float ms = 0.f;
@@ -403,6 +451,7 @@ void fill_result(const unsigned long long* t, const HostJob& j, int n_ebins, int
   }
   r->ms = to.ms;
   r->kernel_ms = to.kernel_ms;
+  r->shade_ms = to.shade_ms;
   r->n_kernel_launches = to.launches;
   r->n_chunks = to.n_chunks;
   if (eh)
@@ -457,6 +506,7 @@ void rtmc_destroy(rtmc_ctx* c) {
   for (auto& t : c->tables) dev_free(c, t.buf);
   dev_free(c, c->queue[0]);
   dev_free(c, c->queue[1]);
+  dev_free(c, c->hits);
   dev_free(c, c->gstack);
   dev_free(c, c->counters);
   dev_free(c, c->ppc);
@@ -774,6 +824,7 @@ rtmc_status rtmc_first_hit(rtmc_ctx* c, int32_t scene_id, const float* rays, int
   if (st) return st;
   c->err.clear();
   if (n < 0 || (n > 0 && (!rays || !tri_out || !t_out))) return fail(c, RTMC_EINVAL, "bad ray arrays");
+  if (n >= (int64_t)0xFFFFFFF0) return fail(c, RTMC_EINVAL, "too many rays");
   if (n == 0) return RTMC_OK;
   HIPCHK(c, hipSetDevice(c->device));
   const Scene& s = c->scenes[scene_id];
@@ -783,8 +834,42 @@ rtmc_status rtmc_first_hit(rtmc_ctx* c, int32_t scene_id, const float* rays, int
   const size_t waves = (size_t)grid * (block / 64);
   st = ensure(c, c->gstack, waves * gdepth * 64 * 4);
   if (st) return st;
-  HIPCHK(c, launch_first_hit(dev_scene(s), rays, n, tri_out, t_out, reinterpret_cast<uint32_t*>(c->gstack.p),
-                             c->cfg.lds_stack, gdepth, grid, block, c->stream));
+  // job 0 carries the scene; hit records go to scratch except code and t
+  DevJob dj{};
+  dj.sc = dev_scene(s);
+  DevBuf scratch;
+  st = ensure(c, scratch, (size_t)n * 20 + 64 + sizeof(DevJob));
+  if (st) return st;
+  uint32_t* u = reinterpret_cast<uint32_t*>(scratch.p);
+  DevJob* djd = reinterpret_cast<DevJob*>(u + 5 * (size_t)n + 16);
+  hipError_t e = hipMemcpyAsync(djd, &dj, sizeof(dj), hipMemcpyHostToDevice, c->stream);
+  TraverseArgs ta{};
+  ta.jobs = djd;
+  ta.n_jobs = 1;
+  ta.src = 2;
+  ta.rays = rays;
+  ta.count = (uint32_t)n;
+  ta.hit.code = tri_out;
+  ta.hit.t = t_out;
+  ta.hit.f0 = reinterpret_cast<float*>(u);
+  ta.hit.f1 = reinterpret_cast<float*>(u + n);
+  ta.hit.visits = u + 2 * (size_t)n;
+  ta.hit.tests = u + 3 * (size_t)n;
+  ta.hit.wraps = u + 4 * (size_t)n;
+  ta.work = u + 5 * (size_t)n;
+  ta.err = ta.work + 1;
+  ta.gstack = reinterpret_cast<uint32_t*>(c->gstack.p);
+  ta.lds_stack = c->cfg.lds_stack;
+  ta.gstack_depth = gdepth;
+  ta.refill = c->cfg.refill;
+  if (e == hipSuccess) e = launch_fill_u32(ta.work, 0u, 2, c->stream);
+  if (e == hipSuccess) e = launch_traverse(ta, false, grid, block, c->stream);
+  if (e == hipSuccess)
+    e = launch_hit_ids(reinterpret_cast<const float4*>(s.tris.p), tri_out, n, tri_out, c->stream);
+  // the scratch is released only after the launches that use it have finished
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  dev_free(c, scratch);
+  if (e != hipSuccess) return fail(c, RTMC_EDEVICE, "first hit: %s", hipGetErrorString(e));
   return RTMC_OK;
 }
 
@@ -820,8 +905,8 @@ rtmc_status rtmc_sort_pairs_u64(rtmc_ctx* c, uint64_t* keys, uint32_t* vals, int
 
 rtmc_status rtmc_set_launch(rtmc_ctx* c, const rtmc_launch_cfg* cfg) {
   if (!c) return RTMC_EINVAL;
-  if (!cfg || cfg->block < 64 || cfg->block > 1024 || cfg->block % 64 || cfg->wg_per_cu < 1 || cfg->wg_per_cu > 64 ||
-      cfg->lds_stack < 4 || cfg->lds_stack > 64 || cfg->chunk < 1)
+  if (!cfg || cfg->block < 64 || cfg->block > 256 || cfg->block % 64 || cfg->wg_per_cu < 1 || cfg->wg_per_cu > 64 ||
+      cfg->lds_stack < 4 || cfg->lds_stack > 64 || cfg->chunk < 1 || cfg->refill < 1 || cfg->refill > 64)
     return fail(c, RTMC_EINVAL, "bad launch shape");
   c->cfg = *cfg;
   return RTMC_OK;
@@ -837,37 +922,59 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
                           uint64_t n_primaries, rtmc_launch_cfg* best) {
   rtmc_status st = check_scene(c, scene_id, true);
   if (st) return st;
+  if (table_id < 0 || table_id >= (int32_t)c->tables.size()) return fail(c, RTMC_EINVAL, "unknown table id %d", table_id);
   const rtmc_launch_cfg keep = c->cfg;
-  const int blocks[] = {256, 512};
-  const int wgs[] = {1, 2, 3, 4, 6, 8};
-  const int stacks[] = {8, 12, 16, 24};
+  // coordinate search: one knob at a time, starting from the current shape
+  rtmc_launch_cfg cur = keep;
+  auto time_cfg = [&](const rtmc_launch_cfg& cf, double* ms) -> rtmc_status {
+    if (traverse_lds_bytes(cf.lds_stack, cf.block) > c->lds_per_block) {
+      *ms = 1e30;
+      return RTMC_OK;
+    }
+    c->cfg = cf;
+    rtmc_result r;
+    rtmc_status s2 = rtmc_trace(c, scene_id, table_id, E_eV, theta_deg, n_primaries, 12345, nullptr, &r);
+    *ms = s2 ? 1e30 : r.kernel_ms + r.shade_ms;
+    return s2;
+  };
   double best_ms = 1e30;
-  rtmc_launch_cfg bestc = keep;
-  for (int b : blocks)
-    for (int w : wgs)
-      for (int sd : stacks) {
-        rtmc_launch_cfg cf{b, w, sd, keep.chunk};
-        TraceArgs probe{};
-        probe.tb = dev_tables(c->tables[table_id]);
-        probe.n_ebins = 256;
-        probe.n_abins = 90;
-        probe.lds_stack = sd;
-        if (trace_lds_bytes(probe, b) > c->lds_per_block) continue;
-        if (b / 64 * w > 32) continue;  // more waves per CU than the hardware holds
-        c->cfg = cf;
-        rtmc_result r;
-        st = rtmc_trace(c, scene_id, table_id, E_eV, theta_deg, n_primaries, 12345, nullptr, &r);
+  st = time_cfg(cur, &best_ms);
+  if (st) {
+    c->cfg = keep;
+    return st;
+  }
+  const int blocks[] = {64, 128, 256};
+  const int wgs[] = {2, 4, 6, 8, 12, 16};
+  const int stacks[] = {8, 12, 16, 24, 32};
+  const int refills[] = {1, 8, 16, 32, 48, 64};
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int knob = 0; knob < 4; ++knob) {
+      const int n = knob == 0 ? 3 : (knob == 1 ? 6 : (knob == 2 ? 5 : 6));
+      for (int i = 0; i < n; ++i) {
+        rtmc_launch_cfg cf = cur;
+        if (knob == 0) {
+          cf.block = blocks[i];
+          cf.wg_per_cu = std::max(1, cur.wg_per_cu * cur.block / blocks[i]);
+        }
+        if (knob == 1) cf.wg_per_cu = wgs[i] * 256 / cf.block;
+        if (knob == 2) cf.lds_stack = stacks[i];
+        if (knob == 3) cf.refill = refills[i];
+        if (cf.wg_per_cu < 1 || cf.wg_per_cu > 64) continue;
+        double ms;
+        st = time_cfg(cf, &ms);
         if (st) {
           c->cfg = keep;
           return st;
         }
-        if (r.ms < best_ms) {
-          best_ms = r.ms;
-          bestc = cf;
+        if (ms < best_ms) {
+          best_ms = ms;
+          cur = cf;
         }
       }
-  c->cfg = bestc;
-  if (best) *best = bestc;
+    }
+  }
+  c->cfg = cur;
+  if (best) *best = cur;
   return RTMC_OK;
 }
 

@@ -9,6 +9,8 @@
 //              16-byte loads from one cache line.
 //   ray queue  structure of arrays, ten 32-bit streams, written and read
 //              coalesced by whole waves.
+//   hit records structure of arrays, seven 32-bit streams, one entry per ray
+//              of the generation being processed.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -85,31 +87,59 @@ struct RayQueue {
   uint32_t* meta;  // gen (4 bits) | job << 4
 };
 
-struct TraceArgs {
+// Per-ray result of the traversal launch (structure of arrays).
+struct HitRecs {
+  int32_t* code;  // sorted triangle index, or -1 escape, -2 substrate, -3 lost
+  float* f0;      // barycentric weight of V1, or substrate x
+  float* f1;      // barycentric weight of V2, or substrate y
+  float* t;       // path length over all periodic segments
+  uint32_t* visits;
+  uint32_t* tests;
+  uint32_t* wraps;  // bit 31: traversal stack overflowed
+};
+
+struct TraverseArgs {
+  const DevJob* jobs;
+  int32_t n_jobs;
+  int32_t src;               // 0: primaries of the chunk, 1: queue, 2: explicit rays
+  RayQueue qin;
+  const float* rays;         // src 2: [n][6]
+  uint32_t count;            // src 0 and 2
+  const uint32_t* count_in;  // src 1
+  uint32_t qcap;
+  uint64_t chunk_lo;
+  HitRecs hit;
+  uint32_t* work;
+  uint32_t* gstack;
+  int32_t lds_stack;
+  int32_t gstack_depth;
+  int32_t refill;  // refill a wave once this many lanes are idle
+  uint32_t* err;   // bit 1: stack overflow
+};
+
+struct ShadeArgs {
   const DevJob* jobs;
   int32_t n_jobs;
   DevTables tb;
   RayQueue qin, qout;
   uint32_t qcap;
-  const uint32_t* count_in;  // generation > 0: queue length in device memory
-  uint32_t n_gen0;           // generation 0: primaries in this chunk
-  uint64_t chunk_lo;         // first concatenated primary index of the chunk
+  const uint32_t* count_in;
+  uint32_t n_gen0;
+  uint64_t chunk_lo;
   uint32_t* count_out;
-  uint32_t* work;            // work counter of this launch
-  uint32_t* ppc;             // per-primary escape counts of the chunk
+  uint32_t* ppc;  // per-primary escape counts of the chunk
   int32_t gen, max_gen;
   int32_t n_ebins, n_abins;
-  uint32_t* gstack;
-  int32_t lds_stack;
-  int32_t gstack_depth;
-  uint32_t* err;  // bit 0: queue overflow, bit 1: stack overflow
+  HitRecs hit;
+  uint32_t* err;  // bit 0: queue overflow
 };
 
 // host-side launchers (defined in the .hip files)
-size_t trace_lds_bytes(const TraceArgs& a, int block);
-hipError_t launch_trace(const TraceArgs& a, int grid, int block, hipStream_t s);
-hipError_t launch_first_hit(DevScene sc, const float* rays, int64_t n, int32_t* tri_out, float* t_out,
-                            uint32_t* gstack, int lds_stack, int gstack_depth, int grid, int block, hipStream_t s);
+size_t traverse_lds_bytes(int lds_stack, int block);
+size_t shade_lds_bytes(const DevTables& tb, int n_ebins, int n_abins, int block);
+hipError_t launch_traverse(const TraverseArgs& a, bool multi, int grid, int block, hipStream_t s);
+hipError_t launch_shade(const ShadeArgs& a, int grid, int block, hipStream_t s);
+hipError_t launch_hit_ids(const float4* tris, const int32_t* code, int64_t n, int32_t* out, hipStream_t s);
 hipError_t launch_chunk_reduce(const DevJob* jobs, int32_t n_jobs, const uint32_t* ppc, uint32_t n,
                                uint64_t chunk_lo, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);

@@ -1,26 +1,24 @@
 // Ray tracing Monte Carlo on gfx950: one lane per ray.
 //
-// One launch processes one generation of rays (the paper's tree of branches,
-// section 2.2, handled breadth-first across all primaries): generation 0 is
-// generated from primary ids, later generations are read from the daughter
-// queue the previous launch filled.  Per ray:
-//   - closest front-facing triangle by BVH traversal (section 2.1): robust
-//     slab tests against both child boxes of a 64-byte node record, and the
-//     watertight ray/triangle test of Woop, Benthin and Wald (JCGT 2013) with
-//     back-face culling; periodic re-entry through the x / y faces, escape
-//     through z_max, the substrate plane at z_min (section 2.2);
-//   - on a hit, the local incidence angle and the flat-surface tables give the
+// A generation of rays (the paper's tree of branches, section 2.2, handled
+// breadth-first across all primaries) is processed by two launches:
+//   k_traverse: closest front-facing triangle by BVH traversal (section 2.1):
+//     robust slab tests against both child boxes of a 64-byte node record and
+//     the watertight ray/triangle test of Woop, Benthin and Wald (JCGT 2013)
+//     with back-face culling; periodic re-entry through the x / y faces,
+//     escape through z_max, substrate plane at z_min (section 2.2).  Lanes
+//     whose ray is done fetch new rays, so waves stay full.  Output: one
+//     28-byte hit record per ray.
+//   k_shade: the local incidence angle and the flat-surface tables give the
 //     daughter count (stochastic rounding, footnote of section 2.2), energies
-//     (inverse of the tabulated CDF, truncated to the energy still available)
-//     and cosine-law directions;
-//   - daughters are appended to the next queue with one atomic per wave
-//     (wave prefix sum of the per-lane counts);
-//   - tallies go to per-wave LDS counters and histograms, flushed to the
-//     job's global tally block once per wave.
-// Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by the job seed,
-// counter (primary id, 0, path code, draw); draw 0 = birth of a primary,
-// 1 = daughter count, 2 + d = daughter d; a daughter's path code is
-// parent * 8 + d + 1.
+//     (inverse of the tabulated CDF truncated to the energy still available)
+//     and cosine-law directions; daughters are appended to the next queue with
+//     one atomic per wave; tallies go to per-wave LDS blocks.
+// Generation 0 rays are regenerated from primary ids in both launches rather
+// than stored.  Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed
+// by the job seed, counter (primary id, 0, path code, draw); draw 0 = birth
+// of a primary, 1 = daughter count, 2 + d = daughter d; a daughter's path
+// code is parent * 8 + d + 1.
 #include "rtmc_internal.h"
 
 namespace rtmc {
@@ -145,162 +143,6 @@ __device__ inline bool tri_test(const RayP& r, float4 a, float4 b, float4 c, flo
   return true;
 }
 
-struct Hit {
-  float t, b1, b2;
-  int32_t idx;  // sorted triangle index, -1 none
-  int32_t oid;  // caller's triangle index
-};
-
-// Closest hit with 0 < t <= tmax.  The stack keeps its first sd entries in
-// LDS (lstk, stride 64 words) and the rest in global memory (gstk, stride 64).
-__device__ inline void traverse(const RayP& r, const float4* __restrict__ nodes, const float4* __restrict__ tris,
-                                float tmax, Hit& h, uint32_t* lstk, uint32_t* gstk, int sd, int gd, uint32_t& visits,
-                                uint32_t& tests, bool& ovf) {
-  h.t = tmax;
-  h.idx = -1;
-  h.oid = 0x7fffffff;
-  uint32_t node = 0;
-  int sp = 0;
-  for (;;) {
-    const float4* N = nodes + 4 * (size_t)node;
-    const float4 n0 = N[0], n1 = N[1], n2 = N[2], n3 = N[3];
-    ++visits;
-    float tl, tr;
-    bool hl = box_test(r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, h.t, tl);
-    bool hr = box_test(r, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, h.t, tr);
-    const uint32_t cl = __float_as_uint(n3.x), cr = __float_as_uint(n3.y);
-#pragma unroll
-    for (int side = 0; side < 2; ++side) {
-      const bool leafhit = side == 0 ? (hl && (cl & kLeafBit)) : (hr && (cr & kLeafBit));
-      if (leafhit) {
-        const uint32_t k = (side == 0 ? cl : cr) & ~kLeafBit;
-        const float4* T = tris + 3 * (size_t)k;
-        const float4 a = T[0], b = T[1], c = T[2];
-        ++tests;
-        float t, b1, b2;
-        if (tri_test(r, a, b, c, h.t, t, b1, b2)) {
-          const int32_t oid = (int32_t)__float_as_uint(a.w);
-          if (t < h.t || (t == h.t && oid < h.oid)) {
-            h.t = t;
-            h.b1 = b1;
-            h.b2 = b2;
-            h.idx = (int32_t)k;
-            h.oid = oid;
-          }
-        }
-        if (side == 0)
-          hl = false;
-        else
-          hr = false;
-      }
-    }
-    if (hl && hr) {
-      const bool lnear = tl <= tr;
-      const uint32_t farc = lnear ? cr : cl;
-      node = lnear ? cl : cr;
-      if (sp < sd) {
-        lstk[sp * 64] = farc;
-      } else if (sp < sd + gd) {
-        gstk[(sp - sd) * 64] = farc;
-      } else {
-        ovf = true;
-        return;
-      }
-      ++sp;
-    } else if (hl) {
-      node = cl;
-    } else if (hr) {
-      node = cr;
-    } else {
-      if (sp == 0) return;
-      --sp;
-      node = sp < sd ? lstk[sp * 64] : gstk[(sp - sd) * 64];
-    }
-  }
-}
-
-enum { K_HIT = 0, K_ESCAPE = 1, K_SUBSTRATE = 2, K_LOST = 3 };
-
-struct PathOut {
-  int kind;
-  Hit h;
-  float px, py, pz;  // substrate point
-  float t_total;
-  int wraps;
-};
-
-// Follow one ray through the periodic cell (section 2.2 boundaries).
-__device__ inline void trace_path(const DevScene& sc, float ox, float oy, float oz, float dx, float dy, float dz,
-                                  uint32_t* lstk, uint32_t* gstk, int sd, int gd, uint32_t& visits,
-                                  uint32_t& tests, bool& ovf, PathOut& out) {
-  RayP r;
-  ray_setup(r, dx, dy, dz);
-  float total = 0.0f;
-  int wraps = 0;
-  const bool periodic = (sc.flags & 1u) != 0;
-  for (;;) {
-    const float tex = dx > 0.0f ? (sc.hi[0] - ox) / dx : (dx < 0.0f ? (sc.lo[0] - ox) / dx : INFINITY);
-    const float tey = dy > 0.0f ? (sc.hi[1] - oy) / dy : (dy < 0.0f ? (sc.lo[1] - oy) / dy : INFINITY);
-    const float tez = dz > 0.0f ? (sc.hi[2] - oz) / dz : (dz < 0.0f ? (sc.lo[2] - oz) / dz : INFINITY);
-    const float te0 = fmaxf(tex, 0.0f), te1 = fmaxf(tey, 0.0f), te2 = fmaxf(tez, 0.0f);
-    const float texit = fminf(fminf(te0, te1), te2);
-    r.ox = ox;
-    r.oy = oy;
-    r.oz = oz;
-    Hit h;
-    h.idx = -1;
-    if (sc.n_tris > 0) traverse(r, sc.nodes, sc.tris, texit, h, lstk, gstk, sd, gd, visits, tests, ovf);
-    if (h.idx >= 0) {
-      out.kind = K_HIT;
-      out.h = h;
-      out.t_total = total + h.t;
-      out.wraps = wraps;
-      return;
-    }
-    if (te2 <= te0 && te2 <= te1) {
-      out.t_total = total + te2;
-      out.wraps = wraps;
-      if (dz > 0.0f) {
-        out.kind = K_ESCAPE;
-      } else if (sc.flags & 2u) {
-        out.kind = K_SUBSTRATE;
-        out.px = ox + te2 * dx;
-        out.py = oy + te2 * dy;
-        out.pz = sc.lo[2];
-      } else {
-        out.kind = K_LOST;
-      }
-      return;
-    }
-    if (!periodic || ovf) {
-      out.kind = K_LOST;
-      out.t_total = total + texit;
-      out.wraps = wraps;
-      return;
-    }
-    total += texit;
-    float px = ox + texit * dx, py = oy + texit * dy, pz = oz + texit * dz;
-    if (te0 == texit)
-      px = dx > 0.0f ? sc.lo[0] : sc.hi[0];
-    else
-      px = fminf(fmaxf(px, sc.lo[0]), sc.hi[0]);
-    if (te1 == texit)
-      py = dy > 0.0f ? sc.lo[1] : sc.hi[1];
-    else
-      py = fminf(fmaxf(py, sc.lo[1]), sc.hi[1]);
-    pz = fminf(fmaxf(pz, sc.lo[2]), sc.hi[2]);
-    ox = px;
-    oy = py;
-    oz = pz;
-    if (++wraps > kWrapMax) {
-      out.kind = K_LOST;
-      out.t_total = total;
-      out.wraps = wraps;
-      return;
-    }
-  }
-}
-
 // ---------------------------------------------------------------- tables (LDS)
 
 __device__ inline float table_yield(const float* yld, const DevTables& tb, float E, float alpha) {
@@ -417,9 +259,310 @@ __device__ inline uint32_t wave_incl_scan(uint32_t v, uint32_t lane) {
   return v;
 }
 
+// ---------------------------------------------------------------- traversal
+
+enum { K_HIT = 0, K_ESCAPE = 1, K_SUBSTRATE = 2, K_LOST = 3 };
+
+// Scene fields one lane needs while it traverses.
+struct LaneScene {
+  const float4* nodes;
+  const float4* tris;
+  int32_t n_tris;
+  uint32_t flags;
+};
+
+// Per-lane traversal state: the current periodic segment of one ray.
+struct Trav {
+  RayP r;
+  float t;        // closest hit so far (starts at the segment's exit distance)
+  float b1, b2;   // barycentric weights of V1, V2 at the hit
+  int32_t idx;    // sorted triangle index of the hit, -1 none
+  int32_t oid;    // caller's triangle index of the hit
+  uint32_t node;
+  int sp;
+  float te0, te1, te2;  // distances to the x, y, z faces of the cell
+  float total;          // path length of earlier segments
+  int wraps;
+};
+
+__device__ inline void seg_begin(Trav& s, const DevScene& sc) {
+  const RayP& r = s.r;
+  const float tex = r.dx > 0.0f ? (sc.hi[0] - r.ox) / r.dx : (r.dx < 0.0f ? (sc.lo[0] - r.ox) / r.dx : INFINITY);
+  const float tey = r.dy > 0.0f ? (sc.hi[1] - r.oy) / r.dy : (r.dy < 0.0f ? (sc.lo[1] - r.oy) / r.dy : INFINITY);
+  const float tez = r.dz > 0.0f ? (sc.hi[2] - r.oz) / r.dz : (r.dz < 0.0f ? (sc.lo[2] - r.oz) / r.dz : INFINITY);
+  s.te0 = fmaxf(tex, 0.0f);
+  s.te1 = fmaxf(tey, 0.0f);
+  s.te2 = fmaxf(tez, 0.0f);
+  s.t = fminf(fminf(s.te0, s.te1), s.te2);
+  s.idx = -1;
+  s.oid = 0x7fffffff;
+  s.node = 0;
+  s.sp = 0;
+}
+
+// One node of the traversal.  Returns true when the segment's traversal has
+// finished (stack empty).  The stack keeps its first sd entries in LDS (lstk,
+// stride 64 words) and the rest in global memory (gstk, stride 64 words).
+__device__ inline bool trav_step(Trav& s, const LaneScene& L, uint32_t* lstk, uint32_t* gstk, int sd, int gd,
+                                 uint32_t& visits, uint32_t& tests, bool& ovf) {
+  const float4* N = L.nodes + 4 * (size_t)s.node;
+  const float4 n0 = N[0], n1 = N[1], n2 = N[2], n3 = N[3];
+  ++visits;
+  float tl, tr;
+  bool hl = box_test(s.r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, s.t, tl);
+  bool hr = box_test(s.r, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, s.t, tr);
+  const uint32_t cl = __float_as_uint(n3.x), cr = __float_as_uint(n3.y);
+#pragma unroll
+  for (int side = 0; side < 2; ++side) {
+    const bool leafhit = side == 0 ? (hl && (cl & kLeafBit)) : (hr && (cr & kLeafBit));
+    if (leafhit) {
+      const uint32_t k = (side == 0 ? cl : cr) & ~kLeafBit;
+      const float4* T = L.tris + 3 * (size_t)k;
+      const float4 a = T[0], b = T[1], c = T[2];
+      ++tests;
+      float t, b1, b2;
+      if (tri_test(s.r, a, b, c, s.t, t, b1, b2)) {
+        const int32_t oid = (int32_t)__float_as_uint(a.w);
+        // closest hit; equal distances go to the lower caller index
+        if (t < s.t || (t == s.t && oid < s.oid)) {
+          s.t = t;
+          s.b1 = b1;
+          s.b2 = b2;
+          s.idx = (int32_t)k;
+          s.oid = oid;
+        }
+      }
+      if (side == 0)
+        hl = false;
+      else
+        hr = false;
+    }
+  }
+  if (hl && hr) {
+    const bool lnear = tl <= tr;
+    const uint32_t farc = lnear ? cr : cl;
+    s.node = lnear ? cl : cr;
+    if (s.sp < sd) {
+      lstk[s.sp * 64] = farc;
+    } else if (s.sp < sd + gd) {
+      gstk[(s.sp - sd) * 64] = farc;
+    } else {
+      ovf = true;
+      return true;
+    }
+    ++s.sp;
+    return false;
+  }
+  if (hl) {
+    s.node = cl;
+    return false;
+  }
+  if (hr) {
+    s.node = cr;
+    return false;
+  }
+  if (s.sp == 0) return true;
+  --s.sp;
+  s.node = s.sp < sd ? lstk[s.sp * 64] : gstk[(s.sp - sd) * 64];
+  return false;
+}
+
+// End of a segment: returns the ray's outcome, or -1 when the ray re-enters
+// through the opposite x / y face and traversal continues (section 2.2
+// boundaries: periodic in x and y, substrate or open bottom at z_min,
+// escape at z_max).
+__device__ inline int seg_end(Trav& s, const DevScene& sc, bool ovf, float& px, float& py) {
+  if (s.idx >= 0) {
+    s.total += s.t;
+    return K_HIT;
+  }
+  const RayP& r = s.r;
+  if (s.te2 <= s.te0 && s.te2 <= s.te1) {
+    s.total += s.te2;
+    if (r.dz > 0.0f) return K_ESCAPE;
+    if (sc.flags & 2u) {
+      px = r.ox + s.te2 * r.dx;
+      py = r.oy + s.te2 * r.dy;
+      return K_SUBSTRATE;
+    }
+    return K_LOST;
+  }
+  const float texit = s.t;
+  if (!(sc.flags & 1u) || ovf) {
+    s.total += texit;
+    return K_LOST;
+  }
+  s.total += texit;
+  float qx = r.ox + texit * r.dx, qy = r.oy + texit * r.dy, qz = r.oz + texit * r.dz;
+  if (s.te0 == texit)
+    qx = r.dx > 0.0f ? sc.lo[0] : sc.hi[0];
+  else
+    qx = fminf(fmaxf(qx, sc.lo[0]), sc.hi[0]);
+  if (s.te1 == texit)
+    qy = r.dy > 0.0f ? sc.lo[1] : sc.hi[1];
+  else
+    qy = fminf(fmaxf(qy, sc.lo[1]), sc.hi[1]);
+  qz = fminf(fmaxf(qz, sc.lo[2]), sc.hi[2]);
+  s.r.ox = qx;
+  s.r.oy = qy;
+  s.r.oz = qz;
+  if (++s.wraps > kWrapMax) return K_LOST;
+  return -1;
+}
+
+// Primary ray of concatenated index g (Fig. flow: a uniform point of the top
+// face, azimuth uniform, fixed or uniform polar angle).
+__device__ inline void primary_ray(const DevJob& J, uint64_t g, float& ox, float& oy, float& oz, float& dx, float& dy,
+                                   float& dz) {
+  const uint64_t pid = J.pid0 + (g - J.gbase);
+  const U4 u = philox(J.seed, (uint32_t)pid, (uint32_t)(pid >> 32), 0u, 0u);
+  const float th = (J.theta >= 0.0f ? J.theta : -J.theta * u01(u.w)) * (kPi / 180.0f);
+  const float psi = 2.0f * kPi * u01(u.z);
+  ox = J.sc.lo[0] + (J.sc.hi[0] - J.sc.lo[0]) * u01(u.x);
+  oy = J.sc.lo[1] + (J.sc.hi[1] - J.sc.lo[1]) * u01(u.y);
+  oz = J.sc.hi[2];
+  const float st = sinf(th);
+  dx = st * cosf(psi);
+  dy = st * sinf(psi);
+  dz = -cosf(th);
+}
+
 extern __shared__ __align__(16) unsigned char smem[];
 
-__global__ __launch_bounds__(1024) void k_trace(TraceArgs a) {
+// Closest-hit traversal of one generation of rays.  Lanes that finish pick
+// up new rays (one atomic per refill of the wave) so that a wave is not held
+// by its slowest ray.  MULTI: rays may belong to different jobs.
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
+  const int wpb = blockDim.x >> 6;
+  const int w = threadIdx.x >> 6;
+  const uint32_t lane = lane_id();
+  const uint64_t lt = (1ull << lane) - 1ull;
+  uint32_t* lstk = reinterpret_cast<uint32_t*>(smem) + (size_t)w * a.lds_stack * 64 + lane;
+  uint32_t* gstk = a.gstack + ((size_t)(blockIdx.x * wpb + w) * a.gstack_depth) * 64 + lane;
+  const uint32_t count = a.src == 1 ? min(*a.count_in, a.qcap) : a.count;
+
+  Trav s;
+  LaneScene L;
+  int job = 0;
+  uint32_t item = 0, visits = 0, tests = 0;
+  bool have = false, ovf = false;
+  bool exhausted = false;
+  if (!MULTI) {
+    L.nodes = a.jobs[0].sc.nodes;
+    L.tris = a.jobs[0].sc.tris;
+    L.n_tris = a.jobs[0].sc.n_tris;
+    L.flags = a.jobs[0].sc.flags;
+  }
+  for (;;) {
+    const uint64_t idle = __ballot(!have);
+    const uint32_t nidle = (uint32_t)__popcll(idle);
+    if (!exhausted && nidle >= (uint32_t)a.refill) {
+      uint32_t base = 0;
+      if (lane == 0) base = atomicAdd(a.work, nidle);
+      base = __shfl(base, 0, 64);
+      if (base + nidle >= count) exhausted = true;
+      if (!have) {
+        item = base + (uint32_t)__popcll(idle & lt);
+        if (item < count) {
+          float ox, oy, oz, dx, dy, dz;
+          if (a.src == 0) {
+            const uint64_t g = a.chunk_lo + item;
+            job = MULTI ? find_job(a.jobs, a.n_jobs, g) : 0;
+            primary_ray(a.jobs[job], g, ox, oy, oz, dx, dy, dz);
+          } else if (a.src == 1) {
+            ox = a.qin.ox[item];
+            oy = a.qin.oy[item];
+            oz = a.qin.oz[item];
+            dx = a.qin.dx[item];
+            dy = a.qin.dy[item];
+            dz = a.qin.dz[item];
+            if (MULTI) job = (int)(a.qin.meta[item] >> 4);
+          } else {
+            const float* q = a.rays + 6 * (size_t)item;
+            ox = q[0];
+            oy = q[1];
+            oz = q[2];
+            dx = q[3];
+            dy = q[4];
+            dz = q[5];
+          }
+          if (MULTI) {
+            L.nodes = a.jobs[job].sc.nodes;
+            L.tris = a.jobs[job].sc.tris;
+            L.n_tris = a.jobs[job].sc.n_tris;
+            L.flags = a.jobs[job].sc.flags;
+          }
+          ray_setup(s.r, dx, dy, dz);
+          s.r.ox = ox;
+          s.r.oy = oy;
+          s.r.oz = oz;
+          s.total = 0.0f;
+          s.wraps = 0;
+          visits = 0;
+          tests = 0;
+          ovf = false;
+          seg_begin(s, a.jobs[job].sc);
+          have = true;
+        }
+      }
+    }
+    if (__ballot(have) == 0ull) {
+      if (exhausted) break;
+      continue;
+    }
+    if (have) {
+      bool done = L.n_tris == 0 || trav_step(s, L, lstk, gstk, a.lds_stack, a.gstack_depth, visits, tests, ovf);
+      if (done) {
+        float px = 0.f, py = 0.f;
+        const DevScene& sc = a.jobs[job].sc;
+        const int kind = seg_end(s, sc, ovf, px, py);
+        if (kind < 0) {
+          seg_begin(s, sc);
+        } else {
+          int32_t code;
+          float f0 = s.b1, f1 = s.b2;
+          if (kind == K_HIT) {
+            code = s.idx;
+          } else if (kind == K_ESCAPE) {
+            code = -1;
+          } else if (kind == K_SUBSTRATE) {
+            code = -2;
+            f0 = px;
+            f1 = py;
+          } else {
+            code = -3;
+          }
+          a.hit.code[item] = code;
+          a.hit.f0[item] = f0;
+          a.hit.f1[item] = f1;
+          a.hit.t[item] = s.total;
+          a.hit.visits[item] = visits;
+          a.hit.tests[item] = tests;
+          a.hit.wraps[item] = (uint32_t)s.wraps | (ovf ? 0x80000000u : 0u);
+          if (ovf) atomicOr(a.err, 2u);
+          have = false;
+        }
+      }
+    }
+  }
+}
+
+// Hit records -> caller triangle indices (first-hit entry point).
+__global__ void k_hit_ids(const float4* __restrict__ tris, const int32_t* __restrict__ code, int64_t n,
+                          int32_t* __restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int32_t c = code[i];
+  out[i] = c >= 0 ? (int32_t)__float_as_uint(tris[3 * (size_t)c].w) : c;
+}
+
+// Shading of one generation (section 2.2): for every ray, its hit record
+// decides escape, absorption or emission; emitting hits draw the daughter
+// count, energies and directions and append the daughters to the next queue
+// with one atomic per wave.  Tables sit in LDS; tallies in per-wave LDS
+// blocks tagged with the job they belong to.
+__global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   const int wpb = blockDim.x >> 6;
   const int w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
@@ -434,10 +577,9 @@ __global__ __launch_bounds__(1024) void k_trace(TraceArgs a) {
   uint32_t* s_eh = reinterpret_cast<uint32_t*>(smem + off);
   off += (size_t)wpb * a.n_ebins * 4;
   uint32_t* s_ah = reinterpret_cast<uint32_t*>(smem + off);
-  off += (size_t)wpb * a.n_abins * 4;
-  off = (off + 15) & ~(size_t)15;
-  uint32_t* s_stk = reinterpret_cast<uint32_t*>(smem + off);
 
+  const uint32_t count = a.gen == 0 ? a.n_gen0 : min(*a.count_in, a.qcap);
+  if ((uint32_t)blockIdx.x * blockDim.x >= count) return;  // whole workgroup idle
   for (int i = threadIdx.x; i < nY; i += blockDim.x) s_yld[i] = tb.yld[i];
   for (int i = threadIdx.x; i < tb.ncdf; i += blockDim.x) {
     s_cE[i] = tb.cdfE[i];
@@ -448,18 +590,10 @@ __global__ __launch_bounds__(1024) void k_trace(TraceArgs a) {
   for (int i = threadIdx.x; i < wpb * a.n_abins; i += blockDim.x) s_ah[i] = 0u;
   __syncthreads();
 
-  // the counter can run past the capacity when appends overflow: never read beyond it
-  const uint32_t count = a.gen == 0 ? a.n_gen0 : min(*a.count_in, a.qcap);
   WaveTally wt{s_cnt + w * T_NCOUNT, s_eh + w * a.n_ebins, s_ah + w * a.n_abins};
-  uint32_t* lstk = s_stk + (size_t)w * a.lds_stack * 64 + lane;
-  uint32_t* gstk = a.gstack + ((size_t)(blockIdx.x * wpb + w) * a.gstack_depth) * 64 + lane;
   int tag = -1;
-
-  for (;;) {
-    uint32_t base = 0;
-    if (lane == 0) base = atomicAdd(a.work, 64u);
-    base = __shfl(base, 0, 64);
-    if (base >= count) break;
+  const uint32_t stride = gridDim.x * (uint32_t)blockDim.x;
+  for (uint32_t base = (blockIdx.x * wpb + w) * 64u; base < count; base += stride) {
     const uint32_t item = base + lane;
     const bool active = item < count;
 
@@ -470,24 +604,10 @@ __global__ __launch_bounds__(1024) void k_trace(TraceArgs a) {
       if (a.gen == 0) {
         const uint64_t g = a.chunk_lo + item;
         job = find_job(a.jobs, a.n_jobs, g);
-        const DevJob& J = a.jobs[job];
-        const uint64_t pid = J.pid0 + (g - J.gbase);
-        const U4 u = philox(J.seed, (uint32_t)pid, (uint32_t)(pid >> 32), 0u, 0u);
-        const float th = (J.theta >= 0.0f ? J.theta : -J.theta * u01(u.w)) * (kPi / 180.0f);
-        const float psi = 2.0f * kPi * u01(u.z);
-        ox = J.sc.lo[0] + (J.sc.hi[0] - J.sc.lo[0]) * u01(u.x);
-        oy = J.sc.lo[1] + (J.sc.hi[1] - J.sc.lo[1]) * u01(u.y);
-        oz = J.sc.hi[2];
-        const float st = sinf(th);
-        dx = st * cosf(psi);
-        dy = st * sinf(psi);
-        dz = -cosf(th);
-        E = J.E0;
+        primary_ray(a.jobs[job], g, ox, oy, oz, dx, dy, dz);
+        E = a.jobs[job].E0;
         ci = item;
       } else {
-        ox = a.qin.ox[item];
-        oy = a.qin.oy[item];
-        oz = a.qin.oz[item];
         dx = a.qin.dx[item];
         dy = a.qin.dy[item];
         dz = a.qin.dz[item];
@@ -499,6 +619,9 @@ __global__ __launch_bounds__(1024) void k_trace(TraceArgs a) {
         job = (int)(m >> 4);
       }
     }
+    (void)ox;
+    (void)oy;
+    (void)oz;
     const int j0 = __shfl(job, 0, 64);
     if (j0 != tag) {
       if (tag >= 0) flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, lane);
@@ -511,19 +634,15 @@ __global__ __launch_bounds__(1024) void k_trace(TraceArgs a) {
     int nd = 0;
     float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;
     if (active) {
-      uint32_t visits = 0, tests = 0;
-      bool ovf = false;
-      PathOut po;
-      trace_path(J.sc, ox, oy, oz, dx, dy, dz, lstk, gstk, a.lds_stack, a.gstack_depth, visits, tests, ovf, po);
+      const int32_t code = a.hit.code[item];
+      const float f0 = a.hit.f0[item], f1 = a.hit.f1[item];
+      const uint32_t wr = a.hit.wraps[item];
       tally_cnt(mine, wt, gt, T_RAYS, 1ull);
-      tally_cnt(mine, wt, gt, T_VISITS, visits);
-      tally_cnt(mine, wt, gt, T_TESTS, tests);
-      if (po.wraps) tally_cnt(mine, wt, gt, T_WRAPS, (unsigned long long)po.wraps);
-      if (ovf) {
-        tally_cnt(mine, wt, gt, T_STACKOVF, 1ull);
-        atomicOr(a.err, 2u);
-      }
-      if (po.kind == K_ESCAPE) {
+      tally_cnt(mine, wt, gt, T_VISITS, a.hit.visits[item]);
+      tally_cnt(mine, wt, gt, T_TESTS, a.hit.tests[item]);
+      if (wr & 0x7fffffffu) tally_cnt(mine, wt, gt, T_WRAPS, (unsigned long long)(wr & 0x7fffffffu));
+      if (wr & 0x80000000u) tally_cnt(mine, wt, gt, T_STACKOVF, 1ull);
+      if (code == -1) {
         tally_cnt(mine, wt, gt, T_ESCAPED, 1ull);
         tally_cnt(mine, wt, gt, T_E_ESC_FX, (unsigned long long)to_fx(E));
         int eb = (int)floorf(E / J.E0 * (float)a.n_ebins);
@@ -539,19 +658,19 @@ __global__ __launch_bounds__(1024) void k_trace(TraceArgs a) {
           atomicAdd(&gt[T_NCOUNT + a.n_ebins + ab], 1ull);
         }
         atomicAdd(&a.ppc[ci], 1u);
-      } else if (po.kind == K_LOST) {
+      } else if (code == -3) {
         tally_cnt(mine, wt, gt, T_LOST, 1ull);
         tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E));
       } else {
-        if (po.kind == K_SUBSTRATE) {
+        if (code == -2) {
           tally_cnt(mine, wt, gt, T_SUBSTRATE, 1ull);
-          px = po.px;
-          py = po.py;
-          pz = po.pz;
+          px = f0;
+          py = f1;
+          pz = J.sc.lo[2];
         } else {
-          const float4* T = J.sc.tris + 3 * (size_t)po.h.idx;
+          const float4* T = J.sc.tris + 3 * (size_t)code;
           const float4 v0 = T[0], v1 = T[1], v2 = T[2];
-          const float b1 = po.h.b1, b2 = po.h.b2, b0 = 1.0f - b1 - b2;
+          const float b1 = f0, b2 = f1, b0 = 1.0f - b1 - b2;
           px = b0 * v0.x + b1 * v1.x + b2 * v2.x;
           py = b0 * v0.y + b1 * v1.y + b2 * v2.y;
           pz = b0 * v0.z + b1 * v1.z + b2 * v2.z;
@@ -660,42 +779,6 @@ __global__ __launch_bounds__(1024) void k_trace(TraceArgs a) {
   if (tag >= 0) flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, lane);
 }
 
-// First surface reached by each ray (parity entry point).
-__global__ __launch_bounds__(1024) void k_first_hit(DevScene sc, const float* __restrict__ rays, int64_t n,
-                                                    int32_t* __restrict__ tri_out, float* __restrict__ t_out,
-                                                    uint32_t* gstack, int sd, int gd) {
-  const int wpb = blockDim.x >> 6;
-  const int w = threadIdx.x >> 6;
-  const uint32_t lane = lane_id();
-  uint32_t* s_stk = reinterpret_cast<uint32_t*>(smem);
-  uint32_t* lstk = s_stk + (size_t)w * sd * 64 + lane;
-  uint32_t* gstk = gstack + ((size_t)(blockIdx.x * wpb + w) * gd) * 64 + lane;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  // every lane of a wave runs the same number of iterations
-  const int64_t start = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t iters = (n + stride - 1) / stride;
-  for (int64_t it = 0; it < iters; ++it) {
-    const int64_t i = start + it * stride;
-    if (i >= n) continue;
-    const float* r = rays + 6 * i;
-    uint32_t visits = 0, tests = 0;
-    bool ovf = false;
-    PathOut po;
-    trace_path(sc, r[0], r[1], r[2], r[3], r[4], r[5], lstk, gstk, sd, gd, visits, tests, ovf, po);
-    int32_t id;
-    if (po.kind == K_HIT)
-      id = po.h.oid;
-    else if (po.kind == K_ESCAPE)
-      id = -1;
-    else if (po.kind == K_SUBSTRATE)
-      id = -2;
-    else
-      id = -3;
-    tri_out[i] = id;
-    t_out[i] = po.t_total;
-  }
-}
-
 __global__ void k_chunk_reduce(const DevJob* jobs, int32_t n_jobs, const uint32_t* __restrict__ ppc, uint32_t n,
                                uint64_t chunk_lo) {
   const uint32_t lane = lane_id();
@@ -761,27 +844,35 @@ __global__ __launch_bounds__(256) void k_copy_probe(float4* __restrict__ dst4, c
 
 }  // namespace
 
-size_t trace_lds_bytes(const TraceArgs& a, int block) {
+size_t traverse_lds_bytes(int lds_stack, int block) { return (size_t)(block / 64) * lds_stack * 64 * 4; }
+
+size_t shade_lds_bytes(const DevTables& tb, int n_ebins, int n_abins, int block) {
   const int wpb = block / 64;
-  size_t off = ((size_t)(a.tb.nE * a.tb.nth + 2 * a.tb.ncdf) * 4 + 15) & ~(size_t)15;
+  size_t off = ((size_t)(tb.nE * tb.nth + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
   off += (size_t)wpb * T_NCOUNT * 8;
-  off += (size_t)wpb * a.n_ebins * 4;
-  off += (size_t)wpb * a.n_abins * 4;
-  off = (off + 15) & ~(size_t)15;
-  off += (size_t)wpb * a.lds_stack * 64 * 4;
+  off += (size_t)wpb * n_ebins * 4;
+  off += (size_t)wpb * n_abins * 4;
   return off;
 }
 
-hipError_t launch_trace(const TraceArgs& a, int grid, int block, hipStream_t s) {
-  const size_t lds = trace_lds_bytes(a, block);
-  k_trace<<<grid, block, lds, s>>>(a);
+hipError_t launch_traverse(const TraverseArgs& a, bool multi, int grid, int block, hipStream_t s) {
+  const size_t lds = traverse_lds_bytes(a.lds_stack, block);
+  if (multi)
+    k_traverse<true><<<grid, block, lds, s>>>(a);
+  else
+    k_traverse<false><<<grid, block, lds, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_first_hit(DevScene sc, const float* rays, int64_t n, int32_t* tri_out, float* t_out,
-                            uint32_t* gstack, int lds_stack, int gstack_depth, int grid, int block, hipStream_t s) {
-  const size_t lds = (size_t)(block / 64) * lds_stack * 64 * 4;
-  k_first_hit<<<grid, block, lds, s>>>(sc, rays, n, tri_out, t_out, gstack, lds_stack, gstack_depth);
+hipError_t launch_shade(const ShadeArgs& a, int grid, int block, hipStream_t s) {
+  const size_t lds = shade_lds_bytes(a.tb, a.n_ebins, a.n_abins, block);
+  k_shade<<<grid, block, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_hit_ids(const float4* tris, const int32_t* code, int64_t n, int32_t* out, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  k_hit_ids<<<(int)((n + 255) / 256), 256, 0, s>>>(tris, code, n, out);
   return hipGetLastError();
 }
 
