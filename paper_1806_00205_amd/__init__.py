@@ -9,8 +9,10 @@ missing or was built for another GPU.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -70,7 +72,7 @@ class Result(C.Structure):
 
 class LaunchCfg(C.Structure):
     _fields_ = [("block", C.c_int32), ("wg_per_cu", C.c_int32), ("lds_stack", C.c_int32), ("chunk", C.c_int32),
-                ("refill", C.c_int32)]
+                ("refill", C.c_int32), ("occupancy", C.c_int32)]
 
 
 class SceneInfo(C.Structure):
@@ -85,6 +87,14 @@ class Job(C.Structure):
 
 
 _lib = None
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # release device memory while torch's allocator is still alive
+    for ctx in list(_live):
+        ctx.close()
 
 
 def load_library(path: str = LIB_PATH):
@@ -152,7 +162,8 @@ class Context:
                     return None
 
             def _f(p, user):
-                torch.cuda.caching_allocator_delete(p)
+                if torch is not None and torch.cuda is not None:
+                    torch.cuda.caching_allocator_delete(p)
 
             self._alloc = Allocator(Allocator._fields_[0][1](_a), Allocator._fields_[1][1](_f), None)
         h = C.c_void_p()
@@ -161,7 +172,7 @@ class Context:
         if st != 0:
             raise RtmcError(st, "rtmc_create failed")
         self.h = h
-        self._keep = []
+        _live.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -267,8 +278,9 @@ class Context:
         self._chk(self.lib.rtmc_sort_pairs_u64(self.h, C.c_void_p(keys.data_ptr()), C.c_void_p(vals.data_ptr()),
                                                keys.numel(), int(key_bits)))
 
-    def set_launch(self, block: int, wg_per_cu: int, lds_stack: int, chunk: int, refill: int = 16):
-        self._chk(self.lib.rtmc_set_launch(self.h, C.byref(LaunchCfg(block, wg_per_cu, lds_stack, chunk, refill))))
+    def set_launch(self, block: int, wg_per_cu: int, lds_stack: int, chunk: int, refill: int = 16, occupancy: int = 0):
+        self._chk(self.lib.rtmc_set_launch(self.h, C.byref(LaunchCfg(block, wg_per_cu, lds_stack, chunk, refill,
+                                                                     occupancy))))
 
     def get_launch(self) -> dict:
         c = LaunchCfg()

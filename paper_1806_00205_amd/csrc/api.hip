@@ -56,7 +56,7 @@ struct rtmc_ctx {
   size_t lds_per_block = 0;
   std::vector<Scene> scenes;
   std::vector<Tables> tables;
-  rtmc_launch_cfg cfg{256, 8, 16, 1 << 21, 16};
+  rtmc_launch_cfg cfg{256, 6, 16, 1 << 24, 48, 0};
   // trace work buffers, grown on demand
   DevBuf queue[2];
   DevBuf hits;  // hit records, qcap entries
@@ -257,13 +257,14 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
     const uint32_t n_here = (uint32_t)std::min<uint64_t>(chunk, total - lo);
     uint32_t* cnt = reinterpret_cast<uint32_t*>(c->counters.p) + ch * ncnt;
     HIPCHK(c, launch_fill_u32(sa.ppc, 0u, n_here, s));
+    HIPCHK(c, launch_primaries(ta.jobs, ta.n_jobs, lo, n_here, q[0], s));
     ta.chunk_lo = sa.chunk_lo = lo;
     sa.n_gen0 = n_here;
     for (int g = 0; g <= max_gen; ++g) {
-      ta.src = g == 0 ? 0 : 1;
+      ta.src = 1;
       ta.count = n_here;
       ta.qin = q[g & 1];
-      ta.count_in = cnt + g;  // produced by generation g - 1
+      ta.count_in = g == 0 ? nullptr : cnt + g;  // produced by generation g - 1
       ta.work = cnt + (kMaxGen + 2) + g;
       sa.gen = g;
       sa.qin = q[g & 1];
@@ -275,13 +276,13 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
         hipEvent_t e0 = ev(k), e1 = ev(k + 1), e2 = ev(k + 2), e3 = ev(k + 3);
         if (!e0 || !e1 || !e2 || !e3) return fail(c, RTMC_EDEVICE, "event creation failed");
         HIPCHK(c, hipEventRecord(e0, s));
-        HIPCHK(c, launch_traverse(ta, multi, grid, block, s));
+        HIPCHK(c, launch_traverse(ta, multi, cfg.occupancy, grid, block, s));
         HIPCHK(c, hipEventRecord(e1, s));
         HIPCHK(c, hipEventRecord(e2, s));
         HIPCHK(c, launch_shade(sa, sgrid, kShadeBlock, s));
         HIPCHK(c, hipEventRecord(e3, s));
       } else {
-        HIPCHK(c, launch_traverse(ta, multi, grid, block, s));
+        HIPCHK(c, launch_traverse(ta, multi, cfg.occupancy, grid, block, s));
         HIPCHK(c, launch_shade(sa, sgrid, kShadeBlock, s));
       }
       ++*n_launch;
@@ -863,7 +864,7 @@ rtmc_status rtmc_first_hit(rtmc_ctx* c, int32_t scene_id, const float* rays, int
   ta.gstack_depth = gdepth;
   ta.refill = c->cfg.refill;
   if (e == hipSuccess) e = launch_fill_u32(ta.work, 0u, 2, c->stream);
-  if (e == hipSuccess) e = launch_traverse(ta, false, grid, block, c->stream);
+  if (e == hipSuccess) e = launch_traverse(ta, false, c->cfg.occupancy, grid, block, c->stream);
   if (e == hipSuccess)
     e = launch_hit_ids(reinterpret_cast<const float4*>(s.tris.p), tri_out, n, tri_out, c->stream);
   // the scratch is released only after the launches that use it have finished
@@ -946,10 +947,11 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
   const int blocks[] = {64, 128, 256};
   const int wgs[] = {2, 4, 6, 8, 12, 16};
   const int stacks[] = {8, 12, 16, 24, 32};
-  const int refills[] = {1, 8, 16, 32, 48, 64};
+  const int refills[] = {24, 32, 40, 48, 56, 64};
+  const int occs[] = {0, 8};
   for (int pass = 0; pass < 2; ++pass) {
-    for (int knob = 0; knob < 4; ++knob) {
-      const int n = knob == 0 ? 3 : (knob == 1 ? 6 : (knob == 2 ? 5 : 6));
+    for (int knob = 0; knob < 5; ++knob) {
+      const int n = knob == 0 ? 3 : (knob == 1 ? 6 : (knob == 2 ? 5 : (knob == 3 ? 6 : 2)));
       for (int i = 0; i < n; ++i) {
         rtmc_launch_cfg cf = cur;
         if (knob == 0) {
@@ -959,6 +961,7 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
         if (knob == 1) cf.wg_per_cu = wgs[i] * 256 / cf.block;
         if (knob == 2) cf.lds_stack = stacks[i];
         if (knob == 3) cf.refill = refills[i];
+        if (knob == 4) cf.occupancy = occs[i];
         if (cf.wg_per_cu < 1 || cf.wg_per_cu > 64) continue;
         double ms;
         st = time_cfg(cf, &ms);

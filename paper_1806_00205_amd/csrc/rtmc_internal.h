@@ -101,11 +101,11 @@ struct HitRecs {
 struct TraverseArgs {
   const DevJob* jobs;
   int32_t n_jobs;
-  int32_t src;               // 0: primaries of the chunk, 1: queue, 2: explicit rays
+  int32_t src;               // 1: queue, 2: explicit rays
   RayQueue qin;
   const float* rays;         // src 2: [n][6]
-  uint32_t count;            // src 0 and 2
-  const uint32_t* count_in;  // src 1
+  uint32_t count;            // ray count when count_in is null
+  const uint32_t* count_in;  // queue length in device memory, or null
   uint32_t qcap;
   uint64_t chunk_lo;
   HitRecs hit;
@@ -137,8 +137,10 @@ struct ShadeArgs {
 // host-side launchers (defined in the .hip files)
 size_t traverse_lds_bytes(int lds_stack, int block);
 size_t shade_lds_bytes(const DevTables& tb, int n_ebins, int n_abins, int block);
-hipError_t launch_traverse(const TraverseArgs& a, bool multi, int grid, int block, hipStream_t s);
+hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int grid, int block, hipStream_t s);
 hipError_t launch_shade(const ShadeArgs& a, int grid, int block, hipStream_t s);
+hipError_t launch_primaries(const DevJob* jobs, int32_t n_jobs, uint64_t chunk_lo, uint32_t n, const RayQueue& q,
+                            hipStream_t s);
 hipError_t launch_hit_ids(const float4* tris, const int32_t* code, int64_t n, int32_t* out, hipStream_t s);
 hipError_t launch_chunk_reduce(const DevJob* jobs, int32_t n_jobs, const uint32_t* ppc, uint32_t n,
                                uint64_t chunk_lo, hipStream_t s);

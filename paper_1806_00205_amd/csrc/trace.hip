@@ -24,9 +24,27 @@
 namespace rtmc {
 namespace {
 
+// Explicit address spaces: pointers that arrive through the job table or the
+// argument struct are otherwise generic, and generic (flat) accesses wait on
+// both the vector-memory and the LDS counters.
+#define GAS __attribute__((address_space(1)))
+#define LAS __attribute__((address_space(3)))
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+template <typename T>
+__device__ inline GAS T* gp(T* p) {
+  return (GAS T*)p;
+}
+template <typename T>
+__device__ inline const GAS T* gp(const T* p) {
+  return (const GAS T*)p;
+}
+
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kDeg = 57.295779513082320876f;  // 180 / pi
-constexpr float kRobust = 1.0000004f;  // >= 1 + 2 gamma(3): conservative far slab distance
+// Conservative far-slab factor: 1 + 2 gamma(3) for the subtraction and the
+// product, widened for the 1-ulp hardware reciprocal of the direction.
+constexpr float kRobust = 1.0000008f;
 
 __device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
@@ -72,7 +90,11 @@ struct RayP {
 
 __device__ inline float pick(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
 
-__device__ inline float safe_inv(float d) { return 1.0f / (fabsf(d) > 1e-20f ? d : copysignf(1e-20f, d)); }
+// Hardware reciprocal (1 ulp); tiny components are replaced so that slab
+// distances stay finite and keep their sign.
+__device__ inline float safe_inv(float d) {
+  return __builtin_amdgcn_rcpf(fabsf(d) > 1e-20f ? d : copysignf(1e-20f, d));
+}
 
 __device__ inline void ray_setup(RayP& r, float dx, float dy, float dz) {
   r.dx = dx;
@@ -94,9 +116,10 @@ __device__ inline void ray_setup(RayP& r, float dx, float dy, float dz) {
   r.kx = kx;
   r.ky = ky;
   r.kz = kz;
-  r.Sx = pick(dx, dy, dz, kx) / dkz;
-  r.Sy = pick(dx, dy, dz, ky) / dkz;
-  r.Sz = 1.0f / dkz;
+  // any per-ray shear is watertight as long as every triangle sees the same one
+  r.Sz = __builtin_amdgcn_rcpf(dkz);
+  r.Sx = pick(dx, dy, dz, kx) * r.Sz;
+  r.Sy = pick(dx, dy, dz, ky) * r.Sz;
 }
 
 __device__ inline bool box_test(const RayP& r, float lx, float ly, float lz, float hx, float hy, float hz, float tmax,
@@ -114,7 +137,7 @@ __device__ inline bool box_test(const RayP& r, float lx, float ly, float lz, flo
 // sheared edge functions (weights of V0, V1, V2); products are kept
 // unfused so that an edge shared by two triangles gets exactly opposite
 // values, and an exactly zero edge function is recomputed in FP64.
-__device__ inline bool tri_test(const RayP& r, float4 a, float4 b, float4 c, float tbest, float& t, float& b1,
+__device__ inline bool tri_test(const RayP& r, f4v a, f4v b, f4v c, float tbest, float& t, float& b1,
                                 float& b2) {
   const float ax = a.x - r.ox, ay = a.y - r.oy, az = a.z - r.oz;
   const float bx = b.x - r.ox, by = b.y - r.oy, bz = b.z - r.oz;
@@ -145,7 +168,7 @@ __device__ inline bool tri_test(const RayP& r, float4 a, float4 b, float4 c, flo
 
 // ---------------------------------------------------------------- tables (LDS)
 
-__device__ inline float table_yield(const float* yld, const DevTables& tb, float E, float alpha) {
+__device__ inline float table_yield(const LAS float* yld, const DevTables& tb, float E, float alpha) {
   float x = (logf(E) - tb.logEmin) * tb.invdlogE;
   x = fminf(fmaxf(x, 0.0f), (float)(tb.nE - 1));
   int i = min((int)floorf(x), tb.nE - 2);
@@ -153,14 +176,14 @@ __device__ inline float table_yield(const float* yld, const DevTables& tb, float
   float y = fminf(fmaxf(alpha * tb.thscale, 0.0f), (float)(tb.nth - 1));
   int j = min((int)floorf(y), tb.nth - 2);
   const float fy = y - (float)j;
-  const float* row0 = yld + i * tb.nth + j;
-  const float* row1 = row0 + tb.nth;
+  const LAS float* row0 = yld + i * tb.nth + j;
+  const LAS float* row1 = row0 + tb.nth;
   return (1.0f - fx) * (1.0f - fy) * row0[0] + fx * (1.0f - fy) * row1[0] + (1.0f - fx) * fy * row0[1] +
          fx * fy * row1[1];
 }
 
 // piecewise-linear CDF at E
-__device__ inline float cdf_at(const float* cE, const float* cF, int n, float E) {
+__device__ inline float cdf_at(const LAS float* cE, const LAS float* cF, int n, float E) {
   if (E <= cE[0]) return cF[0];
   if (E >= cE[n - 1]) return cF[n - 1];
   int lo = 0, hi = n - 1;  // cE[lo] <= E < cE[hi]
@@ -175,7 +198,7 @@ __device__ inline float cdf_at(const float* cE, const float* cF, int n, float E)
 }
 
 // energy where the piecewise-linear CDF first reaches c
-__device__ inline float cdf_inv(const float* cE, const float* cF, int n, float c) {
+__device__ inline float cdf_inv(const LAS float* cE, const LAS float* cF, int n, float c) {
   int lo = 0, hi = n - 1;  // smallest m >= 1 with cF[m] >= c lies in (lo, hi]
   if (!(cF[hi] >= c)) return cE[n - 1];
   while (hi - lo > 1) {
@@ -204,7 +227,7 @@ __device__ inline int find_job(const DevJob* jobs, int n, uint64_t g) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].gbase <= g)
+    if (gp(jobs)[mid].gbase <= g)
       lo = mid;
     else
       hi = mid - 1;
@@ -216,35 +239,69 @@ __device__ inline long long to_fx(float E) { return (long long)llrintf(E * 10485
 
 // ---------------------------------------------------------------- tallies
 
+// Per-wave tallies.  Event counters and sums live in per-lane registers and
+// are reduced across the wave only when the wave flushes; the two histograms
+// are per-wave LDS blocks (their bins are spread, so LDS atomics rarely
+// collide).
 struct WaveTally {
-  unsigned long long* cnt;  // LDS [T_NCOUNT]
-  uint32_t* eh;             // LDS [n_ebins]
-  uint32_t* ah;             // LDS [n_abins]
+  uint32_t c[T_NCOUNT];  // counter slots except the two energy sums
+  unsigned long long e_esc, e_dep;
+  LAS uint32_t* eh;  // LDS [n_ebins]
+  LAS uint32_t* ah;  // LDS [n_abins]
 };
 
-__device__ inline void tally_cnt(bool mine, const WaveTally& wt, unsigned long long* g, int slot,
-                                 unsigned long long v) {
-  if (mine)
-    atomicAdd(&wt.cnt[slot], v);
-  else
-    atomicAdd(&g[slot], v);
+__device__ inline void gadd(unsigned long long* g, unsigned long long v) {
+  __hip_atomic_fetch_add(gp(g), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline void flush_wave(const WaveTally& wt, unsigned long long* g, int n_eb, int n_ab, uint32_t lane) {
-  wave_sync();
-  for (int i = lane; i < T_NCOUNT; i += 64) {
-    const unsigned long long v = wt.cnt[i];
-    if (v) atomicAdd(&g[i], v);
-    wt.cnt[i] = 0ull;
+template <typename T>
+__device__ inline void ladd(LAS T* p, T v) {
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+}
+
+// slot is a compile-time constant at every call site
+__device__ inline void tally_cnt(bool mine, WaveTally& wt, unsigned long long* g, int slot, unsigned long long v) {
+  if (!mine) {
+    gadd(g + slot, v);
+  } else if (slot == T_E_ESC_FX) {
+    wt.e_esc += v;
+  } else if (slot == T_E_DEP_FX) {
+    wt.e_dep += v;
+  } else {
+    wt.c[slot] += (uint32_t)v;
   }
+}
+
+__device__ inline unsigned long long wave_sum(unsigned long long v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__device__ inline void flush_wave(WaveTally& wt, unsigned long long* g, int n_eb, int n_ab, uint32_t lane) {
+#pragma unroll
+  for (int k = 0; k < T_NCOUNT; ++k) {
+    if (k == T_E_ESC_FX || k == T_E_DEP_FX || k == T_C2 || k == T_SPARE) continue;
+    const unsigned long long v = wave_sum((unsigned long long)wt.c[k]);
+    if (lane == 0 && v) gadd(g + k, v);
+    wt.c[k] = 0u;
+  }
+  const unsigned long long ee = wave_sum(wt.e_esc), ed = wave_sum(wt.e_dep);
+  if (lane == 0) {
+    if (ee) gadd(g + T_E_ESC_FX, ee);
+    if (ed) gadd(g + T_E_DEP_FX, ed);
+  }
+  wt.e_esc = 0ull;
+  wt.e_dep = 0ull;
+  wave_sync();
   for (int i = lane; i < n_eb; i += 64) {
     const uint32_t v = wt.eh[i];
-    if (v) atomicAdd(&g[T_NCOUNT + i], (unsigned long long)v);
+    if (v) gadd(g + T_NCOUNT + i, (unsigned long long)v);
     wt.eh[i] = 0u;
   }
   for (int i = lane; i < n_ab; i += 64) {
     const uint32_t v = wt.ah[i];
-    if (v) atomicAdd(&g[T_NCOUNT + n_eb + i], (unsigned long long)v);
+    if (v) gadd(g + T_NCOUNT + n_eb + i, (unsigned long long)v);
     wt.ah[i] = 0u;
   }
   wave_sync();
@@ -280,20 +337,25 @@ struct Trav {
   int32_t oid;    // caller's triangle index of the hit
   uint32_t node;
   int sp;
-  float te0, te1, te2;  // distances to the x, y, z faces of the cell
-  float total;          // path length of earlier segments
+  float total;  // path length of earlier segments
   int wraps;
 };
 
+// Distances from the segment origin to the x, y, z faces of the cell, with
+// the ray's reciprocal direction (recomputed where needed, not kept live).
+__device__ inline void exit_dists(const RayP& r, const DevScene& sc, float& te0, float& te1, float& te2) {
+  const float tex = r.dx > 0.0f ? (sc.hi[0] - r.ox) * r.ix : (r.dx < 0.0f ? (sc.lo[0] - r.ox) * r.ix : INFINITY);
+  const float tey = r.dy > 0.0f ? (sc.hi[1] - r.oy) * r.iy : (r.dy < 0.0f ? (sc.lo[1] - r.oy) * r.iy : INFINITY);
+  const float tez = r.dz > 0.0f ? (sc.hi[2] - r.oz) * r.iz : (r.dz < 0.0f ? (sc.lo[2] - r.oz) * r.iz : INFINITY);
+  te0 = fmaxf(tex, 0.0f);
+  te1 = fmaxf(tey, 0.0f);
+  te2 = fmaxf(tez, 0.0f);
+}
+
 __device__ inline void seg_begin(Trav& s, const DevScene& sc) {
-  const RayP& r = s.r;
-  const float tex = r.dx > 0.0f ? (sc.hi[0] - r.ox) / r.dx : (r.dx < 0.0f ? (sc.lo[0] - r.ox) / r.dx : INFINITY);
-  const float tey = r.dy > 0.0f ? (sc.hi[1] - r.oy) / r.dy : (r.dy < 0.0f ? (sc.lo[1] - r.oy) / r.dy : INFINITY);
-  const float tez = r.dz > 0.0f ? (sc.hi[2] - r.oz) / r.dz : (r.dz < 0.0f ? (sc.lo[2] - r.oz) / r.dz : INFINITY);
-  s.te0 = fmaxf(tex, 0.0f);
-  s.te1 = fmaxf(tey, 0.0f);
-  s.te2 = fmaxf(tez, 0.0f);
-  s.t = fminf(fminf(s.te0, s.te1), s.te2);
+  float te0, te1, te2;
+  exit_dists(s.r, sc, te0, te1, te2);
+  s.t = fminf(fminf(te0, te1), te2);
   s.idx = -1;
   s.oid = 0x7fffffff;
   s.node = 0;
@@ -303,10 +365,10 @@ __device__ inline void seg_begin(Trav& s, const DevScene& sc) {
 // One node of the traversal.  Returns true when the segment's traversal has
 // finished (stack empty).  The stack keeps its first sd entries in LDS (lstk,
 // stride 64 words) and the rest in global memory (gstk, stride 64 words).
-__device__ inline bool trav_step(Trav& s, const LaneScene& L, uint32_t* lstk, uint32_t* gstk, int sd, int gd,
-                                 uint32_t& visits, uint32_t& tests, bool& ovf) {
-  const float4* N = L.nodes + 4 * (size_t)s.node;
-  const float4 n0 = N[0], n1 = N[1], n2 = N[2], n3 = N[3];
+__device__ inline bool trav_step(Trav& s, const LaneScene& L, LAS uint32_t* lstk, GAS uint32_t* gstk, int sd,
+                                 int gd, uint32_t& visits, uint32_t& tests, bool& ovf) {
+  const GAS f4v* N = (const GAS f4v*)L.nodes + 4 * (size_t)s.node;
+  const f4v n0 = N[0], n1 = N[1], n2 = N[2], n3 = N[3];
   ++visits;
   float tl, tr;
   bool hl = box_test(s.r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, s.t, tl);
@@ -317,8 +379,8 @@ __device__ inline bool trav_step(Trav& s, const LaneScene& L, uint32_t* lstk, ui
     const bool leafhit = side == 0 ? (hl && (cl & kLeafBit)) : (hr && (cr & kLeafBit));
     if (leafhit) {
       const uint32_t k = (side == 0 ? cl : cr) & ~kLeafBit;
-      const float4* T = L.tris + 3 * (size_t)k;
-      const float4 a = T[0], b = T[1], c = T[2];
+      const GAS f4v* T = (const GAS f4v*)L.tris + 3 * (size_t)k;
+      const f4v a = T[0], b = T[1], c = T[2];
       ++tests;
       float t, b1, b2;
       if (tri_test(s.r, a, b, c, s.t, t, b1, b2)) {
@@ -377,12 +439,14 @@ __device__ inline int seg_end(Trav& s, const DevScene& sc, bool ovf, float& px, 
     return K_HIT;
   }
   const RayP& r = s.r;
-  if (s.te2 <= s.te0 && s.te2 <= s.te1) {
-    s.total += s.te2;
+  float te0, te1, te2;
+  exit_dists(r, sc, te0, te1, te2);
+  if (te2 <= te0 && te2 <= te1) {
+    s.total += te2;
     if (r.dz > 0.0f) return K_ESCAPE;
     if (sc.flags & 2u) {
-      px = r.ox + s.te2 * r.dx;
-      py = r.oy + s.te2 * r.dy;
+      px = r.ox + te2 * r.dx;
+      py = r.oy + te2 * r.dy;
       return K_SUBSTRATE;
     }
     return K_LOST;
@@ -394,11 +458,11 @@ __device__ inline int seg_end(Trav& s, const DevScene& sc, bool ovf, float& px, 
   }
   s.total += texit;
   float qx = r.ox + texit * r.dx, qy = r.oy + texit * r.dy, qz = r.oz + texit * r.dz;
-  if (s.te0 == texit)
+  if (te0 == texit)
     qx = r.dx > 0.0f ? sc.lo[0] : sc.hi[0];
   else
     qx = fminf(fmaxf(qx, sc.lo[0]), sc.hi[0]);
-  if (s.te1 == texit)
+  if (te1 == texit)
     qy = r.dy > 0.0f ? sc.lo[1] : sc.hi[1];
   else
     qy = fminf(fmaxf(qy, sc.lo[1]), sc.hi[1]);
@@ -429,24 +493,29 @@ __device__ inline void primary_ray(const DevJob& J, uint64_t g, float& ox, float
 
 extern __shared__ __align__(16) unsigned char smem[];
 
-// Closest-hit traversal of one generation of rays.  Lanes that finish pick
-// up new rays (one atomic per refill of the wave) so that a wave is not held
-// by its slowest ray.  MULTI: rays may belong to different jobs.
+// Closest-hit traversal of one generation of rays.  A lane is idle, busy
+// (traversing a segment) or finished (its segment's traversal is over).  The
+// common iteration is one node step of the busy lanes; finished lanes are
+// serviced together -- segment end, periodic re-entry, hit record -- and idle
+// lanes fetch new rays with one atomic per wave, once at least `refill` lanes
+// are not busy.  So a wave is neither held by its slowest ray nor made to run
+// the rare paths on every iteration.  MULTI: rays may belong to different jobs.
 template <bool MULTI>
-__global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
+__device__ inline void traverse_body(const TraverseArgs& a) {
   const int wpb = blockDim.x >> 6;
   const int w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
   const uint64_t lt = (1ull << lane) - 1ull;
-  uint32_t* lstk = reinterpret_cast<uint32_t*>(smem) + (size_t)w * a.lds_stack * 64 + lane;
-  uint32_t* gstk = a.gstack + ((size_t)(blockIdx.x * wpb + w) * a.gstack_depth) * 64 + lane;
-  const uint32_t count = a.src == 1 ? min(*a.count_in, a.qcap) : a.count;
+  LAS uint32_t* lstk = (LAS uint32_t*)smem + (size_t)w * a.lds_stack * 64 + lane;
+  GAS uint32_t* gstk = gp(a.gstack) + ((size_t)(blockIdx.x * wpb + w) * a.gstack_depth) * 64 + lane;
+  const uint32_t count = (a.src == 1 && a.count_in) ? min(*gp(a.count_in), a.qcap) : a.count;
 
   Trav s;
   LaneScene L;
   int job = 0;
   uint32_t item = 0, visits = 0, tests = 0;
-  bool have = false, ovf = false;
+  int st = 0;  // 0 idle, 1 busy, 2 finished
+  bool ovf = false;
   bool exhausted = false;
   if (!MULTI) {
     L.nodes = a.jobs[0].sc.nodes;
@@ -455,70 +524,15 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
     L.flags = a.jobs[0].sc.flags;
   }
   for (;;) {
-    const uint64_t idle = __ballot(!have);
-    const uint32_t nidle = (uint32_t)__popcll(idle);
-    if (!exhausted && nidle >= (uint32_t)a.refill) {
-      uint32_t base = 0;
-      if (lane == 0) base = atomicAdd(a.work, nidle);
-      base = __shfl(base, 0, 64);
-      if (base + nidle >= count) exhausted = true;
-      if (!have) {
-        item = base + (uint32_t)__popcll(idle & lt);
-        if (item < count) {
-          float ox, oy, oz, dx, dy, dz;
-          if (a.src == 0) {
-            const uint64_t g = a.chunk_lo + item;
-            job = MULTI ? find_job(a.jobs, a.n_jobs, g) : 0;
-            primary_ray(a.jobs[job], g, ox, oy, oz, dx, dy, dz);
-          } else if (a.src == 1) {
-            ox = a.qin.ox[item];
-            oy = a.qin.oy[item];
-            oz = a.qin.oz[item];
-            dx = a.qin.dx[item];
-            dy = a.qin.dy[item];
-            dz = a.qin.dz[item];
-            if (MULTI) job = (int)(a.qin.meta[item] >> 4);
-          } else {
-            const float* q = a.rays + 6 * (size_t)item;
-            ox = q[0];
-            oy = q[1];
-            oz = q[2];
-            dx = q[3];
-            dy = q[4];
-            dz = q[5];
-          }
-          if (MULTI) {
-            L.nodes = a.jobs[job].sc.nodes;
-            L.tris = a.jobs[job].sc.tris;
-            L.n_tris = a.jobs[job].sc.n_tris;
-            L.flags = a.jobs[job].sc.flags;
-          }
-          ray_setup(s.r, dx, dy, dz);
-          s.r.ox = ox;
-          s.r.oy = oy;
-          s.r.oz = oz;
-          s.total = 0.0f;
-          s.wraps = 0;
-          visits = 0;
-          tests = 0;
-          ovf = false;
-          seg_begin(s, a.jobs[job].sc);
-          have = true;
-        }
-      }
-    }
-    if (__ballot(have) == 0ull) {
-      if (exhausted) break;
-      continue;
-    }
-    if (have) {
-      bool done = L.n_tris == 0 || trav_step(s, L, lstk, gstk, a.lds_stack, a.gstack_depth, visits, tests, ovf);
-      if (done) {
+    const uint64_t busy = __ballot(st == 1);
+    if (64u - (uint32_t)__popcll(busy) >= (uint32_t)a.refill || busy == 0ull) {
+      if (st == 2) {
         float px = 0.f, py = 0.f;
         const DevScene& sc = a.jobs[job].sc;
         const int kind = seg_end(s, sc, ovf, px, py);
         if (kind < 0) {
           seg_begin(s, sc);
+          st = 1;
         } else {
           int32_t code;
           float f0 = s.b1, f1 = s.b2;
@@ -533,18 +547,106 @@ __global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
           } else {
             code = -3;
           }
-          a.hit.code[item] = code;
-          a.hit.f0[item] = f0;
-          a.hit.f1[item] = f1;
-          a.hit.t[item] = s.total;
-          a.hit.visits[item] = visits;
-          a.hit.tests[item] = tests;
-          a.hit.wraps[item] = (uint32_t)s.wraps | (ovf ? 0x80000000u : 0u);
+          gp(a.hit.code)[item] = code;
+          gp(a.hit.f0)[item] = f0;
+          gp(a.hit.f1)[item] = f1;
+          gp(a.hit.t)[item] = s.total;
+          gp(a.hit.visits)[item] = visits;
+          gp(a.hit.tests)[item] = tests;
+          gp(a.hit.wraps)[item] = (uint32_t)s.wraps | (ovf ? 0x80000000u : 0u);
           if (ovf) atomicOr(a.err, 2u);
-          have = false;
+          st = 0;
         }
       }
+      const uint64_t idle = __ballot(st == 0);
+      if (!exhausted && idle) {
+        const uint32_t nidle = (uint32_t)__popcll(idle);
+        uint32_t base = 0;
+        if (lane == 0) base = __hip_atomic_fetch_add(gp(a.work), nidle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        base = __shfl(base, 0, 64);
+        if (base + nidle >= count) exhausted = true;
+        if (st == 0) {
+          item = base + (uint32_t)__popcll(idle & lt);
+          if (item < count) {
+            float ox, oy, oz, dx, dy, dz;
+            if (a.src == 1) {
+              ox = gp(a.qin.ox)[item];
+              oy = gp(a.qin.oy)[item];
+              oz = gp(a.qin.oz)[item];
+              dx = gp(a.qin.dx)[item];
+              dy = gp(a.qin.dy)[item];
+              dz = gp(a.qin.dz)[item];
+              if (MULTI) job = (int)(gp(a.qin.meta)[item] >> 4);
+            } else {
+              const GAS float* q = gp(a.rays) + 6 * (size_t)item;
+              ox = q[0];
+              oy = q[1];
+              oz = q[2];
+              dx = q[3];
+              dy = q[4];
+              dz = q[5];
+            }
+            if (MULTI) {
+              L.nodes = a.jobs[job].sc.nodes;
+              L.tris = a.jobs[job].sc.tris;
+              L.n_tris = a.jobs[job].sc.n_tris;
+              L.flags = a.jobs[job].sc.flags;
+            }
+            ray_setup(s.r, dx, dy, dz);
+            s.r.ox = ox;
+            s.r.oy = oy;
+            s.r.oz = oz;
+            s.total = 0.0f;
+            s.wraps = 0;
+            visits = 0;
+            tests = 0;
+            ovf = false;
+            seg_begin(s, a.jobs[job].sc);
+            st = 1;
+          }
+        }
+      }
+      // after servicing no lane is finished: none busy means the work is done
+      if (__ballot(st == 1) == 0ull) break;
     }
+    if (st == 1) {
+      if (L.n_tris == 0 || trav_step(s, L, lstk, gstk, a.lds_stack, a.gstack_depth, visits, tests, ovf)) st = 2;
+    }
+  }
+}
+
+// Register-limited variants: the default lets the compiler choose (about 6
+// waves per SIMD); O8 caps registers for 8 waves per SIMD at the price of a
+// few spilled, rarely used values.  The autotuner picks by measurement.
+template <bool MULTI>
+__global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
+  traverse_body<MULTI>(a);
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) void k_traverse_o8(TraverseArgs a) {
+  traverse_body<MULTI>(a);
+}
+
+// Primary rays of one chunk, written to the queue so that both launches of
+// generation 0 read them like any other generation.
+__global__ void k_primaries(const DevJob* __restrict__ jobs, int32_t n_jobs, uint64_t chunk_lo, uint32_t n,
+                            RayQueue q) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    const uint64_t g = chunk_lo + i;
+    const int job = find_job(jobs, n_jobs, g);
+    float ox, oy, oz, dx, dy, dz;
+    primary_ray(jobs[job], g, ox, oy, oz, dx, dy, dz);
+    gp(q.ox)[i] = ox;
+    gp(q.oy)[i] = oy;
+    gp(q.oz)[i] = oz;
+    gp(q.dx)[i] = dx;
+    gp(q.dy)[i] = dy;
+    gp(q.dz)[i] = dz;
+    gp(q.E)[i] = jobs[job].E0;
+    gp(q.path)[i] = 0u;
+    gp(q.ci)[i] = i;
+    gp(q.meta)[i] = (uint32_t)job << 4;
   }
 }
 
@@ -568,29 +670,33 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   const uint32_t lane = lane_id();
   const DevTables& tb = a.tb;
   const int nY = tb.nE * tb.nth;
-  float* s_yld = reinterpret_cast<float*>(smem);
-  float* s_cE = s_yld + nY;
-  float* s_cF = s_cE + tb.ncdf;
+  LAS unsigned char* lds = (LAS unsigned char*)smem;
+  LAS float* s_yld = (LAS float*)lds;
+  LAS float* s_cE = s_yld + nY;
+  LAS float* s_cF = s_cE + tb.ncdf;
   size_t off = ((size_t)(nY + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
-  unsigned long long* s_cnt = reinterpret_cast<unsigned long long*>(smem + off);
-  off += (size_t)wpb * T_NCOUNT * 8;
-  uint32_t* s_eh = reinterpret_cast<uint32_t*>(smem + off);
+  LAS uint32_t* s_eh = (LAS uint32_t*)(lds + off);
   off += (size_t)wpb * a.n_ebins * 4;
-  uint32_t* s_ah = reinterpret_cast<uint32_t*>(smem + off);
+  LAS uint32_t* s_ah = (LAS uint32_t*)(lds + off);
 
-  const uint32_t count = a.gen == 0 ? a.n_gen0 : min(*a.count_in, a.qcap);
+  const uint32_t count = a.gen == 0 ? a.n_gen0 : min(*gp(a.count_in), a.qcap);  // queue length
   if ((uint32_t)blockIdx.x * blockDim.x >= count) return;  // whole workgroup idle
-  for (int i = threadIdx.x; i < nY; i += blockDim.x) s_yld[i] = tb.yld[i];
+  for (int i = threadIdx.x; i < nY; i += blockDim.x) s_yld[i] = gp(tb.yld)[i];
   for (int i = threadIdx.x; i < tb.ncdf; i += blockDim.x) {
-    s_cE[i] = tb.cdfE[i];
-    s_cF[i] = tb.cdfF[i];
+    s_cE[i] = gp(tb.cdfE)[i];
+    s_cF[i] = gp(tb.cdfF)[i];
   }
-  for (int i = threadIdx.x; i < wpb * T_NCOUNT; i += blockDim.x) s_cnt[i] = 0ull;
   for (int i = threadIdx.x; i < wpb * a.n_ebins; i += blockDim.x) s_eh[i] = 0u;
   for (int i = threadIdx.x; i < wpb * a.n_abins; i += blockDim.x) s_ah[i] = 0u;
   __syncthreads();
 
-  WaveTally wt{s_cnt + w * T_NCOUNT, s_eh + w * a.n_ebins, s_ah + w * a.n_abins};
+  WaveTally wt;
+#pragma unroll
+  for (int k = 0; k < T_NCOUNT; ++k) wt.c[k] = 0u;
+  wt.e_esc = 0ull;
+  wt.e_dep = 0ull;
+  wt.eh = s_eh + w * a.n_ebins;
+  wt.ah = s_ah + w * a.n_abins;
   int tag = -1;
   const uint32_t stride = gridDim.x * (uint32_t)blockDim.x;
   for (uint32_t base = (blockIdx.x * wpb + w) * 64u; base < count; base += stride) {
@@ -601,20 +707,14 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     uint32_t path = 0, ci = 0;
     int gen = a.gen, job = 0;
     if (active) {
-      if (a.gen == 0) {
-        const uint64_t g = a.chunk_lo + item;
-        job = find_job(a.jobs, a.n_jobs, g);
-        primary_ray(a.jobs[job], g, ox, oy, oz, dx, dy, dz);
-        E = a.jobs[job].E0;
-        ci = item;
-      } else {
-        dx = a.qin.dx[item];
-        dy = a.qin.dy[item];
-        dz = a.qin.dz[item];
-        E = a.qin.E[item];
-        path = a.qin.path[item];
-        ci = a.qin.ci[item];
-        const uint32_t m = a.qin.meta[item];
+      {
+        dx = gp(a.qin.dx)[item];
+        dy = gp(a.qin.dy)[item];
+        dz = gp(a.qin.dz)[item];
+        E = gp(a.qin.E)[item];
+        path = gp(a.qin.path)[item];
+        ci = gp(a.qin.ci)[item];
+        const uint32_t m = gp(a.qin.meta)[item];
         gen = (int)(m & 15u);
         job = (int)(m >> 4);
       }
@@ -634,12 +734,12 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     int nd = 0;
     float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;
     if (active) {
-      const int32_t code = a.hit.code[item];
-      const float f0 = a.hit.f0[item], f1 = a.hit.f1[item];
-      const uint32_t wr = a.hit.wraps[item];
+      const int32_t code = gp(a.hit.code)[item];
+      const float f0 = gp(a.hit.f0)[item], f1 = gp(a.hit.f1)[item];
+      const uint32_t wr = gp(a.hit.wraps)[item];
       tally_cnt(mine, wt, gt, T_RAYS, 1ull);
-      tally_cnt(mine, wt, gt, T_VISITS, a.hit.visits[item]);
-      tally_cnt(mine, wt, gt, T_TESTS, a.hit.tests[item]);
+      tally_cnt(mine, wt, gt, T_VISITS, gp(a.hit.visits)[item]);
+      tally_cnt(mine, wt, gt, T_TESTS, gp(a.hit.tests)[item]);
       if (wr & 0x7fffffffu) tally_cnt(mine, wt, gt, T_WRAPS, (unsigned long long)(wr & 0x7fffffffu));
       if (wr & 0x80000000u) tally_cnt(mine, wt, gt, T_STACKOVF, 1ull);
       if (code == -1) {
@@ -651,13 +751,13 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
         int ab = (int)floorf(pol * (1.0f / 90.0f) * (float)a.n_abins);
         ab = min(max(ab, 0), a.n_abins - 1);
         if (mine) {
-          atomicAdd(&wt.eh[eb], 1u);
-          atomicAdd(&wt.ah[ab], 1u);
+          ladd(wt.eh + eb, 1u);
+          ladd(wt.ah + ab, 1u);
         } else {
-          atomicAdd(&gt[T_NCOUNT + eb], 1ull);
-          atomicAdd(&gt[T_NCOUNT + a.n_ebins + ab], 1ull);
+          gadd(gt + T_NCOUNT + eb, 1ull);
+          gadd(gt + T_NCOUNT + a.n_ebins + ab, 1ull);
         }
-        atomicAdd(&a.ppc[ci], 1u);
+        __hip_atomic_fetch_add(gp(a.ppc) + ci, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else if (code == -3) {
         tally_cnt(mine, wt, gt, T_LOST, 1ull);
         tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E));
@@ -668,8 +768,8 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
           py = f1;
           pz = J.sc.lo[2];
         } else {
-          const float4* T = J.sc.tris + 3 * (size_t)code;
-          const float4 v0 = T[0], v1 = T[1], v2 = T[2];
+          const GAS f4v* T = (const GAS f4v*)J.sc.tris + 3 * (size_t)code;
+          const f4v v0 = T[0], v1 = T[1], v2 = T[2];
           const float b1 = f0, b2 = f1, b0 = 1.0f - b1 - b2;
           px = b0 * v0.x + b1 * v1.x + b2 * v2.x;
           py = b0 * v0.y + b1 * v1.y + b2 * v2.y;
@@ -719,7 +819,7 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     const uint32_t total = __shfl(incl, 63, 64);
     if (total == 0u) continue;
     uint32_t obase = 0;
-    if (lane == 0) obase = atomicAdd(a.count_out, total);
+    if (lane == 0) obase = __hip_atomic_fetch_add(gp(a.count_out), total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     obase = __shfl(obase, 0, 64);
     if (nd > 0) {
       const uint32_t first = obase + incl - (uint32_t)nd;
@@ -754,16 +854,16 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
         qz = fminf(fmaxf(qz, J.sc.lo[2]), J.sc.hi[2]);
         const uint32_t slot = first + (uint32_t)d;
         if (slot < a.qcap) {
-          a.qout.ox[slot] = qx;
-          a.qout.oy[slot] = qy;
-          a.qout.oz[slot] = qz;
-          a.qout.dx[slot] = ddx;
-          a.qout.dy[slot] = ddy;
-          a.qout.dz[slot] = ddz;
-          a.qout.E[slot] = Ed;
-          a.qout.path[slot] = path * 8u + (uint32_t)d + 1u;
-          a.qout.ci[slot] = ci;
-          a.qout.meta[slot] = (uint32_t)(gen + 1) | ((uint32_t)job << 4);
+          gp(a.qout.ox)[slot] = qx;
+          gp(a.qout.oy)[slot] = qy;
+          gp(a.qout.oz)[slot] = qz;
+          gp(a.qout.dx)[slot] = ddx;
+          gp(a.qout.dy)[slot] = ddy;
+          gp(a.qout.dz)[slot] = ddz;
+          gp(a.qout.E)[slot] = Ed;
+          gp(a.qout.path)[slot] = path * 8u + (uint32_t)d + 1u;
+          gp(a.qout.ci)[slot] = ci;
+          gp(a.qout.meta)[slot] = (uint32_t)(gen + 1) | ((uint32_t)job << 4);
         } else {
           ++dropped;
         }
@@ -779,34 +879,33 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   if (tag >= 0) flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, lane);
 }
 
+// Sum over the chunk's primaries of (escape count)^2 for the yield's standard
+// error, and the optional per-primary output.  Each thread accumulates its
+// grid-stride items and the wave reduces once at the end.
 __global__ void k_chunk_reduce(const DevJob* jobs, int32_t n_jobs, const uint32_t* __restrict__ ppc, uint32_t n,
                                uint64_t chunk_lo) {
   const uint32_t lane = lane_id();
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  const uint64_t start = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const uint64_t iters = (n + stride - 1) / stride;
-  for (uint64_t it = 0; it < iters; ++it) {
-    const uint64_t i = start + it * stride;
-    const bool valid = i < n;
-    int job = 0;
-    unsigned long long c2 = 0;
-    if (valid) {
-      const uint64_t g = chunk_lo + i;
-      job = find_job(jobs, n_jobs, g);
-      const uint32_t c = ppc[i];
-      c2 = (unsigned long long)c * c;
-      if (jobs[job].pp_escaped) jobs[job].pp_escaped[g - jobs[job].gbase] = c;
+  const uint32_t stride = gridDim.x * blockDim.x;
+  int job = -1;
+  unsigned long long acc = 0;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const uint64_t g = chunk_lo + i;
+    const int j = n_jobs == 1 ? 0 : find_job(jobs, n_jobs, g);
+    if (j != job) {
+      if (job >= 0 && acc) gadd(&jobs[job].tally[T_C2], acc);
+      job = j;
+      acc = 0;
     }
-    const int j0 = __shfl(job, 0, 64);
-    const bool uniform = __all(!valid || job == j0);
-    if (uniform) {
-      unsigned long long s = c2;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
-      if (lane == 0 && s) atomicAdd(&jobs[j0].tally[T_C2], s);
-    } else if (valid && c2) {
-      atomicAdd(&jobs[job].tally[T_C2], c2);
-    }
+    const uint32_t c = gp(ppc)[i];
+    acc += (unsigned long long)c * c;
+    if (jobs[j].pp_escaped) gp(jobs[j].pp_escaped)[g - jobs[j].gbase] = c;
+  }
+  const int j0 = __shfl(job, 0, 64);
+  if (__all(job == j0)) {
+    const unsigned long long sum = wave_sum(acc);
+    if (lane == 0 && j0 >= 0 && sum) gadd(&jobs[j0].tally[T_C2], sum);
+  } else if (job >= 0 && acc) {
+    gadd(&jobs[job].tally[T_C2], acc);
   }
 }
 
@@ -820,8 +919,6 @@ __global__ void k_fill_u64(unsigned long long* p, unsigned long long v, size_t n
 
 // Streaming copy used to measure achievable HBM bandwidth: four independent
 // 16-byte loads in flight per lane, coalesced across the wave.
-typedef float f4v __attribute__((ext_vector_type(4)));
-
 __global__ __launch_bounds__(256) void k_copy_probe(float4* __restrict__ dst4, const float4* __restrict__ src4,
                                                     size_t n) {
   const f4v* src = reinterpret_cast<const f4v*>(src4);
@@ -849,24 +946,39 @@ size_t traverse_lds_bytes(int lds_stack, int block) { return (size_t)(block / 64
 size_t shade_lds_bytes(const DevTables& tb, int n_ebins, int n_abins, int block) {
   const int wpb = block / 64;
   size_t off = ((size_t)(tb.nE * tb.nth + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
-  off += (size_t)wpb * T_NCOUNT * 8;
   off += (size_t)wpb * n_ebins * 4;
   off += (size_t)wpb * n_abins * 4;
   return off;
 }
 
-hipError_t launch_traverse(const TraverseArgs& a, bool multi, int grid, int block, hipStream_t s) {
+hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int grid, int block, hipStream_t s) {
   const size_t lds = traverse_lds_bytes(a.lds_stack, block);
-  if (multi)
-    k_traverse<true><<<grid, block, lds, s>>>(a);
-  else
-    k_traverse<false><<<grid, block, lds, s>>>(a);
+  if (occupancy >= 8) {
+    if (multi)
+      k_traverse_o8<true><<<grid, block, lds, s>>>(a);
+    else
+      k_traverse_o8<false><<<grid, block, lds, s>>>(a);
+  } else {
+    if (multi)
+      k_traverse<true><<<grid, block, lds, s>>>(a);
+    else
+      k_traverse<false><<<grid, block, lds, s>>>(a);
+  }
   return hipGetLastError();
 }
 
 hipError_t launch_shade(const ShadeArgs& a, int grid, int block, hipStream_t s) {
   const size_t lds = shade_lds_bytes(a.tb, a.n_ebins, a.n_abins, block);
   k_shade<<<grid, block, lds, s>>>(a);
+  return hipGetLastError();
+}
+
+hipError_t launch_primaries(const DevJob* jobs, int32_t n_jobs, uint64_t chunk_lo, uint32_t n, const RayQueue& q,
+                            hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  int grid = (int)((n + 255) / 256);
+  if (grid > 16384) grid = 16384;
+  k_primaries<<<grid, 256, 0, s>>>(jobs, n_jobs, chunk_lo, n, q);
   return hipGetLastError();
 }
 
