@@ -228,6 +228,30 @@ rtmc_status rtmc_autotune(rtmc_ctx* ctx, int32_t scene_id, int32_t table_id, dou
  * mean time per copy (the achievable-bandwidth probe). */
 rtmc_status rtmc_copy_probe(rtmc_ctx* ctx, void* dst, const void* src, size_t bytes, int32_t reps, double* ms);
 
+/* ---- Learned surrogate of the yield (an extension of the method: trained on
+ * yields that rtmc_trace produces; plain RTMC stays the reference).
+ * Architecture: n_in inputs -> depth hidden layers of width GELU units -> 1
+ * output; BF16 operands on the matrix cores with FP32 accumulation; FP32
+ * master weights updated with AdamW.  Only width 256 and depth 4 are built.
+ * Parameter vector order (FP32): W1 [width x n_in] (row = output unit), b1
+ * [width], W2 [width x width], b2, ..., W_depth, b_depth, w_out [width],
+ * b_out [1]; rtmc_srg_param_count gives its length.
+ * X: device float [n, n_in] (features already normalised by the caller);
+ * y: device float [n].  Training and gradient calls need batch % 32 == 0. */
+rtmc_status rtmc_srg_create(rtmc_ctx* ctx, int32_t n_in, int32_t width, int32_t depth, uint64_t seed,
+                            int32_t* srg_id); /* 1 <= n_in <= 32; He-uniform weights, zero biases */
+rtmc_status rtmc_srg_param_count(rtmc_ctx* ctx, int32_t srg_id, int64_t* n);
+rtmc_status rtmc_srg_get_params(rtmc_ctx* ctx, int32_t srg_id, float* params, int64_t n); /* host */
+rtmc_status rtmc_srg_set_params(rtmc_ctx* ctx, int32_t srg_id, const float* params, int64_t n); /* host; resets AdamW */
+/* Mean-squared-error loss and its gradient (host float [n params], may be NULL) without an update. */
+rtmc_status rtmc_srg_gradient(rtmc_ctx* ctx, int32_t srg_id, const float* X, const float* y, int64_t batch,
+                              float* loss, float* grads);
+/* One AdamW step (beta 0.9 / 0.999, eps 1e-8) on a batch; *loss is the batch loss before the step. */
+rtmc_status rtmc_srg_train_step(rtmc_ctx* ctx, int32_t srg_id, const float* X, const float* y, int64_t batch,
+                                float lr, float weight_decay, float* loss);
+/* Predictions for n rows (any n), written to device float y[n]; asynchronous on the context stream. */
+rtmc_status rtmc_srg_predict(rtmc_ctx* ctx, int32_t srg_id, const float* X, int64_t n, float* y);
+
 #ifdef __cplusplus
 }
 #endif

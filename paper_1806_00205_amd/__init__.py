@@ -31,7 +31,8 @@ EXPORTS = [
     "rtmc_create", "rtmc_destroy", "rtmc_last_error", "rtmc_set_stream", "rtmc_load_mesh", "rtmc_build_bvh",
     "rtmc_get_scene_info", "rtmc_bvh_download", "rtmc_load_tables", "rtmc_trace", "rtmc_trace_batch",
     "rtmc_first_hit", "rtmc_sort_pairs_u64", "rtmc_set_launch", "rtmc_get_launch", "rtmc_autotune",
-    "rtmc_copy_probe",
+    "rtmc_copy_probe", "rtmc_srg_create", "rtmc_srg_param_count", "rtmc_srg_get_params", "rtmc_srg_set_params",
+    "rtmc_srg_gradient", "rtmc_srg_train_step", "rtmc_srg_predict",
 ]
 
 
@@ -125,6 +126,13 @@ def load_library(path: str = LIB_PATH):
         "rtmc_get_launch": ([P, C.POINTER(LaunchCfg)], C.c_int),
         "rtmc_autotune": ([P, i32, i32, dbl, dbl, u64, C.POINTER(LaunchCfg)], C.c_int),
         "rtmc_copy_probe": ([P, P, P, C.c_size_t, i32, C.POINTER(dbl)], C.c_int),
+        "rtmc_srg_create": ([P, i32, i32, i32, u64, C.POINTER(i32)], C.c_int),
+        "rtmc_srg_param_count": ([P, i32, C.POINTER(i64)], C.c_int),
+        "rtmc_srg_get_params": ([P, i32, P, i64], C.c_int),
+        "rtmc_srg_set_params": ([P, i32, P, i64], C.c_int),
+        "rtmc_srg_gradient": ([P, i32, P, P, i64, C.POINTER(C.c_float), P], C.c_int),
+        "rtmc_srg_train_step": ([P, i32, P, P, i64, C.c_float, C.c_float, C.POINTER(C.c_float)], C.c_int),
+        "rtmc_srg_predict": ([P, i32, P, i64, P], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -302,3 +310,53 @@ class Context:
         self._chk(self.lib.rtmc_copy_probe(self.h, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()),
                                            src.numel() * 4, int(reps), C.byref(ms)))
         return 2.0 * nbytes / (ms.value * 1e-3) / 1e9
+
+    # ---------------------------------------------------------------- surrogate
+    def srg_create(self, n_in: int = 8, width: int = 256, depth: int = 4, seed: int = 0) -> int:
+        sid = C.c_int32()
+        self._chk(self.lib.rtmc_srg_create(self.h, n_in, width, depth, int(seed), C.byref(sid)))
+        return sid.value
+
+    def srg_params(self, srg: int) -> np.ndarray:
+        n = C.c_int64()
+        self._chk(self.lib.rtmc_srg_param_count(self.h, srg, C.byref(n)))
+        p = np.zeros(n.value, dtype=np.float32)
+        self._chk(self.lib.rtmc_srg_get_params(self.h, srg, _ptr(p), p.size))
+        return p
+
+    def srg_set_params(self, srg: int, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        self._chk(self.lib.rtmc_srg_set_params(self.h, srg, _ptr(p), p.size))
+
+    def _dev(self, a):
+        torch = self.torch
+        t = torch.as_tensor(a, dtype=torch.float32)
+        return t.to(f"cuda:{self.device}").contiguous()
+
+    def srg_gradient(self, srg: int, X, y):
+        """Loss and gradient (public parameter order) of one batch, no update."""
+        Xd, yd = self._dev(X), self._dev(y)
+        n = self.srg_params(srg).size
+        g = np.zeros(n, dtype=np.float32)
+        loss = C.c_float()
+        self._chk(self.lib.rtmc_srg_gradient(self.h, srg, C.c_void_p(Xd.data_ptr()), C.c_void_p(yd.data_ptr()),
+                                             Xd.shape[0], C.byref(loss), _ptr(g)))
+        return loss.value, g
+
+    def srg_train_step(self, srg: int, X, y, lr: float, weight_decay: float = 0.0) -> float:
+        """X, y: torch tensors on the GPU (float32) or arrays."""
+        Xd = X if getattr(X, "is_cuda", False) else self._dev(X)
+        yd = y if getattr(y, "is_cuda", False) else self._dev(y)
+        loss = C.c_float()
+        self._chk(self.lib.rtmc_srg_train_step(self.h, srg, C.c_void_p(Xd.data_ptr()), C.c_void_p(yd.data_ptr()),
+                                               Xd.shape[0], float(lr), float(weight_decay), C.byref(loss)))
+        return loss.value
+
+    def srg_predict(self, srg: int, X):
+        """Returns a float32 GPU tensor of predictions."""
+        Xd = X if getattr(X, "is_cuda", False) else self._dev(X)
+        y = self.torch.empty(Xd.shape[0], dtype=self.torch.float32, device=Xd.device)
+        self._chk(self.lib.rtmc_srg_predict(self.h, srg, C.c_void_p(Xd.data_ptr()), Xd.shape[0],
+                                            C.c_void_p(y.data_ptr())))
+        return y
+

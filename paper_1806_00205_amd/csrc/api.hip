@@ -36,6 +36,16 @@ struct Scene {
   double build_ms = 0.0;
 };
 
+struct Surrogate {
+  int n_in = 0, width = 256, depth = 4;
+  int64_t n_pub = 0, n_pad = 0;  // public and padded (first layer 32 wide) parameter counts
+  DevBuf master, mom1, mom2, grad;  // FP32, padded layout
+  DevBuf wbf;                       // BF16 weights: W_l and W_l^T per layer
+  DevBuf ws;                        // batch workspace
+  int64_t ws_rows = 0;
+  int64_t step = 0;
+};
+
 struct Tables {
   DevBuf buf;  // yield | cdf_E | cdf_F
   int32_t nE = 0, nth = 0, ncdf = 0;
@@ -56,6 +66,7 @@ struct rtmc_ctx {
   size_t lds_per_block = 0;
   std::vector<Scene> scenes;
   std::vector<Tables> tables;
+  std::vector<Surrogate> srgs;
   rtmc_launch_cfg cfg{256, 6, 16, 1 << 24, 48, 0};
   // trace work buffers, grown on demand
   DevBuf queue[2];
@@ -505,6 +516,14 @@ void rtmc_destroy(rtmc_ctx* c) {
     dev_free(c, s.nodes);
   }
   for (auto& t : c->tables) dev_free(c, t.buf);
+  for (auto& g : c->srgs) {
+    dev_free(c, g.master);
+    dev_free(c, g.mom1);
+    dev_free(c, g.mom2);
+    dev_free(c, g.grad);
+    dev_free(c, g.wbf);
+    dev_free(c, g.ws);
+  }
   dev_free(c, c->queue[0]);
   dev_free(c, c->queue[1]);
   dev_free(c, c->hits);
@@ -1000,4 +1019,401 @@ rtmc_status rtmc_copy_probe(rtmc_ctx* c, void* dst, const void* src, size_t byte
   return RTMC_OK;
 }
 
+
 }  // extern "C"
+
+// ---------------------------------------------------------------- surrogate
+namespace {
+
+constexpr int kPadIn = 32;  // first-layer inputs padded to one MFMA k-step
+
+// offsets (floats) into the padded FP32 parameter vector
+struct SrgLayout {
+  int64_t W[5], b[5], wout, bout, total;
+};
+
+SrgLayout srg_layout(const Surrogate& g) {
+  SrgLayout L{};
+  int64_t o = 0;
+  for (int l = 1; l <= g.depth; ++l) {
+    const int kin = l == 1 ? kPadIn : g.width;
+    L.W[l] = o;
+    o += (int64_t)g.width * kin;
+    L.b[l] = o;
+    o += g.width;
+  }
+  L.wout = o;
+  o += g.width;
+  L.bout = o;
+  o += 1;
+  L.total = o;
+  return L;
+}
+
+// BF16 weight copies: per layer W_l [width x kin] then W_l^T [kin x width]
+int64_t srg_wbf_off(const Surrogate& g, int l, bool transposed) {
+  int64_t o = 0;
+  for (int q = 1; q < l; ++q) o += 2 * (int64_t)g.width * (q == 1 ? kPadIn : g.width);
+  const int kin = l == 1 ? kPadIn : g.width;
+  return o + (transposed ? (int64_t)g.width * kin : 0);
+}
+
+struct SrgWs {
+  __bf16 *X, *Xt;
+  float* Z[5];
+  __bf16 *H[5], *Ht[5];
+  __bf16 *G[2], *Gt[2];
+  float *y, *dy, *acc;
+};
+
+// workspace for `rows` rows: X, Xt, Z1..4, H1..4, Ht1..4, two G ping-pongs, y, dy, acc
+SrgWs srg_ws(Surrogate& g, int64_t rows) {
+  SrgWs w{};
+  char* p = reinterpret_cast<char*>(g.ws.p);
+  const size_t R = (size_t)rows, W = (size_t)g.width;
+  auto take = [&](size_t bytes) {
+    char* q = p;
+    p += (bytes + 255) & ~(size_t)255;
+    return q;
+  };
+  w.X = reinterpret_cast<__bf16*>(take(R * kPadIn * 2));
+  w.Xt = reinterpret_cast<__bf16*>(take(R * kPadIn * 2));
+  for (int l = 1; l <= 4; ++l) w.Z[l] = reinterpret_cast<float*>(take(R * W * 4));
+  for (int l = 1; l <= 4; ++l) w.H[l] = reinterpret_cast<__bf16*>(take(R * W * 2));
+  for (int l = 1; l <= 4; ++l) w.Ht[l] = reinterpret_cast<__bf16*>(take(R * W * 2));
+  for (int i = 0; i < 2; ++i) w.G[i] = reinterpret_cast<__bf16*>(take(R * W * 2));
+  for (int i = 0; i < 2; ++i) w.Gt[i] = reinterpret_cast<__bf16*>(take(R * W * 2));
+  w.y = reinterpret_cast<float*>(take(R * 4));
+  w.dy = reinterpret_cast<float*>(take(R * 4));
+  w.acc = reinterpret_cast<float*>(take(64));
+  return w;
+}
+
+size_t srg_ws_total(const Surrogate& g, int64_t rows) {
+  const size_t R = (size_t)rows, W = (size_t)g.width;
+  auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  return 2 * r(R * kPadIn * 2) + 4 * r(R * W * 4) + 8 * r(R * W * 2) + 4 * r(R * W * 2) + 2 * r(R * 4) + r(64);
+}
+
+rtmc_status srg_check(rtmc_ctx* c, int32_t id) {
+  if (!c) return RTMC_EINVAL;
+  c->err.clear();
+  if (id < 0 || id >= (int32_t)c->srgs.size()) return fail(c, RTMC_EINVAL, "unknown surrogate id %d", id);
+  return RTMC_OK;
+}
+
+rtmc_status srg_refresh_bf16(rtmc_ctx* c, Surrogate& g) {
+  const SrgLayout L = srg_layout(g);
+  const float* m = reinterpret_cast<const float*>(g.master.p);
+  __bf16* wb = reinterpret_cast<__bf16*>(g.wbf.p);
+  for (int l = 1; l <= g.depth; ++l) {
+    const int kin = l == 1 ? kPadIn : g.width;
+    HIPCHK(c, mlp_to_bf16(m + L.W[l], g.width, kin, wb + srg_wbf_off(g, l, false), wb + srg_wbf_off(g, l, true),
+                          c->stream));
+  }
+  return RTMC_OK;
+}
+
+// Forward over `rows` rows of X; training keeps Z, H^T and X^T for the backward.
+rtmc_status srg_forward(rtmc_ctx* c, Surrogate& g, const float* X, int64_t rows, bool train, const SrgWs& w,
+                        float* y_out) {
+  const SrgLayout L = srg_layout(g);
+  const float* m = reinterpret_cast<const float*>(g.master.p);
+  const __bf16* wb = reinterpret_cast<const __bf16*>(g.wbf.p);
+  const int R = (int)rows;
+  HIPCHK(c, mlp_pack_input(X, R, g.n_in, w.X, train ? w.Xt : nullptr, c->stream));
+  for (int l = 1; l <= g.depth; ++l) {
+    MlpGemm q{};
+    const int kin = l == 1 ? kPadIn : g.width;
+    q.A = l == 1 ? w.X : w.H[l - 1];
+    q.lda = kin;
+    q.B = wb + srg_wbf_off(g, l, false);
+    q.ldb = kin;
+    q.M = R;
+    q.N = g.width;
+    q.K = kin;
+    q.epi = MLP_EPI_FWD_GELU;
+    q.bias = m + L.b[l];
+    q.Z = train ? w.Z[l] : nullptr;
+    q.ldz = g.width;
+    q.H = w.H[l];
+    q.ldh = g.width;
+    q.Ht = train ? w.Ht[l] : nullptr;
+    q.ldht = R;
+    HIPCHK(c, mlp_gemm(q, c->stream));
+  }
+  HIPCHK(c, mlp_out_fwd(w.H[g.depth], R, g.width, m + L.wout, m + L.bout, y_out, c->stream));
+  return RTMC_OK;
+}
+
+// Loss and gradients (padded layout, into g.grad) for one batch.
+rtmc_status srg_backward(rtmc_ctx* c, Surrogate& g, const float* y_true, int64_t rows, const SrgWs& w) {
+  const SrgLayout L = srg_layout(g);
+  const float* m = reinterpret_cast<const float*>(g.master.p);
+  const __bf16* wb = reinterpret_cast<const __bf16*>(g.wbf.p);
+  float* gr = reinterpret_cast<float*>(g.grad.p);
+  const int R = (int)rows, Wd = g.width;
+  HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(w.acc), 0u, 2, c->stream));
+  HIPCHK(c, mlp_mse(w.y, y_true, R, w.dy, w.acc, c->stream));
+  // output layer
+  HIPCHK(c, mlp_rowsum(w.Ht[g.depth], Wd, R, w.dy, gr + L.wout, c->stream));
+  HIPCHK(c, hipMemcpyAsync(gr + L.bout, w.acc + 1, 4, hipMemcpyDeviceToDevice, c->stream));
+  int cur = 0;
+  HIPCHK(c, mlp_out_bwd_hidden(w.dy, m + L.wout, w.Z[g.depth], R, Wd, w.G[cur], w.Gt[cur], c->stream));
+  for (int l = g.depth; l >= 1; --l) {
+    const int kin = l == 1 ? kPadIn : Wd;
+    // dW_l = G^T H_{l-1}  (FP32)
+    MlpGemm q{};
+    q.A = w.Gt[cur];
+    q.lda = R;
+    q.B = l == 1 ? w.Xt : w.Ht[l - 1];
+    q.ldb = R;
+    q.M = Wd;
+    q.N = kin;
+    q.K = R;
+    q.epi = MLP_EPI_F32;
+    q.C = gr + L.W[l];
+    q.ldc = kin;
+    HIPCHK(c, mlp_gemm(q, c->stream));
+    HIPCHK(c, mlp_rowsum(w.Gt[cur], Wd, R, nullptr, gr + L.b[l], c->stream));
+    if (l > 1) {
+      // G_{l-1} = (G W_l) * GELU'(Z_{l-1})
+      MlpGemm d{};
+      d.A = w.G[cur];
+      d.lda = Wd;
+      d.B = wb + srg_wbf_off(g, l, true);
+      d.ldb = Wd;
+      d.M = R;
+      d.N = Wd;
+      d.K = Wd;
+      d.epi = MLP_EPI_BWD_GELU;
+      d.Zs = w.Z[l - 1];
+      d.ldz = Wd;
+      d.H = w.G[cur ^ 1];
+      d.ldh = Wd;
+      d.Ht = w.Gt[cur ^ 1];
+      d.ldht = R;
+      HIPCHK(c, mlp_gemm(d, c->stream));
+      cur ^= 1;
+    }
+  }
+  return RTMC_OK;
+}
+
+rtmc_status srg_ensure_ws(rtmc_ctx* c, Surrogate& g, int64_t rows) {
+  if (g.ws.p && g.ws_rows >= rows) return RTMC_OK;
+  rtmc_status st = ensure(c, g.ws, srg_ws_total(g, rows));
+  if (st) return st;
+  g.ws_rows = rows;
+  return RTMC_OK;
+}
+
+void pub_to_pad(const Surrogate& g, const float* pub, std::vector<float>& pad) {
+  const SrgLayout L = srg_layout(g);
+  pad.assign((size_t)L.total, 0.0f);
+  int64_t o = 0;
+  for (int l = 1; l <= g.depth; ++l) {
+    const int kin = l == 1 ? g.n_in : g.width;
+    const int kp = l == 1 ? kPadIn : g.width;
+    for (int r = 0; r < g.width; ++r)
+      for (int k = 0; k < kin; ++k) pad[(size_t)(L.W[l] + (int64_t)r * kp + k)] = pub[o++];
+    for (int r = 0; r < g.width; ++r) pad[(size_t)(L.b[l] + r)] = pub[o++];
+  }
+  for (int r = 0; r < g.width; ++r) pad[(size_t)(L.wout + r)] = pub[o++];
+  pad[(size_t)L.bout] = pub[o++];
+}
+
+void pad_to_pub(const Surrogate& g, const float* pad, float* pub) {
+  const SrgLayout L = srg_layout(g);
+  int64_t o = 0;
+  for (int l = 1; l <= g.depth; ++l) {
+    const int kin = l == 1 ? g.n_in : g.width;
+    const int kp = l == 1 ? kPadIn : g.width;
+    for (int r = 0; r < g.width; ++r)
+      for (int k = 0; k < kin; ++k) pub[o++] = pad[(size_t)(L.W[l] + (int64_t)r * kp + k)];
+    for (int r = 0; r < g.width; ++r) pub[o++] = pad[(size_t)(L.b[l] + r)];
+  }
+  for (int r = 0; r < g.width; ++r) pub[o++] = pad[(size_t)(L.wout + r)];
+  pub[o++] = pad[(size_t)L.bout];
+}
+
+rtmc_status srg_upload(rtmc_ctx* c, Surrogate& g, const std::vector<float>& pad) {
+  HIPCHK(c, hipMemcpyAsync(g.master.p, pad.data(), pad.size() * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(g.mom1.p), 0u, pad.size(), c->stream));
+  HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(g.mom2.p), 0u, pad.size(), c->stream));
+  g.step = 0;
+  rtmc_status st = srg_refresh_bf16(c, g);
+  if (st) return st;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return RTMC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+rtmc_status rtmc_srg_create(rtmc_ctx* c, int32_t n_in, int32_t width, int32_t depth, uint64_t seed, int32_t* id) {
+  if (!c) return RTMC_EINVAL;
+  c->err.clear();
+  if (!id || n_in < 1 || n_in > kPadIn) return fail(c, RTMC_EINVAL, "n_in must be in [1, 32]");
+  if (width != 256 || depth != 4) return fail(c, RTMC_ENOTIMPL, "only width 256 and depth 4 are built");
+  HIPCHK(c, hipSetDevice(c->device));
+  Surrogate g;
+  g.n_in = n_in;
+  g.width = width;
+  g.depth = depth;
+  const SrgLayout L = srg_layout(g);
+  g.n_pad = L.total;
+  g.n_pub = L.total - (int64_t)width * (kPadIn - n_in);
+  if (ensure(c, g.master, L.total * 4) || ensure(c, g.mom1, L.total * 4) || ensure(c, g.mom2, L.total * 4) ||
+      ensure(c, g.grad, L.total * 4) || ensure(c, g.wbf, (size_t)srg_wbf_off(g, depth + 1, false) * 2)) {
+    dev_free(c, g.master);
+    dev_free(c, g.mom1);
+    dev_free(c, g.mom2);
+    dev_free(c, g.grad);
+    dev_free(c, g.wbf);
+    return RTMC_ENOMEM;
+  }
+  // He-uniform initialisation from a seeded 64-bit generator (host)
+  std::vector<float> pub((size_t)g.n_pub, 0.0f);
+  uint64_t st = seed ^ 0x9E3779B97F4A7C15ull;
+  auto next = [&]() {
+    st += 0x9E3779B97F4A7C15ull;
+    uint64_t z = st;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return (double)(z >> 11) * (1.0 / 9007199254740992.0);
+  };
+  int64_t o = 0;
+  for (int l = 1; l <= depth; ++l) {
+    const int kin = l == 1 ? n_in : width;
+    const double a = std::sqrt(6.0 / kin);
+    for (int64_t i = 0; i < (int64_t)width * kin; ++i) pub[(size_t)o++] = (float)((2.0 * next() - 1.0) * a);
+    o += width;  // zero bias
+  }
+  const double a = std::sqrt(3.0 / width);
+  for (int r = 0; r < width; ++r) pub[(size_t)o++] = (float)((2.0 * next() - 1.0) * a);
+  c->srgs.push_back(g);
+  Surrogate& gg = c->srgs.back();
+  std::vector<float> pad;
+  pub_to_pad(gg, pub.data(), pad);
+  rtmc_status s2 = srg_upload(c, gg, pad);
+  if (s2) return s2;
+  *id = (int32_t)c->srgs.size() - 1;
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_srg_param_count(rtmc_ctx* c, int32_t id, int64_t* n) {
+  rtmc_status st = srg_check(c, id);
+  if (st) return st;
+  if (!n) return fail(c, RTMC_EINVAL, "null output");
+  *n = c->srgs[id].n_pub;
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_srg_get_params(rtmc_ctx* c, int32_t id, float* params, int64_t n) {
+  rtmc_status st = srg_check(c, id);
+  if (st) return st;
+  Surrogate& g = c->srgs[id];
+  if (!params || n != g.n_pub) return fail(c, RTMC_EINVAL, "parameter array must hold %lld floats", (long long)g.n_pub);
+  HIPCHK(c, hipSetDevice(c->device));
+  std::vector<float> pad((size_t)g.n_pad);
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(pad.data(), g.master.p, pad.size() * 4, hipMemcpyDeviceToHost));
+  pad_to_pub(g, pad.data(), params);
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_srg_set_params(rtmc_ctx* c, int32_t id, const float* params, int64_t n) {
+  rtmc_status st = srg_check(c, id);
+  if (st) return st;
+  Surrogate& g = c->srgs[id];
+  if (!params || n != g.n_pub) return fail(c, RTMC_EINVAL, "parameter array must hold %lld floats", (long long)g.n_pub);
+  for (int64_t i = 0; i < n; ++i)
+    if (!std::isfinite(params[i])) return fail(c, RTMC_EINVAL, "parameter %lld is not finite", (long long)i);
+  HIPCHK(c, hipSetDevice(c->device));
+  std::vector<float> pad;
+  pub_to_pad(g, params, pad);
+  return srg_upload(c, g, pad);
+}
+
+rtmc_status rtmc_srg_gradient(rtmc_ctx* c, int32_t id, const float* X, const float* y, int64_t batch, float* loss,
+                              float* grads) {
+  rtmc_status st = srg_check(c, id);
+  if (st) return st;
+  Surrogate& g = c->srgs[id];
+  if (!X || !y || batch < 32 || batch % 32 || batch > (1 << 22)) return fail(c, RTMC_EINVAL, "batch must be a positive multiple of 32");
+  HIPCHK(c, hipSetDevice(c->device));
+  st = srg_ensure_ws(c, g, batch);
+  if (st) return st;
+  const SrgWs w = srg_ws(g, batch);
+  st = srg_forward(c, g, X, batch, true, w, w.y);
+  if (st) return st;
+  st = srg_backward(c, g, y, batch, w);
+  if (st) return st;
+  float acc[2] = {0.f, 0.f};
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  HIPCHK(c, hipMemcpy(acc, w.acc, 8, hipMemcpyDeviceToHost));
+  if (loss) *loss = acc[0];
+  if (grads) {
+    std::vector<float> pad((size_t)g.n_pad);
+    HIPCHK(c, hipMemcpy(pad.data(), g.grad.p, pad.size() * 4, hipMemcpyDeviceToHost));
+    pad_to_pub(g, pad.data(), grads);
+  }
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_srg_train_step(rtmc_ctx* c, int32_t id, const float* X, const float* y, int64_t batch, float lr,
+                                float weight_decay, float* loss) {
+  rtmc_status st = srg_check(c, id);
+  if (st) return st;
+  Surrogate& g = c->srgs[id];
+  if (!X || !y || batch < 32 || batch % 32 || batch > (1 << 22)) return fail(c, RTMC_EINVAL, "batch must be a positive multiple of 32");
+  if (!(lr > 0.0f) || !(weight_decay >= 0.0f)) return fail(c, RTMC_EINVAL, "bad learning rate or weight decay");
+  HIPCHK(c, hipSetDevice(c->device));
+  st = srg_ensure_ws(c, g, batch);
+  if (st) return st;
+  const SrgWs w = srg_ws(g, batch);
+  st = srg_forward(c, g, X, batch, true, w, w.y);
+  if (st) return st;
+  st = srg_backward(c, g, y, batch, w);
+  if (st) return st;
+  g.step += 1;
+  const float b1 = 0.9f, b2 = 0.999f;
+  const float c1 = 1.0f - (float)std::pow(b1, (double)g.step), c2 = 1.0f - (float)std::pow(b2, (double)g.step);
+  HIPCHK(c, mlp_adamw(reinterpret_cast<float*>(g.master.p), reinterpret_cast<float*>(g.mom1.p),
+                      reinterpret_cast<float*>(g.mom2.p), reinterpret_cast<const float*>(g.grad.p), g.n_pad, lr, b1,
+                      b2, 1e-8f, weight_decay, c1, c2, c->stream));
+  st = srg_refresh_bf16(c, g);
+  if (st) return st;
+  if (loss) {
+    float acc[2] = {0.f, 0.f};
+    HIPCHK(c, hipMemcpyAsync(acc, w.acc, 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *loss = acc[0];
+  }
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_srg_predict(rtmc_ctx* c, int32_t id, const float* X, int64_t n, float* y) {
+  rtmc_status st = srg_check(c, id);
+  if (st) return st;
+  Surrogate& g = c->srgs[id];
+  if (n < 0 || (n > 0 && (!X || !y))) return fail(c, RTMC_EINVAL, "bad prediction arrays");
+  if (n == 0) return RTMC_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  const int64_t chunk = std::min<int64_t>(n, 1 << 18);
+  st = srg_ensure_ws(c, g, chunk);
+  if (st) return st;
+  const SrgWs w = srg_ws(g, chunk);
+  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
+    const int64_t rows = std::min(chunk, n - r0);
+    st = srg_forward(c, g, X + r0 * g.n_in, rows, false, w, y + r0);
+    if (st) return st;
+  }
+  return RTMC_OK;
+}
+
+}  // extern "C"
+

@@ -1,0 +1,250 @@
+// Learned surrogate of the yield: an MLP from foam descriptors and (E, cos
+// theta) to the RTMC yield, trained on yields the traversal path produces.
+// Hidden layers are dense contractions, so they run on gfx950 matrix cores:
+// BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16), with bias,
+// GELU and its derivative fused into the GEMM epilogues.
+//
+// One GEMM shape serves the forward and both backward products: C = A * B^T
+// with A [M, K] and B [N, K] both K-contiguous (row-major), K a multiple of 32.
+//   forward       Z_l  = H_{l-1} W_l^T        (A = H_{l-1} [B, K],  B = W_l [N, K])
+//   input grad    dH   = G_l W_l              (A = G_l [B, N],      B = W_l^T [K, N])
+//   weight grad   dW_l = G_l^T H_{l-1}        (A = G_l^T [N, B],    B = H_{l-1}^T [K, B])
+// so activations and gradients are written in both layouts by the epilogues.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rtmc_internal.h"
+
+namespace rtmc {
+namespace {
+
+#define GAS __attribute__((address_space(1)))
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
+
+// GELU with the exact normal CDF, and its derivative
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+__device__ inline float gelu_d(float x) {
+  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+}
+
+// Workgroup tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA blocks of 16 x 16).
+// Fragment layout of the 16x16x32 BF16 MFMA (lane l):
+//   A: row l % 16, k = 8 (l / 16) .. + 7;  B: column l % 16, same k;
+//   C: column l % 16, rows 4 (l / 16) .. + 3.
+__global__ __launch_bounds__(256) void k_gemm_nt(MlpGemm g) {
+  const int w = threadIdx.x >> 6;
+  const uint32_t l = lane_id();
+  const int m0 = blockIdx.x * 64 + (w >> 1) * 32;
+  const int n0 = blockIdx.y * 64 + (w & 1) * 32;
+  const int r = l & 15, kg = (l >> 4) * 8;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero8 = {};
+  for (int k0 = 0; k0 < g.K; k0 += 32) {
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int m = m0 + 16 * i + r;
+      a[i] = m < g.M ? *(const GAS bf16x8*)(g.A + (size_t)m * g.lda + k0 + kg) : zero8;
+      const int n = n0 + 16 * i + r;
+      b[i] = n < g.N ? *(const GAS bf16x8*)(g.B + (size_t)n * g.ldb + k0 + kg) : zero8;
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int n = n0 + 16 * j + (l & 15);
+      if (n >= g.N) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int m = m0 + 16 * i + 4 * (l >> 4) + q;
+        if (m >= g.M) continue;
+        const float v = acc[i][j][q];
+        if (g.epi == MLP_EPI_F32) {
+          g.C[(size_t)m * g.ldc + n] = v;
+        } else if (g.epi == MLP_EPI_FWD_GELU) {
+          const float z = v + g.bias[n];
+          const float h = gelu(z);
+          if (g.Z) g.Z[(size_t)m * g.ldz + n] = z;
+          g.H[(size_t)m * g.ldh + n] = (__bf16)h;
+          if (g.Ht) g.Ht[(size_t)n * g.ldht + m] = (__bf16)h;
+        } else {  // MLP_EPI_BWD_GELU: dZ = dH * GELU'(Z)
+          const float d = v * gelu_d(g.Zs[(size_t)m * g.ldz + n]);
+          g.H[(size_t)m * g.ldh + n] = (__bf16)d;
+          if (g.Ht) g.Ht[(size_t)n * g.ldht + m] = (__bf16)d;
+        }
+      }
+    }
+}
+
+// Inputs: float [B, n_in] -> bf16 [B, 32] (zero padded) and its transpose [32, B].
+__global__ void k_pack_input(const float* __restrict__ x, int B, int n_in, __bf16* __restrict__ X,
+                             __bf16* __restrict__ Xt) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  for (int k = 0; k < 32; ++k) {
+    const __bf16 v = (__bf16)(k < n_in ? x[(size_t)b * n_in + k] : 0.0f);
+    X[(size_t)b * 32 + k] = v;
+    if (Xt) Xt[(size_t)k * B + b] = v;
+  }
+}
+
+// Output layer: y = H w + c (one wave per 64 rows, FP32 accumulation).
+__global__ void k_out_fwd(const __bf16* __restrict__ H, int B, int width, const float* __restrict__ w,
+                          const float* __restrict__ c, float* __restrict__ y) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= B) return;
+  float s = c[0];
+  const __bf16* h = H + (size_t)b * width;
+  for (int k = 0; k < width; ++k) s += (float)h[k] * w[k];
+  y[b] = s;
+}
+
+// Mean squared error: dy = 2 (y - t) / B; acc[0] += mean (y - t)^2, acc[1] +=
+// sum dy (the output bias gradient).
+__global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, int B, float* __restrict__ dy,
+                      float* __restrict__ acc) {
+  __shared__ float part[2][256];
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  float e = 0.f, g = 0.f;
+  if (b < B) {
+    const float d = y[b] - t[b];
+    g = 2.0f * d / (float)B;
+    dy[b] = g;
+    e = d * d / (float)B;
+  }
+  part[0][threadIdx.x] = e;
+  part[1][threadIdx.x] = g;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) {
+      part[0][threadIdx.x] += part[0][threadIdx.x + s];
+      part[1][threadIdx.x] += part[1][threadIdx.x + s];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    atomicAdd(acc, part[0][0]);
+    atomicAdd(acc + 1, part[1][0]);
+  }
+}
+
+// Backward of the output layer into the last hidden layer:
+//   G[b, k] = dy[b] w[k] GELU'(Z[b, k]) (bf16, both layouts).
+__global__ void k_out_bwd_hidden(const float* __restrict__ dy, const float* __restrict__ w,
+                                 const float* __restrict__ Z, int B, int width, __bf16* __restrict__ G,
+                                 __bf16* __restrict__ Gt) {
+  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (size_t)B * width) return;
+  const int b = (int)(i / width), k = (int)(i % width);
+  const float d = dy[b] * w[k] * gelu_d(Z[i]);
+  G[i] = (__bf16)d;
+  Gt[(size_t)k * B + b] = (__bf16)d;
+}
+
+// Row sums of a [R, B] bf16 matrix into FP32 (bias gradients from G^T), or of
+// dy * H^T rows (output weights): out[r] = sum_b Mt[r, b] * (s ? s[b] : 1).
+__global__ void k_rowsum(const __bf16* __restrict__ Mt, int R, int B, const float* __restrict__ s,
+                         float* __restrict__ out) {
+  __shared__ float part[256];
+  const int r = blockIdx.x;
+  if (r >= R) return;
+  float acc = 0.f;
+  for (int b = threadIdx.x; b < B; b += blockDim.x) acc += (float)Mt[(size_t)r * B + b] * (s ? s[b] : 1.0f);
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int k = 128; k > 0; k >>= 1) {
+    if ((int)threadIdx.x < k) part[threadIdx.x] += part[threadIdx.x + k];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[r] = part[0];
+}
+
+// AdamW on the FP32 master parameters (Loshchilov and Hutter), then BF16
+// copies of the weight matrices in both layouts.
+__global__ void k_adamw(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                        const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps, float wd,
+                        float c1, float c2) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i]);
+  }
+}
+
+__global__ void k_to_bf16(const float* __restrict__ W, int rows, int cols, __bf16* __restrict__ Wb,
+                          __bf16* __restrict__ Wtb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= rows * cols) return;
+  const int r = i / cols, c = i % cols;
+  const __bf16 v = (__bf16)W[i];
+  Wb[i] = v;
+  if (Wtb) Wtb[(size_t)c * rows + r] = v;
+}
+
+}  // namespace
+
+hipError_t mlp_gemm(const MlpGemm& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  dim3 grid((g.M + 63) / 64, (g.N + 63) / 64);
+  k_gemm_nt<<<grid, 256, 0, s>>>(g);
+  return hipGetLastError();
+}
+
+hipError_t mlp_pack_input(const float* x, int B, int n_in, __bf16* X, __bf16* Xt, hipStream_t s) {
+  k_pack_input<<<(B + 255) / 256, 256, 0, s>>>(x, B, n_in, X, Xt);
+  return hipGetLastError();
+}
+
+hipError_t mlp_out_fwd(const __bf16* H, int B, int width, const float* w, const float* c, float* y, hipStream_t s) {
+  k_out_fwd<<<(B + 255) / 256, 256, 0, s>>>(H, B, width, w, c, y);
+  return hipGetLastError();
+}
+
+hipError_t mlp_mse(const float* y, const float* t, int B, float* dy, float* loss_acc, hipStream_t s) {
+  k_mse<<<(B + 255) / 256, 256, 0, s>>>(y, t, B, dy, loss_acc);
+  return hipGetLastError();
+}
+
+hipError_t mlp_out_bwd_hidden(const float* dy, const float* w, const float* Z, int B, int width, __bf16* G,
+                              __bf16* Gt, hipStream_t s) {
+  const size_t n = (size_t)B * width;
+  k_out_bwd_hidden<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dy, w, Z, B, width, G, Gt);
+  return hipGetLastError();
+}
+
+hipError_t mlp_rowsum(const __bf16* Mt, int R, int B, const float* scale, float* out, hipStream_t s) {
+  k_rowsum<<<R, 256, 0, s>>>(Mt, R, B, scale, out);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adamw(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                     float wd, float c1, float c2, hipStream_t s) {
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  k_adamw<<<grid, 256, 0, s>>>(p, m, v, g, n, lr, b1, b2, eps, wd, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t mlp_to_bf16(const float* W, int rows, int cols, __bf16* Wb, __bf16* Wtb, hipStream_t s) {
+  const int n = rows * cols;
+  k_to_bf16<<<(n + 255) / 256, 256, 0, s>>>(W, rows, cols, Wb, Wtb);
+  return hipGetLastError();
+}
+
+}  // namespace rtmc

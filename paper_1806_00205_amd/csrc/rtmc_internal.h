@@ -148,6 +148,40 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t s);
 hipError_t launch_copy_probe(float4* dst, const float4* src, size_t n16, int grid, hipStream_t s);
 
+// Surrogate MLP pieces (mlp.hip)
+enum MlpEpi { MLP_EPI_F32 = 0, MLP_EPI_FWD_GELU = 1, MLP_EPI_BWD_GELU = 2 };
+
+// C = A B^T, A [M, K] and B [N, K] bf16 row-major, K % 32 == 0, FP32 accumulation.
+//   MLP_EPI_F32:      C[m, n] (float, ldc)
+//   MLP_EPI_FWD_GELU: z = acc + bias[n]; Z[m, n] = z (if Z); H[m, n] = GELU(z) (bf16); Ht[n, m] likewise (if Ht)
+//   MLP_EPI_BWD_GELU: d = acc * GELU'(Zs[m, n]); H[m, n] = d (bf16); Ht[n, m] likewise (if Ht)
+struct MlpGemm {
+  const __bf16* A;
+  const __bf16* B;
+  int M, N, K, lda, ldb;
+  int epi;
+  const float* bias;
+  float* Z;
+  int ldz;
+  __bf16* H;
+  int ldh;
+  __bf16* Ht;
+  int ldht;
+  float* C;
+  int ldc;
+  const float* Zs;
+};
+hipError_t mlp_gemm(const MlpGemm& g, hipStream_t s);
+hipError_t mlp_pack_input(const float* x, int B, int n_in, __bf16* X, __bf16* Xt, hipStream_t s);
+hipError_t mlp_out_fwd(const __bf16* H, int B, int width, const float* w, const float* c, float* y, hipStream_t s);
+hipError_t mlp_mse(const float* y, const float* t, int B, float* dy, float* acc, hipStream_t s);
+hipError_t mlp_out_bwd_hidden(const float* dy, const float* w, const float* Z, int B, int width, __bf16* G,
+                              __bf16* Gt, hipStream_t s);
+hipError_t mlp_rowsum(const __bf16* Mt, int R, int B, const float* scale, float* out, hipStream_t s);
+hipError_t mlp_adamw(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
+                     float wd, float c1, float c2, hipStream_t s);
+hipError_t mlp_to_bf16(const float* W, int rows, int cols, __bf16* Wb, __bf16* Wtb, hipStream_t s);
+
 // BVH builder pieces
 struct BvhBuild {
   const float4* tris_in;  // [3 n] unsorted, compacted

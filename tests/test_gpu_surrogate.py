@@ -1,0 +1,113 @@
+"""Surrogate MLP kernels (BF16 MFMA, FP32 accumulation) against the FP64 reference."""
+import numpy as np
+import pytest
+
+from oracle import mlp_ref
+
+pytestmark = pytest.mark.gpu
+
+N_IN = 8
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_1806_00205_amd as rt
+    c = rt.Context(0)
+    yield c
+    c.close()
+
+
+def _data(seed, B):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(B, N_IN)).astype(np.float32)
+    t = (np.sin(X[:, 0]) + 0.5 * X[:, 1] * X[:, 2] - 0.3 * X[:, 7]).astype(np.float32)
+    return X, t
+
+
+def test_params_roundtrip(ctx):
+    s = ctx.srg_create(N_IN, 256, 4, seed=3)
+    p = ctx.srg_params(s)
+    assert p.size == mlp_ref.n_params(N_IN)
+    q = np.random.default_rng(0).normal(size=p.size).astype(np.float32) * 0.01
+    ctx.srg_set_params(s, q)
+    assert np.array_equal(ctx.srg_params(s), q)
+
+
+@pytest.mark.parametrize("B", [64, 1000, 4096 + 7])
+def test_forward_matches_reference(ctx, B):
+    s = ctx.srg_create(N_IN, 256, 4, seed=1)
+    p = ctx.srg_params(s)
+    X, _ = _data(2, B)
+    y = ctx.srg_predict(s, X).cpu().numpy().astype(np.float64)
+    pv = mlp_ref.gpu_visible_params(p, N_IN)
+    yr, _ = mlp_ref.forward(pv, mlp_ref.round_bf16(X), N_IN)
+    # BF16 activations between layers: relative error of a few 2^-8 steps
+    err = np.abs(y - yr)
+    assert np.max(err) <= 0.03 * np.max(np.abs(yr)) + 1e-3, np.max(err)
+    assert np.sqrt(np.mean(err ** 2)) <= 0.01 * np.sqrt(np.mean(yr ** 2)) + 1e-4
+
+
+def test_predict_across_chunks_and_tiny(ctx):
+    s = ctx.srg_create(N_IN, 256, 4, seed=4)
+    X, _ = _data(5, (1 << 18) + 77)
+    y_all = ctx.srg_predict(s, X).cpu().numpy()
+    y_head = ctx.srg_predict(s, X[:1]).cpu().numpy()
+    y_tail = ctx.srg_predict(s, X[-100:]).cpu().numpy()
+    assert y_head[0] == y_all[0]
+    assert np.array_equal(y_tail, y_all[-100:])
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradient_matches_reference(ctx, seed):
+    s = ctx.srg_create(N_IN, 256, 4, seed=10 + seed)
+    p = ctx.srg_params(s)
+    X, t = _data(20 + seed, 512)
+    loss, g = ctx.srg_gradient(s, X, t)
+    pv = mlp_ref.gpu_visible_params(p, N_IN)
+    lr, gr = mlp_ref.loss_and_grad(pv, mlp_ref.round_bf16(X), t, N_IN)
+    assert loss == pytest.approx(lr, rel=2e-2)
+    g = g.astype(np.float64)
+    cos = g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr))
+    rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    assert cos > 0.999 and rel < 2e-2, (cos, rel)
+    # every parameter block, separately
+    n_in, W = N_IN, 256
+    bounds = [0, W * n_in, W * n_in + W]
+    o = bounds[-1]
+    for _ in range(3):
+        o += W * W
+        bounds.append(o)
+        o += W
+        bounds.append(o)
+    bounds += [o + W, o + W + 1]
+    for a, b in zip(bounds[:-1], bounds[1:]):
+        ga, gb = g[a:b], gr[a:b]
+        if np.linalg.norm(gb) > 0:
+            assert np.linalg.norm(ga - gb) <= 3e-2 * np.linalg.norm(gb) + 1e-7, (a, b)
+
+
+def test_training_converges(ctx):
+    import torch
+    s = ctx.srg_create(N_IN, 256, 4, seed=7)
+    X, t = _data(30, 8192)
+    Xd = torch.tensor(X, device="cuda:0")
+    td = torch.tensor(t, device="cuda:0")
+    first = None
+    for it in range(400):
+        idx = torch.randint(0, 8192, (1024,), device="cuda:0",
+                            generator=torch.Generator(device="cuda:0").manual_seed(it))
+        loss = ctx.srg_train_step(s, Xd[idx].contiguous(), td[idx].contiguous(), lr=1e-3)
+        first = loss if first is None else first
+    y = ctx.srg_predict(s, Xd).cpu().numpy()
+    mse = float(np.mean((y - t) ** 2))
+    assert mse < first / 20, (first, mse)
+
+
+def test_rejects_bad_shapes(ctx):
+    import paper_1806_00205_amd as rt
+    s = ctx.srg_create(N_IN, 256, 4, seed=0)
+    X, t = _data(0, 100)
+    with pytest.raises(rt.RtmcError):
+        ctx.srg_gradient(s, X, t)  # batch not a multiple of 32
+    with pytest.raises(rt.RtmcError):
+        ctx.srg_create(N_IN, 128, 4, seed=0)
