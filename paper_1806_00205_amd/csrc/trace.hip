@@ -680,7 +680,11 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   LAS uint32_t* s_ah = (LAS uint32_t*)(lds + off);
 
   const uint32_t count = a.gen == 0 ? a.n_gen0 : min(*gp(a.count_in), a.qcap);  // queue length
-  if ((uint32_t)blockIdx.x * blockDim.x >= count) return;  // whole workgroup idle
+  // each wave takes one contiguous slice (a multiple of 64 rays): neighbouring
+  // rays mostly share a job, so the per-wave tallies rarely change owner
+  const uint32_t total_waves = gridDim.x * (uint32_t)wpb;
+  const uint32_t per = ((count + total_waves - 1) / total_waves + 63u) & ~63u;
+  if ((uint64_t)blockIdx.x * wpb * per >= count) return;  // whole workgroup idle
   for (int i = threadIdx.x; i < nY; i += blockDim.x) s_yld[i] = gp(tb.yld)[i];
   for (int i = threadIdx.x; i < tb.ncdf; i += blockDim.x) {
     s_cE[i] = gp(tb.cdfE)[i];
@@ -698,8 +702,9 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   wt.eh = s_eh + w * a.n_ebins;
   wt.ah = s_ah + w * a.n_abins;
   int tag = -1;
-  const uint32_t stride = gridDim.x * (uint32_t)blockDim.x;
-  for (uint32_t base = (blockIdx.x * wpb + w) * 64u; base < count; base += stride) {
+  const uint64_t seg0 = (uint64_t)(blockIdx.x * wpb + w) * per;
+  const uint32_t seg1 = (uint32_t)min((uint64_t)count, seg0 + per);
+  for (uint32_t base = (uint32_t)min(seg0, (uint64_t)count); base < seg1; base += 64u) {
     const uint32_t item = base + lane;
     const bool active = item < count;
 

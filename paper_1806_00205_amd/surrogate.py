@@ -1,0 +1,218 @@
+"""Learned yield surrogate: data from RTMC, training and evaluation.
+
+The surrogate maps eight inputs -- foam porosity, surface-to-volume ratio,
+mean and variance of the surface mean curvature, mean and standard deviation
+of the void chord length, ln E and cos(theta) -- to the secondary electron
+yield.  Its training targets are yields traced by the library itself
+(rtmc_trace_batch); its forward and backward passes and AdamW updates run in
+the library's BF16 matrix-core kernels (rtmc_srg_*).  Plain RTMC stays the
+reference: it judges the surrogate on held-out foams and is the fallback for
+inputs outside the training support.
+
+Command line: ``python -m paper_1806_00205_amd.surrogate --out results.json``.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+
+import numpy as np
+
+import foamgen as fg
+from foamgen.descriptors import foam_descriptors
+
+GRID_E = [50.0, 100.0, 250.0, 500.0, 1000.0]
+GRID_THETA = [0.0, 20.0, 40.0, 60.0, 80.0]
+
+
+def make_foam(seed: int, rng: np.random.Generator, sizes=(40, 48, 56)):
+    """One foam of the batched-workload family: porosity ~ U[0.2, 0.8]."""
+    n = int(rng.choice(sizes))
+    p = float(rng.uniform(0.2, 0.8))
+    field, tau = fg.foam_field(n, p, 2.0, seed=seed)
+    mesh = fg.make_grf_foam(n, p, 2.0, seed=seed)
+    return mesh, foam_descriptors(mesh, field, tau)
+
+
+def features(desc, E, theta_deg):
+    """Rows of the eight surrogate inputs (unnormalised)."""
+    desc = np.atleast_2d(desc)
+    E = np.asarray(E, dtype=np.float64).reshape(-1)
+    th = np.asarray(theta_deg, dtype=np.float64).reshape(-1)
+    return np.concatenate([desc, np.log(E)[:, None], np.cos(np.deg2rad(th))[:, None]], axis=1)
+
+
+def rtmc_yields(ctx, table, jobs, max_gen=6, batch=4096):
+    """Yields of (scene, E, theta, n, seed) jobs through the batched graph path."""
+    out = []
+    for i in range(0, len(jobs), batch):
+        out.extend(ctx.trace_batch(table, jobs[i:i + batch], max_gen=max_gen))
+    return np.array([r["yield"] for r in out]), np.array([r["yield_sigma"] for r in out]), out
+
+
+class Surrogate:
+    """Normalisation + the library's MLP; RTMC fallback outside the training support."""
+
+    def __init__(self, ctx, seed: int = 0):
+        self.ctx = ctx
+        self.id = ctx.srg_create(8, 256, 4, seed=seed)
+        self.mu = None
+        self.sd = None
+        self.lo = None
+        self.hi = None
+
+    def _norm(self, F):
+        return ((F - self.mu) / self.sd).astype(np.float32)
+
+    def fit(self, F, y, steps=4000, batch=1024, lr=2e-3, weight_decay=1e-5, seed=0, log=None):
+        import torch
+
+        self.mu = F.mean(axis=0)
+        self.sd = F.std(axis=0) + 1e-12
+        self.lo = F.min(axis=0)
+        self.hi = F.max(axis=0)
+        Xd = torch.tensor(self._norm(F), device=f"cuda:{self.ctx.device}")
+        yd = torch.tensor(np.asarray(y, dtype=np.float32), device=Xd.device)
+        g = torch.Generator(device=Xd.device).manual_seed(seed)
+        n = Xd.shape[0]
+        losses = []
+        for it in range(steps):
+            frac = it / max(steps - 1, 1)
+            lr_it = lr * (0.02 + 0.49 * (1.0 + math.cos(math.pi * frac)))  # cosine decay to 2 %
+            idx = torch.randint(0, n, (batch,), device=Xd.device, generator=g)
+            loss = self.ctx.srg_train_step(self.id, Xd[idx].contiguous(), yd[idx].contiguous(), lr=lr_it,
+                                           weight_decay=weight_decay)
+            if it % 200 == 0 or it == steps - 1:
+                losses.append((it, loss))
+                if log:
+                    log(f"step {it}: loss {loss:.3e}")
+        return losses
+
+    def predict(self, F):
+        import torch
+
+        Xd = torch.tensor(self._norm(np.asarray(F, dtype=np.float64)), device=f"cuda:{self.ctx.device}")
+        return self.ctx.srg_predict(self.id, Xd).cpu().numpy().astype(np.float64)
+
+    def in_support(self, F, margin=0.05):
+        span = self.hi - self.lo
+        F = np.atleast_2d(F)
+        return np.all((F >= self.lo - margin * span) & (F <= self.hi + margin * span), axis=1)
+
+    def predict_or_trace(self, F, fallback):
+        """Surrogate where the inputs lie in the training support, else fallback(row index)."""
+        F = np.atleast_2d(F)
+        y = self.predict(F)
+        ok = self.in_support(F)
+        for i in np.nonzero(~ok)[0]:
+            y[i] = fallback(int(i))
+        return y, ok
+
+
+def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primaries=20000,
+                   judge_primaries=100000, steps=4000, seed=0, log=print):
+    """Train on RTMC yields of n_train foams, judge on n_test held-out foams."""
+    rng = np.random.default_rng(seed)
+    tab = fg.make_tables("vaughan")
+    tid = ctx.load_tables(tab)
+    t0 = time.time()
+    train_desc, train_jobs = [], []
+    for i in range(n_train):
+        mesh, d = make_foam(10000 + i, rng)
+        sid = ctx.load_scene(mesh)
+        E = np.exp(rng.uniform(np.log(50.0), np.log(1000.0), size=points_per_foam))
+        th = rng.uniform(0.0, 80.0, size=points_per_foam)
+        for e, t in zip(E, th):
+            train_jobs.append((sid, float(e), float(t), train_primaries, int(rng.integers(1, 2 ** 62))))
+            train_desc.append((d, e, t))
+    t_gen = time.time() - t0
+    log(f"[srg] {n_train} training foams generated in {t_gen:.1f} s")
+    t0 = time.time()
+    y_train, s_train, res = rtmc_yields(ctx, tid, train_jobs)
+    t_rtmc = time.time() - t0
+    prim = sum(r["n_primaries"] for r in res)
+    log(f"[srg] {len(train_jobs)} training yields traced in {t_rtmc:.2f} s ({prim / t_rtmc:.3g} primaries/s)")
+    F_train = features(np.array([d for d, _, _ in train_desc]), [e for _, e, _ in train_desc],
+                       [t for _, _, t in train_desc])
+    model = Surrogate(ctx, seed=seed)
+    t0 = time.time()
+    losses = model.fit(F_train, y_train, steps=steps, seed=seed, log=log)
+    t_train = time.time() - t0
+    log(f"[srg] trained {steps} steps in {t_train:.2f} s")
+
+    # held-out foams judged by RTMC on the 5 x 5 grid
+    test_desc, test_jobs, test_grid = [], [], []
+    for i in range(n_test):
+        mesh, d = make_foam(90000 + i, rng)
+        sid = ctx.load_scene(mesh)
+        test_grid.append(mesh.meta["n"])
+        for e in GRID_E:
+            for t in GRID_THETA:
+                test_jobs.append((sid, e, t, judge_primaries, int(rng.integers(1, 2 ** 62))))
+                test_desc.append((d, e, t))
+    t0 = time.time()
+    y_test, s_test, res_t = rtmc_yields(ctx, tid, test_jobs)
+    t_judge = time.time() - t0
+    prim_t = sum(r["n_primaries"] for r in res_t)
+    F_test = features(np.array([d for d, _, _ in test_desc]), [e for _, e, _ in test_desc],
+                      [t for _, _, t in test_desc])
+    y_hat = model.predict(F_test)
+    err = np.abs(y_hat - y_test)
+    ok = model.in_support(F_test)
+    # timing of one million surrogate queries
+    Fq = np.repeat(F_test, int(math.ceil(1e6 / len(F_test))), axis=0)[:1_000_000]
+    import torch
+
+    Xq = torch.tensor(model._norm(Fq), device=f"cuda:{ctx.device}")
+    ctx.srg_predict(model.id, Xq)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.srg_predict(model.id, Xq)
+    torch.cuda.synchronize()
+    t_q = time.perf_counter() - t0
+    # RTMC cost of one yield at the surrogate's error: primaries for sigma = MAE
+    sd_pp = float(np.median(s_test * math.sqrt(judge_primaries)))
+    mae = float(err.mean())
+    n_matched = (sd_pp / mae) ** 2
+    rtmc_rate = prim_t / t_judge
+    rtmc_yield_s = rtmc_rate / n_matched
+    out = {
+        "n_train_foams": n_train, "train_yields": len(train_jobs), "train_primaries_per_yield": train_primaries,
+        "n_test_foams": n_test, "test_points": len(test_jobs), "judge_primaries_per_yield": judge_primaries,
+        "mae": mae, "p95_abs_err": float(np.quantile(err, 0.95)), "max_abs_err": float(err.max()),
+        "mae_in_support": float(err[ok].mean()) if ok.any() else None, "in_support_frac": float(ok.mean()),
+        "judge_sigma_median": float(np.median(s_test)),
+        "mae_by_grid": {str(n): float(err[np.repeat(np.array(test_grid) == n, 25)].mean())
+                        for n in sorted(set(test_grid))},
+        "final_loss": losses[-1][1], "train_seconds": t_train, "gen_seconds": t_gen,
+        "surrogate_queries_per_s": 1e6 / t_q, "rtmc_primaries_per_s": rtmc_rate,
+        "rtmc_primaries_for_matched_error": n_matched, "rtmc_yields_per_s_matched_error": rtmc_yield_s,
+        "gain": (1e6 / t_q) / rtmc_yield_s,
+    }
+    return out, model
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--train-foams", type=int, default=256)
+    ap.add_argument("--points", type=int, default=64)
+    ap.add_argument("--test-foams", type=int, default=64)
+    ap.add_argument("--steps", type=int, default=4000)
+    args = ap.parse_args()
+    import paper_1806_00205_amd as rt
+
+    ctx = rt.Context(0)
+    res, _ = run_experiment(ctx, n_train=args.train_foams, points_per_foam=args.points, n_test=args.test_foams,
+                            steps=args.steps)
+    print(json.dumps(res))
+    if args.out:
+        with open(args.out, "w") as f:
+            json.dump(res, f, indent=1)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
