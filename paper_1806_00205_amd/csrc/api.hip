@@ -76,6 +76,9 @@ struct rtmc_ctx {
   DevBuf counters, ppc, err_word, jobs, tally;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> kev;  // per-launch timing events (eager traces)
+  // last instantiated batch graph and the signature it was captured for
+  hipGraphExec_t gexec = nullptr;
+  std::vector<uint64_t> gkey;
 };
 
 namespace {
@@ -192,6 +195,45 @@ HitRecs hit_recs(void* base, size_t cap) {
 
 constexpr int kShadeBlock = 256;
 
+// One chunk of the batch: primaries [lo, lo + n) of the concatenated jobs,
+// which lie in jobs j_lo..j_hi.
+struct ChunkPlan {
+  uint64_t lo;
+  uint32_t n;
+  int32_t j_lo, j_hi;
+};
+
+// Cut the concatenated primaries into chunks of at most `chunk`.  A chunk is
+// also closed before it would span more than kShadeJobs jobs, once it holds a
+// quarter of `chunk`: shading then keeps every job's tallies in LDS, while
+// batches of many small jobs still get chunks large enough to fill the device.
+std::vector<ChunkPlan> plan_chunks(const std::vector<HostJob>& jobs, uint32_t chunk) {
+  std::vector<ChunkPlan> out;
+  ChunkPlan cur{0, 0, -1, -1};
+  uint64_t g = 0;
+  const uint32_t min_fill = std::max<uint32_t>(1u, chunk / 4);
+  for (int32_t j = 0; j < (int32_t)jobs.size(); ++j) {
+    uint64_t left = jobs[j].n;
+    while (left > 0) {
+      if (cur.n > 0 && (cur.n == chunk || (j - cur.j_lo + 1 > kShadeJobs && cur.n >= min_fill))) {
+        out.push_back(cur);
+        cur = ChunkPlan{g, 0, -1, -1};
+      }
+      if (cur.n == 0) {
+        cur.lo = g;
+        cur.j_lo = j;
+      }
+      const uint32_t take = (uint32_t)std::min<uint64_t>(left, (uint64_t)(chunk - cur.n));
+      cur.n += take;
+      cur.j_hi = j;
+      left -= take;
+      g += take;
+    }
+  }
+  if (cur.n > 0) out.push_back(cur);
+  return out;
+}
+
 // Enqueue the launch sequence of a batch of jobs with a given chunk size:
 // per chunk and generation, traversal then shading.
 rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJob>& jobs, int max_gen,
@@ -200,7 +242,9 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   const int block = cfg.block;
   const int grid = grid_of(c, cfg);
   const int sgrid = c->n_cu * 4;
-  const uint64_t n_chunks = (total + chunk - 1) / chunk;
+  const std::vector<ChunkPlan> plan = plan_chunks(jobs, chunk);
+  const uint64_t n_chunks = plan.size();
+  (void)total;
   const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins;
   const int ncnt = 2 * (kMaxGen + 2);
   int gdepth = kGlobalStack;
@@ -264,11 +308,14 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
     return c->kev[k];
   };
   for (uint64_t ch = 0; ch < n_chunks; ++ch) {
-    const uint64_t lo = ch * chunk;
-    const uint32_t n_here = (uint32_t)std::min<uint64_t>(chunk, total - lo);
+    const uint64_t lo = plan[ch].lo;
+    const uint32_t n_here = plan[ch].n;
     uint32_t* cnt = reinterpret_cast<uint32_t*>(c->counters.p) + ch * ncnt;
+    const int32_t j_lo = plan[ch].j_lo, j_hi = plan[ch].j_hi;
     HIPCHK(c, launch_fill_u32(sa.ppc, 0u, n_here, s));
-    HIPCHK(c, launch_primaries(ta.jobs, ta.n_jobs, lo, n_here, q[0], s));
+    HIPCHK(c, launch_primaries(ta.jobs, j_lo, j_hi, lo, n_here, q[0], s));
+    sa.j_lo = j_lo;
+    sa.j_hi = j_hi;
     ta.chunk_lo = sa.chunk_lo = lo;
     sa.n_gen0 = n_here;
     for (int g = 0; g <= max_gen; ++g) {
@@ -298,7 +345,7 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
       }
       ++*n_launch;
     }
-    HIPCHK(c, launch_chunk_reduce(ta.jobs, ta.n_jobs, sa.ppc, n_here, lo, s));
+    HIPCHK(c, launch_chunk_reduce(ta.jobs, j_lo, j_hi, sa.ppc, n_here, lo, s));
   }
   return RTMC_OK;
 }
@@ -340,7 +387,7 @@ rtmc_status prepare_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
     if (st) return st;
     c->qcap = (uint32_t)need_q;
   }
-  const uint64_t n_chunks = (g + chunk - 1) / chunk;
+  const uint64_t n_chunks = plan_chunks(jobs, chunk).size();
   st = ensure(c, c->counters, (size_t)n_chunks * 2 * (kMaxGen + 2) * 4 + 16);
   if (st) return st;
   st = ensure(c, c->ppc, (size_t)chunk * 4);
@@ -365,7 +412,7 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
     rtmc_status st = prepare_trace(c, tb, jobs, n_ebins, n_abins, cfg, &total);
     if (st) return st;
     const size_t lds_t = traverse_lds_bytes(cfg.lds_stack, cfg.block);
-    const size_t lds_s = shade_lds_bytes(dev_tables(tb), n_ebins, n_abins, kShadeBlock);
+    const size_t lds_s = shade_lds_bytes(dev_tables(tb), n_ebins, n_abins, kShadeBlock, kShadeJobs);
     if (lds_t > c->lds_per_block || lds_s > c->lds_per_block)
       return fail(c, RTMC_EINVAL, "launch needs %zu / %zu bytes of LDS per workgroup (device limit %zu)", lds_t,
                   lds_s, c->lds_per_block);
@@ -373,27 +420,52 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
     if (use_graph) {
       HIPCHK(c, hipEventRecord(c->ev0, c->stream));
       HIPCHK(c, hipStreamWaitEvent(c->gstream, c->ev0, 0));
-      hipGraph_t graph = nullptr;
-      HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+      // The graph depends on the launch sequence (sizes, shapes) and on the
+      // device buffers it names, not on the job table's contents, which are
+      // uploaded to the same buffer before every launch.
+      std::vector<uint64_t> key = {(uint64_t)jobs.size(), total, (uint64_t)max_gen, (uint64_t)n_ebins,
+                                   (uint64_t)n_abins, (uint64_t)cfg.block, (uint64_t)cfg.wg_per_cu,
+                                   (uint64_t)cfg.lds_stack, (uint64_t)cfg.chunk, (uint64_t)cfg.refill,
+                                   (uint64_t)cfg.occupancy, (uint64_t)table_id, (uint64_t)(uintptr_t)c->jobs.p,
+                                   (uint64_t)(uintptr_t)c->tally.p, (uint64_t)(uintptr_t)c->queue[0].p,
+                                   (uint64_t)(uintptr_t)c->queue[1].p, (uint64_t)(uintptr_t)c->hits.p,
+                                   (uint64_t)(uintptr_t)c->counters.p, (uint64_t)(uintptr_t)c->ppc.p,
+                                   (uint64_t)(uintptr_t)c->gstack.p, (uint64_t)(uintptr_t)c->err_word.p, c->qcap};
+      int gd = kGlobalStack;
+      for (auto& j : jobs) gd = std::max(gd, c->scenes[j.scene].depth + 2);
+      key.push_back((uint64_t)gd);
+      bool multi = jobs.size() > 1;
+      key.push_back(multi ? 1u : 0u);
+      // the per-job primary counts fix each chunk's job range, baked into the launches
+      for (auto& j : jobs) key.push_back(j.n);
       uint64_t nl = 0;
-      st = enqueue_trace(c, tb, jobs, max_gen, n_ebins, n_abins, cfg, (uint32_t)cfg.chunk, s, total, false, &nl);
-      hipError_t ce = hipStreamEndCapture(s, &graph);
+      if (!c->gexec || key != c->gkey) {
+        if (c->gexec) {
+          (void)hipGraphExecDestroy(c->gexec);
+          c->gexec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        st = enqueue_trace(c, tb, jobs, max_gen, n_ebins, n_abins, cfg, (uint32_t)cfg.chunk, s, total, false, &nl);
+        hipError_t ce = hipStreamEndCapture(s, &graph);
+        if (st) {
+          if (graph) (void)hipGraphDestroy(graph);
+          return st;
+        }
+        HIPCHK(c, ce);
+        hipError_t ie = hipGraphInstantiate(&c->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        HIPCHK(c, ie);
+        c->gkey = key;
+      } else {
+        nl = (uint64_t)plan_chunks(jobs, (uint32_t)cfg.chunk).size() * (uint64_t)(max_gen + 1);
+      }
       out.launches = nl;
       out.kernel_ms = 0.0;
-      if (st) {
-        if (graph) (void)hipGraphDestroy(graph);
-        return st;
-      }
-      HIPCHK(c, ce);
-      hipGraphExec_t exec = nullptr;
-      hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-      (void)hipGraphDestroy(graph);
-      HIPCHK(c, ie);
       HIPCHK(c, hipEventRecord(c->ev0, s));
-      hipError_t le = hipGraphLaunch(exec, s);
+      hipError_t le = hipGraphLaunch(c->gexec, s);
       HIPCHK(c, hipEventRecord(c->ev1, s));
       hipError_t se = hipStreamSynchronize(s);
-      (void)hipGraphExecDestroy(exec);
       HIPCHK(c, le);
       HIPCHK(c, se);
     } else {
@@ -429,9 +501,7 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
     out.tally.resize(tw * jobs.size());
     HIPCHK(c, hipMemcpy(out.tally.data(), c->tally.p, out.tally.size() * 8, hipMemcpyDeviceToHost));
     out.ms = ms;
-    uint64_t total_n = 0;
-    for (auto& j : jobs) total_n += j.n;
-    out.n_chunks = (int)((total_n + cfg.chunk - 1) / cfg.chunk);
+    out.n_chunks = (int)plan_chunks(jobs, (uint32_t)cfg.chunk).size();
     (void)attempt;
     return RTMC_OK;
   }
@@ -535,6 +605,7 @@ void rtmc_destroy(rtmc_ctx* c) {
   dev_free(c, c->tally);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   for (auto e : c->kev) (void)hipEventDestroy(e);
   if (c->gstream) (void)hipStreamDestroy(c->gstream);
   delete c;

@@ -223,8 +223,8 @@ __device__ inline void onb(float nx, float ny, float nz, float3& t1, float3& t2)
   t2 = make_float3(b, sign + ny * ny * a, -ny);
 }
 
-__device__ inline int find_job(const DevJob* jobs, int n, uint64_t g) {
-  int lo = 0, hi = n - 1;
+// Job of concatenated primary index g among jobs [lo, hi] (sorted by gbase).
+__device__ inline int find_job(const DevJob* jobs, int lo, int hi, uint64_t g) {
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
     if (gp(jobs)[mid].gbase <= g)
@@ -256,13 +256,33 @@ __device__ inline void gadd(unsigned long long* g, unsigned long long v) {
 
 template <typename T>
 __device__ inline void ladd(LAS T* p, T v) {
-  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+  __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// slot is a compile-time constant at every call site
-__device__ inline void tally_cnt(bool mine, WaveTally& wt, unsigned long long* g, int slot, unsigned long long v) {
+// Workgroup-wide LDS tally blocks, one per job of the chunk (when few enough):
+// [T_NCOUNT u64 counters][n_ebins u32][n_abins u32] per job.
+struct JobTab {
+  LAS unsigned char* base;
+  int stride, n_eb, n_ab, j_lo, J;
+};
+
+__device__ inline LAS unsigned long long* jt_cnt(const JobTab& t, int job) {
+  return (LAS unsigned long long*)(t.base + (size_t)(job - t.j_lo) * t.stride);
+}
+__device__ inline LAS uint32_t* jt_eh(const JobTab& t, int job) {
+  return (LAS uint32_t*)(t.base + (size_t)(job - t.j_lo) * t.stride + T_NCOUNT * 8);
+}
+
+// slot is a compile-time constant at every call site.  A lane whose ray belongs
+// to another job than its wave's tally adds directly: to that job's LDS block
+// when the workgroup keeps one per job (jt), else to global memory.
+__device__ inline void tally_cnt(bool mine, WaveTally& wt, unsigned long long* g, int slot, unsigned long long v,
+                                 const JobTab* jt, int job) {
   if (!mine) {
-    gadd(g + slot, v);
+    if (jt)
+      ladd(jt_cnt(*jt, job) + slot, v);
+    else
+      gadd(g + slot, v);
   } else if (slot == T_E_ESC_FX) {
     wt.e_esc += v;
   } else if (slot == T_E_DEP_FX) {
@@ -276,6 +296,23 @@ __device__ inline unsigned long long wave_sum(unsigned long long v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
+}
+
+__device__ inline void flush_wave_lds(WaveTally& wt, LAS unsigned long long* cnt, uint32_t lane) {
+#pragma unroll
+  for (int k = 0; k < T_NCOUNT; ++k) {
+    if (k == T_E_ESC_FX || k == T_E_DEP_FX || k == T_C2 || k == T_SPARE) continue;
+    const unsigned long long v = wave_sum((unsigned long long)wt.c[k]);
+    if (lane == 0 && v) ladd(cnt + k, v);
+    wt.c[k] = 0u;
+  }
+  const unsigned long long ee = wave_sum(wt.e_esc), ed = wave_sum(wt.e_dep);
+  if (lane == 0) {
+    if (ee) ladd(cnt + T_E_ESC_FX, ee);
+    if (ed) ladd(cnt + T_E_DEP_FX, ed);
+  }
+  wt.e_esc = 0ull;
+  wt.e_dep = 0ull;
 }
 
 __device__ inline void flush_wave(WaveTally& wt, unsigned long long* g, int n_eb, int n_ab, uint32_t lane) {
@@ -630,11 +667,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(8, 8))) voi
 
 // Primary rays of one chunk, written to the queue so that both launches of
 // generation 0 read them like any other generation.
-__global__ void k_primaries(const DevJob* __restrict__ jobs, int32_t n_jobs, uint64_t chunk_lo, uint32_t n,
-                            RayQueue q) {
+__global__ void k_primaries(const DevJob* __restrict__ jobs, int32_t j_lo, int32_t j_hi, uint64_t chunk_lo,
+                            uint32_t n, RayQueue q) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
     const uint64_t g = chunk_lo + i;
-    const int job = find_job(jobs, n_jobs, g);
+    const int job = find_job(jobs, j_lo, j_hi, g);
     float ox, oy, oz, dx, dy, dz;
     primary_ray(jobs[job], g, ox, oy, oz, dx, dy, dz);
     gp(q.ox)[i] = ox;
@@ -676,8 +713,16 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   LAS float* s_cF = s_cE + tb.ncdf;
   size_t off = ((size_t)(nY + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
   LAS uint32_t* s_eh = (LAS uint32_t*)(lds + off);
-  off += (size_t)wpb * a.n_ebins * 4;
-  LAS uint32_t* s_ah = (LAS uint32_t*)(lds + off);
+  LAS uint32_t* s_ah = s_eh + wpb * a.n_ebins;
+  JobTab jtab;
+  jtab.base = lds + off;
+  jtab.stride = (T_NCOUNT * 8 + (a.n_ebins + a.n_abins) * 4 + 7) & ~7;
+  jtab.n_eb = a.n_ebins;
+  jtab.n_ab = a.n_abins;
+  jtab.j_lo = a.j_lo;
+  jtab.J = a.j_hi - a.j_lo + 1;
+  const bool shared = jtab.J <= kShadeJobs;
+  const JobTab* jt = shared ? &jtab : nullptr;
 
   const uint32_t count = a.gen == 0 ? a.n_gen0 : min(*gp(a.count_in), a.qcap);  // queue length
   // each wave takes one contiguous slice (a multiple of 64 rays): neighbouring
@@ -690,8 +735,13 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     s_cE[i] = gp(tb.cdfE)[i];
     s_cF[i] = gp(tb.cdfF)[i];
   }
-  for (int i = threadIdx.x; i < wpb * a.n_ebins; i += blockDim.x) s_eh[i] = 0u;
-  for (int i = threadIdx.x; i < wpb * a.n_abins; i += blockDim.x) s_ah[i] = 0u;
+  if (shared) {
+    const int words = jtab.J * jtab.stride / 4;
+    for (int i = threadIdx.x; i < words; i += blockDim.x) ((LAS uint32_t*)jtab.base)[i] = 0u;
+  } else {
+    for (int i = threadIdx.x; i < wpb * a.n_ebins; i += blockDim.x) s_eh[i] = 0u;
+    for (int i = threadIdx.x; i < wpb * a.n_abins; i += blockDim.x) s_ah[i] = 0u;
+  }
   __syncthreads();
 
   WaveTally wt;
@@ -729,7 +779,12 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     (void)oz;
     const int j0 = __shfl(job, 0, 64);
     if (j0 != tag) {
-      if (tag >= 0) flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, lane);
+      if (tag >= 0) {
+        if (shared)
+          flush_wave_lds(wt, jt_cnt(jtab, tag), lane);
+        else
+          flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, lane);
+      }
       tag = j0;
     }
     const DevJob& J = a.jobs[job];
@@ -742,20 +797,24 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
       const int32_t code = gp(a.hit.code)[item];
       const float f0 = gp(a.hit.f0)[item], f1 = gp(a.hit.f1)[item];
       const uint32_t wr = gp(a.hit.wraps)[item];
-      tally_cnt(mine, wt, gt, T_RAYS, 1ull);
-      tally_cnt(mine, wt, gt, T_VISITS, gp(a.hit.visits)[item]);
-      tally_cnt(mine, wt, gt, T_TESTS, gp(a.hit.tests)[item]);
-      if (wr & 0x7fffffffu) tally_cnt(mine, wt, gt, T_WRAPS, (unsigned long long)(wr & 0x7fffffffu));
-      if (wr & 0x80000000u) tally_cnt(mine, wt, gt, T_STACKOVF, 1ull);
+      tally_cnt(mine, wt, gt, T_RAYS, 1ull, jt, job);
+      tally_cnt(mine, wt, gt, T_VISITS, gp(a.hit.visits)[item], jt, job);
+      tally_cnt(mine, wt, gt, T_TESTS, gp(a.hit.tests)[item], jt, job);
+      if (wr & 0x7fffffffu) tally_cnt(mine, wt, gt, T_WRAPS, (unsigned long long)(wr & 0x7fffffffu), jt, job);
+      if (wr & 0x80000000u) tally_cnt(mine, wt, gt, T_STACKOVF, 1ull, jt, job);
       if (code == -1) {
-        tally_cnt(mine, wt, gt, T_ESCAPED, 1ull);
-        tally_cnt(mine, wt, gt, T_E_ESC_FX, (unsigned long long)to_fx(E));
+        tally_cnt(mine, wt, gt, T_ESCAPED, 1ull, jt, job);
+        tally_cnt(mine, wt, gt, T_E_ESC_FX, (unsigned long long)to_fx(E), jt, job);
         int eb = (int)floorf(E / J.E0 * (float)a.n_ebins);
         eb = min(max(eb, 0), a.n_ebins - 1);
         const float pol = acosf(fminf(dz, 1.0f)) * kDeg;
         int ab = (int)floorf(pol * (1.0f / 90.0f) * (float)a.n_abins);
         ab = min(max(ab, 0), a.n_abins - 1);
-        if (mine) {
+        if (shared) {
+          LAS uint32_t* h = jt_eh(jtab, job);
+          ladd(h + eb, 1u);
+          ladd(h + a.n_ebins + ab, 1u);
+        } else if (mine) {
           ladd(wt.eh + eb, 1u);
           ladd(wt.ah + ab, 1u);
         } else {
@@ -764,11 +823,11 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
         }
         __hip_atomic_fetch_add(gp(a.ppc) + ci, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       } else if (code == -3) {
-        tally_cnt(mine, wt, gt, T_LOST, 1ull);
-        tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E));
+        tally_cnt(mine, wt, gt, T_LOST, 1ull, jt, job);
+        tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E), jt, job);
       } else {
         if (code == -2) {
-          tally_cnt(mine, wt, gt, T_SUBSTRATE, 1ull);
+          tally_cnt(mine, wt, gt, T_SUBSTRATE, 1ull, jt, job);
           px = f0;
           py = f1;
           pz = J.sc.lo[2];
@@ -799,12 +858,12 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
           }
         }
         if (gen >= a.max_gen) {
-          tally_cnt(mine, wt, gt, T_TRUNCATED, 1ull);
-          tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E));
+          tally_cnt(mine, wt, gt, T_TRUNCATED, 1ull, jt, job);
+          tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E), jt, job);
         } else {
-          tally_cnt(mine, wt, gt, T_ABSORBED, 1ull);
+          tally_cnt(mine, wt, gt, T_ABSORBED, 1ull, jt, job);
           if (E <= tb.Ec) {
-            tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E));
+            tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E), jt, job);
           } else {
             const float cosa = fminf(fmaxf(-(dx * nx + dy * ny + dz * nz), 0.0f), 1.0f);
             const float alpha = acosf(cosa) * kDeg;
@@ -813,7 +872,7 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
             const U4 u = philox(J.seed, (uint32_t)pid, (uint32_t)(pid >> 32), path, 1u);
             const float fl = floorf(delta);
             nd = (int)fl + (u01(u.x) < delta - fl ? 1 : 0);
-            if (nd == 0) tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E));
+            if (nd == 0) tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E), jt, job);
           }
         }
       }
@@ -873,45 +932,76 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
           ++dropped;
         }
       }
-      tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)fx_left);
-      tally_cnt(mine, wt, gt, T_SPAWNED, (unsigned long long)nd);
+      tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)fx_left, jt, job);
+      tally_cnt(mine, wt, gt, T_SPAWNED, (unsigned long long)nd, jt, job);
       if (dropped) {
-        tally_cnt(mine, wt, gt, T_DROPPED, dropped);
+        tally_cnt(mine, wt, gt, T_DROPPED, dropped, jt, job);
         atomicOr(a.err, 1u);
       }
     }
   }
-  if (tag >= 0) flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, lane);
+  if (shared) {
+    if (tag >= 0) flush_wave_lds(wt, jt_cnt(jtab, tag), lane);
+    __syncthreads();
+    // the workgroup's job blocks to global memory, nonzero entries only
+    const int slots = T_NCOUNT + a.n_ebins + a.n_abins;
+    for (int i = threadIdx.x; i < jtab.J * slots; i += blockDim.x) {
+      const int j = i / slots, k = i % slots;
+      const LAS unsigned char* blk = jtab.base + (size_t)j * jtab.stride;
+      const unsigned long long v = k < T_NCOUNT
+                                       ? ((const LAS unsigned long long*)blk)[k]
+                                       : (unsigned long long)((const LAS uint32_t*)(blk + T_NCOUNT * 8))[k - T_NCOUNT];
+      if (v) gadd(a.jobs[jtab.j_lo + j].tally + k, v);
+    }
+  } else if (tag >= 0) {
+    flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, lane);
+  }
 }
 
 // Sum over the chunk's primaries of (escape count)^2 for the yield's standard
-// error, and the optional per-primary output.  Each thread accumulates its
-// grid-stride items and the wave reduces once at the end.
-__global__ void k_chunk_reduce(const DevJob* jobs, int32_t n_jobs, const uint32_t* __restrict__ ppc, uint32_t n,
-                               uint64_t chunk_lo) {
+// error, and the optional per-primary output.  Each wave takes a contiguous
+// slice of the chunk, so its items change job rarely: lanes accumulate in
+// registers and the wave reduces once per job it touches.
+__global__ void k_chunk_reduce(const DevJob* jobs, int32_t j_lo, int32_t j_hi, const uint32_t* __restrict__ ppc,
+                               uint32_t n, uint64_t chunk_lo) {
   const uint32_t lane = lane_id();
-  const uint32_t stride = gridDim.x * blockDim.x;
-  int job = -1;
+  const uint32_t wpb = blockDim.x >> 6;
+  const uint32_t total_waves = gridDim.x * wpb;
+  const uint64_t per = (((uint64_t)n + total_waves - 1) / total_waves + 63) & ~63ull;
+  const uint64_t b = (uint64_t)(blockIdx.x * wpb + (threadIdx.x >> 6)) * per;
+  if (b >= n) return;
+  const uint32_t e = (uint32_t)(b + per < n ? b + per : n);
+  int tag = find_job(jobs, j_lo, j_hi, chunk_lo + b);
+  uint64_t end = tag < j_hi ? gp(jobs)[tag + 1].gbase : ~0ull;
   unsigned long long acc = 0;
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+  for (uint32_t i0 = (uint32_t)b; i0 < e; i0 += 64) {
+    const uint32_t i = i0 + lane;
+    const bool ok = i < e;
     const uint64_t g = chunk_lo + i;
-    const int j = n_jobs == 1 ? 0 : find_job(jobs, n_jobs, g);
-    if (j != job) {
-      if (job >= 0 && acc) gadd(&jobs[job].tally[T_C2], acc);
-      job = j;
+    const uint32_t c = ok ? gp(ppc)[i] : 0u;
+    const uint64_t g_last = chunk_lo + (i0 + 63 < e ? i0 + 63 : e - 1);
+    if (g_last < end) {
+      acc += (unsigned long long)c * c;
+      uint32_t* pp = gp(jobs)[tag].pp_escaped;
+      if (pp && ok) gp(pp)[g - gp(jobs)[tag].gbase] = c;
+    } else {
+      // the wave's items reach into later jobs
+      const int j = ok ? find_job(jobs, tag, j_hi, g) : tag;
+      if (j == tag)
+        acc += (unsigned long long)c * c;
+      else if (c)
+        gadd(&jobs[j].tally[T_C2], (unsigned long long)c * c);
+      uint32_t* pp = gp(jobs)[j].pp_escaped;
+      if (pp && ok) gp(pp)[g - gp(jobs)[j].gbase] = c;
+      const unsigned long long sum = wave_sum(acc);
+      if (lane == 0 && sum) gadd(&jobs[tag].tally[T_C2], sum);
       acc = 0;
+      tag = find_job(jobs, tag, j_hi, g_last);
+      end = tag < j_hi ? gp(jobs)[tag + 1].gbase : ~0ull;
     }
-    const uint32_t c = gp(ppc)[i];
-    acc += (unsigned long long)c * c;
-    if (jobs[j].pp_escaped) gp(jobs[j].pp_escaped)[g - jobs[j].gbase] = c;
   }
-  const int j0 = __shfl(job, 0, 64);
-  if (__all(job == j0)) {
-    const unsigned long long sum = wave_sum(acc);
-    if (lane == 0 && j0 >= 0 && sum) gadd(&jobs[j0].tally[T_C2], sum);
-  } else if (job >= 0 && acc) {
-    gadd(&jobs[job].tally[T_C2], acc);
-  }
+  const unsigned long long sum = wave_sum(acc);
+  if (lane == 0 && sum) gadd(&jobs[tag].tally[T_C2], sum);
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
@@ -948,12 +1038,14 @@ __global__ __launch_bounds__(256) void k_copy_probe(float4* __restrict__ dst4, c
 
 size_t traverse_lds_bytes(int lds_stack, int block) { return (size_t)(block / 64) * lds_stack * 64 * 4; }
 
-size_t shade_lds_bytes(const DevTables& tb, int n_ebins, int n_abins, int block) {
+size_t shade_lds_bytes(const DevTables& tb, int n_ebins, int n_abins, int block, int n_jobs) {
   const int wpb = block / 64;
   size_t off = ((size_t)(tb.nE * tb.nth + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
-  off += (size_t)wpb * n_ebins * 4;
-  off += (size_t)wpb * n_abins * 4;
-  return off;
+  const size_t per_wave = (size_t)wpb * (n_ebins + n_abins) * 4;
+  const size_t per_job = n_jobs <= kShadeJobs
+                             ? (size_t)n_jobs * ((T_NCOUNT * 8 + (n_ebins + n_abins) * 4 + 7) & ~7)
+                             : 0;
+  return off + (per_wave > per_job ? per_wave : per_job);
 }
 
 hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int grid, int block, hipStream_t s) {
@@ -973,17 +1065,17 @@ hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int
 }
 
 hipError_t launch_shade(const ShadeArgs& a, int grid, int block, hipStream_t s) {
-  const size_t lds = shade_lds_bytes(a.tb, a.n_ebins, a.n_abins, block);
+  const size_t lds = shade_lds_bytes(a.tb, a.n_ebins, a.n_abins, block, a.j_hi - a.j_lo + 1);
   k_shade<<<grid, block, lds, s>>>(a);
   return hipGetLastError();
 }
 
-hipError_t launch_primaries(const DevJob* jobs, int32_t n_jobs, uint64_t chunk_lo, uint32_t n, const RayQueue& q,
-                            hipStream_t s) {
+hipError_t launch_primaries(const DevJob* jobs, int32_t j_lo, int32_t j_hi, uint64_t chunk_lo, uint32_t n,
+                            const RayQueue& q, hipStream_t s) {
   if (n == 0) return hipSuccess;
   int grid = (int)((n + 255) / 256);
   if (grid > 16384) grid = 16384;
-  k_primaries<<<grid, 256, 0, s>>>(jobs, n_jobs, chunk_lo, n, q);
+  k_primaries<<<grid, 256, 0, s>>>(jobs, j_lo, j_hi, chunk_lo, n, q);
   return hipGetLastError();
 }
 
@@ -993,12 +1085,12 @@ hipError_t launch_hit_ids(const float4* tris, const int32_t* code, int64_t n, in
   return hipGetLastError();
 }
 
-hipError_t launch_chunk_reduce(const DevJob* jobs, int32_t n_jobs, const uint32_t* ppc, uint32_t n,
+hipError_t launch_chunk_reduce(const DevJob* jobs, int32_t j_lo, int32_t j_hi, const uint32_t* ppc, uint32_t n,
                                uint64_t chunk_lo, hipStream_t s) {
   if (n == 0) return hipSuccess;
   int grid = (int)((n + 255) / 256);
   if (grid > 4096) grid = 4096;
-  k_chunk_reduce<<<grid, 256, 0, s>>>(jobs, n_jobs, ppc, n, chunk_lo);
+  k_chunk_reduce<<<grid, 256, 0, s>>>(jobs, j_lo, j_hi, ppc, n, chunk_lo);
   return hipGetLastError();
 }
 
