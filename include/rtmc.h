@@ -233,6 +233,8 @@ rtmc_status rtmc_copy_probe(rtmc_ctx* ctx, void* dst, const void* src, size_t by
  * Architecture: n_in inputs -> depth hidden layers of width GELU units -> 1
  * output; BF16 operands on the matrix cores with FP32 accumulation; FP32
  * master weights updated with AdamW.  Only width 256 and depth 4 are built.
+ * GELU(z) = z Phi(z) with erf evaluated by Abramowitz-Stegun 7.1.26
+ * (absolute error <= 1.5e-7). 
  * Parameter vector order (FP32): W1 [width x n_in] (row = output unit), b1
  * [width], W2 [width x width], b2, ..., W_depth, b_depth, w_out [width],
  * b_out [1]; rtmc_srg_param_count gives its length.
@@ -249,7 +251,10 @@ rtmc_status rtmc_srg_gradient(rtmc_ctx* ctx, int32_t srg_id, const float* X, con
 /* One AdamW step (beta 0.9 / 0.999, eps 1e-8) on a batch; *loss is the batch loss before the step. */
 rtmc_status rtmc_srg_train_step(rtmc_ctx* ctx, int32_t srg_id, const float* X, const float* y, int64_t batch,
                                 float lr, float weight_decay, float* loss);
-/* Predictions for n rows (any n), written to device float y[n]; asynchronous on the context stream. */
+/* Predictions for n rows (any n), written to device float y[n]; asynchronous on the context stream.
+ * One fused kernel per call: each workgroup runs all layers for 128 rows with
+ * the activations held in LDS (BF16 between layers), so the call allocates
+ * nothing and touches memory only for X, y and the weights. */
 rtmc_status rtmc_srg_predict(rtmc_ctx* ctx, int32_t srg_id, const float* X, int64_t n, float* y);
 
 #ifdef __cplusplus

@@ -1474,15 +1474,22 @@ rtmc_status rtmc_srg_predict(rtmc_ctx* c, int32_t id, const float* X, int64_t n,
   if (n < 0 || (n > 0 && (!X || !y))) return fail(c, RTMC_EINVAL, "bad prediction arrays");
   if (n == 0) return RTMC_OK;
   HIPCHK(c, hipSetDevice(c->device));
-  const int64_t chunk = std::min<int64_t>(n, 1 << 18);
-  st = srg_ensure_ws(c, g, chunk);
-  if (st) return st;
-  const SrgWs w = srg_ws(g, chunk);
-  for (int64_t r0 = 0; r0 < n; r0 += chunk) {
-    const int64_t rows = std::min(chunk, n - r0);
-    st = srg_forward(c, g, X + r0 * g.n_in, rows, false, w, y + r0);
-    if (st) return st;
+  // one fused kernel: activations stay in LDS, no workspace
+  const SrgLayout L = srg_layout(g);
+  const float* m = reinterpret_cast<const float*>(g.master.p);
+  const __bf16* wb = reinterpret_cast<const __bf16*>(g.wbf.p);
+  MlpInfer q{};
+  q.x = X;
+  q.n = n;
+  q.n_in = g.n_in;
+  for (int l = 1; l <= 4; ++l) {
+    q.W[l - 1] = wb + srg_wbf_off(g, l, false);
+    q.bias[l - 1] = m + L.b[l];
   }
+  q.wout = m + L.wout;
+  q.bout = m + L.bout;
+  q.y = y;
+  HIPCHK(c, mlp_infer(q, c->stream));
   return RTMC_OK;
 }
 

@@ -25,10 +25,21 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 __device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
-// GELU with the exact normal CDF, and its derivative
-__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erff(x * 0.70710678118654752f)); }
+// erf by Abramowitz and Stegun 7.1.26 (absolute error <= 1.5e-7): branch
+// free, one reciprocal and one exponential, far below the BF16 rounding the
+// activations then take.
+__device__ inline float erf_as(float x) {
+  const float ax = fabsf(x);
+  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
+  const float poly =
+      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
+  return copysignf(1.0f - poly * __expf(-ax * ax), x);
+}
+
+// GELU with the normal CDF, x Phi(x), and its derivative
+__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
 __device__ inline float gelu_d(float x) {
-  return 0.5f * (1.0f + erff(x * 0.70710678118654752f)) + x * 0.39894228040143268f * expf(-0.5f * x * x);
+  return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
 }
 
 // Workgroup tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA blocks of 16 x 16).
@@ -197,7 +208,131 @@ __global__ void k_to_bf16(const float* __restrict__ W, int rows, int cols, __bf1
   if (Wtb) Wtb[(size_t)c * rows + r] = v;
 }
 
+// ---------------------------------------------------------------- inference
+// All layers of a 128-row tile in one workgroup.  Each of the four waves owns
+// 64 of the 256 output columns for all 128 rows (8 x 4 MFMA blocks, FP32
+// accumulators in registers); the layer's input tile is read from LDS, its
+// weights from memory (L2-resident, each weight read once per workgroup).
+// Between layers the bias + GELU output goes back to the same LDS tile as
+// BF16, so activations never reach HBM: per row the kernel reads n_in floats
+// and writes one.
+constexpr int kInfRows = 128;
+constexpr int kInfLd = 256 + 8;  // bf16 per LDS row; the 16-byte pad spreads row reads over banks
+
+typedef __attribute__((address_space(3))) bf16x8 lds_bf16x8;
+
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_infer(MlpInfer p) {
+  __shared__ __attribute__((aligned(16))) __bf16 act[kInfRows * kInfLd];
+  __shared__ float ypart[4][kInfRows];
+  const int w = threadIdx.x >> 6;
+  const uint32_t l = lane_id();
+  const int r = l & 15, kg = (l >> 4) * 8;
+  const int64_t row0 = (int64_t)blockIdx.x * kInfRows;
+  const int n0 = w * 64;
+  const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+  f32x4 acc[8][4];
+
+  // layer 1: K = 32 (one MFMA step), inputs straight from memory
+  {
+    bf16x8 b[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = *(const GAS bf16x8*)(p.W[0] + (size_t)(n0 + 16 * j + r) * 32 + kg);
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t row = row0 + 16 * i + r;
+      bf16x8 a = {};
+      if (row < p.n) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (kg + e < p.n_in) a[e] = (__bf16)((const GAS float*)p.x)[row * p.n_in + kg + e];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], zero4, 0, 0, 0);
+    }
+  }
+
+#pragma unroll 1
+  for (int layer = 1; layer < 4; ++layer) {
+    // previous layer's output: bias + GELU, BF16, into the LDS tile
+    const float* bias = p.bias[layer - 1];
+    __syncthreads();  // every wave has finished reading the tile
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int col = n0 + 16 * j + r;
+      const float bc = ((const GAS float*)bias)[col];
+#pragma unroll
+      for (int i = 0; i < 8; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) act[(16 * i + 4 * (l >> 4) + q) * kInfLd + col] = (__bf16)gelu(acc[i][j][q] + bc);
+    }
+    __syncthreads();
+    const __bf16* W = p.W[layer];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = zero4;
+#pragma unroll 2
+    for (int k0 = 0; k0 < 256; k0 += 32) {
+      bf16x8 b[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = *(const GAS bf16x8*)(W + (size_t)(n0 + 16 * j + r) * 256 + k0 + kg);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const bf16x8 a = *(const lds_bf16x8*)((__attribute__((address_space(3))) __bf16*)act +
+                                              (16 * i + r) * kInfLd + k0 + kg);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+      }
+    }
+  }
+
+  // output layer from the last hidden layer's accumulators: per row, the
+  // wave's 64 columns summed over the 16 lanes that share the row
+  const float* b4 = p.bias[3];
+  float part[8][4];
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) part[i][q] = 0.f;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = n0 + 16 * j + r;
+    const float bc = ((const GAS float*)b4)[col], wc = ((const GAS float*)p.wout)[col];
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) part[i][q] += (float)(__bf16)gelu(acc[i][j][q] + bc) * wc;
+  }
+#pragma unroll
+  for (int i = 0; i < 8; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      float v = part[i][q];
+      v += __shfl_xor(v, 1, 64);
+      v += __shfl_xor(v, 2, 64);
+      v += __shfl_xor(v, 4, 64);
+      v += __shfl_xor(v, 8, 64);
+      if (r == 0) ypart[w][16 * i + 4 * (l >> 4) + q] = v;
+    }
+  __syncthreads();
+  if (threadIdx.x < kInfRows) {
+    const int64_t row = row0 + threadIdx.x;
+    if (row < p.n) {
+      const int t = threadIdx.x;
+      ((GAS float*)p.y)[row] = ((const GAS float*)p.bout)[0] + ((ypart[0][t] + ypart[1][t]) + (ypart[2][t] + ypart[3][t]));
+    }
+  }
+}
+
 }  // namespace
+
+hipError_t mlp_infer(const MlpInfer& p, hipStream_t s) {
+  if (p.n <= 0) return hipSuccess;
+  const int64_t grid = (p.n + kInfRows - 1) / kInfRows;
+  if (grid > 0x7fffffff) return hipErrorInvalidValue;
+  k_mlp_infer<<<(unsigned)grid, 256, 0, s>>>(p);
+  return hipGetLastError();
+}
 
 hipError_t mlp_gemm(const MlpGemm& g, hipStream_t s) {
   if (g.M <= 0 || g.N <= 0) return hipSuccess;

@@ -185,6 +185,21 @@ hipError_t mlp_adamw(float* p, float* m, float* v, const float* g, int64_t n, fl
                      float wd, float c1, float c2, hipStream_t s);
 hipError_t mlp_to_bf16(const float* W, int rows, int cols, __bf16* Wb, __bf16* Wtb, hipStream_t s);
 
+// Fused inference of the 4 x 256 GELU network: y[r] = wout . H4(x[r]) + bout
+// for r < n.  Hidden weights are the bf16 copies in [256, kin] layout
+// (kin = 32 for layer 1, columns >= n_in zero); n_in <= 32.
+struct MlpInfer {
+  const float* x;  // [n, n_in]
+  int64_t n;
+  int n_in;
+  const __bf16* W[4];
+  const float* bias[4];
+  const float* wout;  // [256]
+  const float* bout;  // [1]
+  float* y;           // [n]
+};
+hipError_t mlp_infer(const MlpInfer& p, hipStream_t s);
+
 // BVH builder pieces
 struct BvhBuild {
   const float4* tris_in;  // [3 n] unsorted, compacted

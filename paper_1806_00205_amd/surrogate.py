@@ -111,6 +111,33 @@ class Surrogate:
         return y, ok
 
 
+def forward_flops(n_in: int = 8, width: int = 256, depth: int = 4) -> int:
+    """Multiply-adds x 2 of one forward pass (unpadded layer sizes)."""
+    return 2 * (n_in * width + (depth - 1) * width * width + width)
+
+
+def bench_inference(ctx, srg_id: int, n_in: int = 8, n: int = 1_000_000, reps: int = 20, seed: int = 0):
+    """Timed batches of n queries through the fused kernel (HIP events on the
+    library's stream); dense BF16 matrix-core peak 2.5 PFLOP/s."""
+    import torch
+
+    dev = f"cuda:{ctx.device}"
+    X = torch.randn(n, n_in, generator=torch.Generator().manual_seed(seed)).to(dev)
+    ctx.srg_predict(srg_id, X)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        ctx.srg_predict(srg_id, X)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = forward_flops(n_in) * n
+    return {"queries": n, "ms_per_batch": ms, "queries_per_s": n / (ms * 1e-3),
+            "tflops": flops / (ms * 1e-3) / 1e12, "peak_tflops": 2500.0,
+            "frac": flops / (ms * 1e-3) / 2.5e15}
+
+
 def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primaries=20000,
                    judge_primaries=100000, steps=4000, seed=0, log=print):
     """Train on RTMC yields of n_train foams, judge on n_test held-out foams."""
@@ -161,7 +188,7 @@ def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primar
     y_hat = model.predict(F_test)
     err = np.abs(y_hat - y_test)
     ok = model.in_support(F_test)
-    # timing of one million surrogate queries
+    # timing of one million surrogate queries (the held-out features, repeated)
     Fq = np.repeat(F_test, int(math.ceil(1e6 / len(F_test))), axis=0)[:1_000_000]
     import torch
 
@@ -172,6 +199,7 @@ def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primar
     ctx.srg_predict(model.id, Xq)
     torch.cuda.synchronize()
     t_q = time.perf_counter() - t0
+    inf = bench_inference(ctx, model.id)
     # RTMC cost of one yield at the surrogate's error: primaries for sigma = MAE
     sd_pp = float(np.median(s_test * math.sqrt(judge_primaries)))
     mae = float(err.mean())
@@ -190,6 +218,8 @@ def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primar
         "surrogate_queries_per_s": 1e6 / t_q, "rtmc_primaries_per_s": rtmc_rate,
         "rtmc_primaries_for_matched_error": n_matched, "rtmc_yields_per_s_matched_error": rtmc_yield_s,
         "gain": (1e6 / t_q) / rtmc_yield_s,
+        "inference_kernel": inf,
+        "train_samples_per_s": steps * 1024 / t_train,
     }
     return out, model
 

@@ -111,3 +111,29 @@ def test_rejects_bad_shapes(ctx):
         ctx.srg_gradient(s, X, t)  # batch not a multiple of 32
     with pytest.raises(rt.RtmcError):
         ctx.srg_create(N_IN, 128, 4, seed=0)
+
+
+@pytest.mark.parametrize("n_in,B", [(8, 128 * 3 + 1), (5, 64), (32, 1000)])
+def test_fused_prediction_matches_reference_any_width(ctx, n_in, B):
+    """The fused inference kernel (all layers in one workgroup, activations in
+    LDS) against the FP64 reference, for input counts that fill a different
+    part of the padded first layer and a ragged final tile."""
+    s = ctx.srg_create(n_in, 256, 4, seed=20 + n_in)
+    p = ctx.srg_params(s)
+    rng = np.random.default_rng(n_in)
+    X = rng.normal(size=(B, n_in)).astype(np.float32)
+    y = ctx.srg_predict(s, X).cpu().numpy().astype(np.float64)
+    yr, _ = mlp_ref.forward(mlp_ref.gpu_visible_params(p, n_in), mlp_ref.round_bf16(X), n_in)
+    err = np.abs(y - yr)
+    assert np.max(err) <= 0.03 * np.max(np.abs(yr)) + 1e-3, np.max(err)
+
+
+def test_fused_prediction_agrees_with_training_forward(ctx):
+    """Two GPU forward paths -- the fused inference kernel and the layer-by-layer
+    GEMMs of training -- differ only in FP32 summation order: the training loss
+    against the fused predictions as targets is ~0."""
+    s = ctx.srg_create(N_IN, 256, 4, seed=31)
+    X, _ = _data(32, 2048)
+    y = ctx.srg_predict(s, X).cpu().numpy()
+    loss, _ = ctx.srg_gradient(s, X, y)
+    assert loss <= 1e-8 * float(np.mean(y.astype(np.float64) ** 2)) + 1e-12, (loss, float(np.mean(y ** 2)))
