@@ -193,7 +193,7 @@ HitRecs hit_recs(void* base, size_t cap) {
   return h;
 }
 
-constexpr int kShadeBlock = 256;
+constexpr int kShadeBlock = 1024;  // k_shade workgroup: 16 waves share one queue reservation per step
 
 // One chunk of the batch: primaries [lo, lo + n) of the concatenated jobs,
 // which lie in jobs j_lo..j_hi.
@@ -241,7 +241,6 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
                           uint64_t total, bool timed, uint64_t* n_launch) {
   const int block = cfg.block;
   const int grid = grid_of(c, cfg);
-  const int sgrid = c->n_cu * 4;
   const std::vector<ChunkPlan> plan = plan_chunks(jobs, chunk);
   const uint64_t n_chunks = plan.size();
   (void)total;
@@ -337,11 +336,11 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
         HIPCHK(c, launch_traverse(ta, multi, cfg.occupancy, grid, block, s));
         HIPCHK(c, hipEventRecord(e1, s));
         HIPCHK(c, hipEventRecord(e2, s));
-        HIPCHK(c, launch_shade(sa, sgrid, kShadeBlock, s));
+        HIPCHK(c, launch_shade(sa, c->n_cu, kShadeBlock, s));
         HIPCHK(c, hipEventRecord(e3, s));
       } else {
         HIPCHK(c, launch_traverse(ta, multi, cfg.occupancy, grid, block, s));
-        HIPCHK(c, launch_shade(sa, sgrid, kShadeBlock, s));
+        HIPCHK(c, launch_shade(sa, c->n_cu, kShadeBlock, s));
       }
       ++*n_launch;
     }
@@ -377,7 +376,9 @@ rtmc_status prepare_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   HIPCHK(c, hipMemcpyAsync(c->jobs.p, dj.data(), sizeof(DevJob) * dj.size(), hipMemcpyHostToDevice, c->stream));
   const uint32_t chunk = (uint32_t)cfg.chunk;
   const uint64_t need_q = (uint64_t)chunk * tb.max_d;
-  if (need_q > 0xFFFFFFF0ull) return fail(c, RTMC_EINVAL, "chunk too large for the queue index range");
+  // the 32-bit work counters may run past the queue length by one block claim per wave
+  const uint64_t claim_slack = (uint64_t)grid_of(c, cfg) * (cfg.block / 64) * kClaimMax;
+  if (need_q + claim_slack > 0xFFFFFFF0ull) return fail(c, RTMC_EINVAL, "chunk too large for the queue index range");
   if (c->qcap < need_q || !c->queue[0].p) {
     for (int i = 0; i < 2; ++i) {
       st = ensure(c, c->queue[i], (size_t)need_q * 40);

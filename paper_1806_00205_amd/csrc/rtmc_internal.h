@@ -27,6 +27,7 @@ constexpr int kMaxAbins = 360;
 constexpr int kMaxYield = 8192;
 constexpr int kMaxCdf = 1024;
 constexpr int kGlobalStack = 64;  // minimum traversal stack entries per lane beyond the LDS part
+constexpr int kClaimMax = 2048;   // largest block of rays one traversal wave claims at once
 constexpr int kShadeJobs = 8;     // chunks with at most this many jobs tally per workgroup in LDS
 
 // tally counter slots (u64 each), followed by the energy and angle histograms
@@ -141,7 +142,7 @@ size_t traverse_lds_bytes(int lds_stack, int block);
 // LDS of a shading workgroup; n_jobs = jobs of the chunk (tallied in LDS when <= kShadeJobs)
 size_t shade_lds_bytes(const DevTables& tb, int n_ebins, int n_abins, int block, int n_jobs);
 hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int grid, int block, hipStream_t s);
-hipError_t launch_shade(const ShadeArgs& a, int grid, int block, hipStream_t s);
+hipError_t launch_shade(const ShadeArgs& a, int n_cu, int block, hipStream_t s);  // grid = n_cu x occupancy
 hipError_t launch_primaries(const DevJob* jobs, int32_t j_lo, int32_t j_hi, uint64_t chunk_lo, uint32_t n,
                             const RayQueue& q, hipStream_t s);
 hipError_t launch_hit_ids(const float4* tris, const int32_t* code, int64_t n, int32_t* out, hipStream_t s);

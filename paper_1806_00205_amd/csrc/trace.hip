@@ -534,9 +534,13 @@ extern __shared__ __align__(16) unsigned char smem[];
 // (traversing a segment) or finished (its segment's traversal is over).  The
 // common iteration is one node step of the busy lanes; finished lanes are
 // serviced together -- segment end, periodic re-entry, hit record -- and idle
-// lanes fetch new rays with one atomic per wave, once at least `refill` lanes
-// are not busy.  So a wave is neither held by its slowest ray nor made to run
-// the rare paths on every iteration.  MULTI: rays may belong to different jobs.
+// lanes take new rays once at least `refill` lanes are not busy.  So a wave is
+// neither held by its slowest ray nor made to run the rare paths on every
+// iteration.  Rays come from a per-wave reservation of consecutive indices,
+// claimed from the generation's counter in guided blocks (a share of the
+// estimated remaining work, at least the idle lanes, at most kClaimMax): one
+// contended atomic serves many refills early on, and blocks shrink towards
+// the end so the waves finish together.  MULTI: rays may belong to different jobs.
 template <bool MULTI>
 __device__ inline void traverse_body(const TraverseArgs& a) {
   const int wpb = blockDim.x >> 6;
@@ -554,6 +558,8 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
   int st = 0;  // 0 idle, 1 busy, 2 finished
   bool ovf = false;
   bool exhausted = false;
+  uint32_t res_lo = 0, res_hi = 0, seen = 0;  // wave-uniform reservation and counter estimate
+  const uint32_t total_waves = gridDim.x * (uint32_t)wpb;
   if (!MULTI) {
     L.nodes = a.jobs[0].sc.nodes;
     L.tris = a.jobs[0].sc.tris;
@@ -596,15 +602,35 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
         }
       }
       const uint64_t idle = __ballot(st == 0);
-      if (!exhausted && idle) {
+      if (idle && (res_lo < res_hi || !exhausted)) {
         const uint32_t nidle = (uint32_t)__popcll(idle);
-        uint32_t base = 0;
-        if (lane == 0) base = __hip_atomic_fetch_add(gp(a.work), nidle, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        base = __shfl(base, 0, 64);
-        if (base + nidle >= count) exhausted = true;
+        const uint32_t have = res_hi - res_lo;
+        uint32_t base = 0, new_hi = 0;
+        bool claimed = false;
+        if (have < nidle && !exhausted) {
+          const uint32_t want = nidle - have;
+          const uint32_t left = count > seen ? count - seen : 0u;
+          uint32_t claim = (left / (2u * total_waves)) & ~63u;
+          claim = claim > (uint32_t)kClaimMax ? (uint32_t)kClaimMax : claim;
+          claim = claim < want ? want : claim;
+          if (lane == 0) base = __hip_atomic_fetch_add(gp(a.work), claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          base = __shfl(base, 0, 64);
+          seen = base + claim;
+          if (base + claim >= count) exhausted = true;
+          new_hi = base >= count ? base : min(base + claim, count);
+          claimed = true;
+        }
+        const uint32_t rank = (uint32_t)__popcll(idle & lt);
         if (st == 0) {
-          item = base + (uint32_t)__popcll(idle & lt);
-          if (item < count) {
+          bool got = false;
+          if (rank < have) {
+            item = res_lo + rank;
+            got = true;
+          } else if (claimed) {
+            item = base + (rank - have);
+            got = item < new_hi;
+          }
+          if (got) {
             float ox, oy, oz, dx, dy, dz;
             if (a.src == 1) {
               ox = gp(a.qin.ox)[item];
@@ -641,6 +667,13 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
             seg_begin(s, a.jobs[job].sc);
             st = 1;
           }
+        }
+        if (claimed) {
+          const uint32_t lo2 = base + (nidle - have);
+          res_lo = lo2 < new_hi ? lo2 : new_hi;
+          res_hi = new_hi;
+        } else {
+          res_lo = res_lo + nidle < res_hi ? res_lo + nidle : res_hi;
         }
       }
       // after servicing no lane is finished: none busy means the work is done
@@ -701,7 +734,7 @@ __global__ void k_hit_ids(const float4* __restrict__ tris, const int32_t* __rest
 // count, energies and directions and append the daughters to the next queue
 // with one atomic per wave.  Tables sit in LDS; tallies in per-wave LDS
 // blocks tagged with the job they belong to.
-__global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void k_shade(ShadeArgs a) {
   const int wpb = blockDim.x >> 6;
   const int w = threadIdx.x >> 6;
   const uint32_t lane = lane_id();
@@ -714,6 +747,7 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   size_t off = ((size_t)(nY + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
   LAS uint32_t* s_eh = (LAS uint32_t*)(lds + off);
   LAS uint32_t* s_ah = s_eh + wpb * a.n_ebins;
+  __shared__ uint32_t s_wtot[16], s_wbase[16];  // per-wave daughter totals and queue offsets of a step
   JobTab jtab;
   jtab.base = lds + off;
   jtab.stride = (T_NCOUNT * 8 + (a.n_ebins + a.n_abins) * 4 + 7) & ~7;
@@ -725,11 +759,14 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   const JobTab* jt = shared ? &jtab : nullptr;
 
   const uint32_t count = a.gen == 0 ? a.n_gen0 : min(*gp(a.count_in), a.qcap);  // queue length
-  // each wave takes one contiguous slice (a multiple of 64 rays): neighbouring
-  // rays mostly share a job, so the per-wave tallies rarely change owner
-  const uint32_t total_waves = gridDim.x * (uint32_t)wpb;
-  const uint32_t per = ((count + total_waves - 1) / total_waves + 63u) & ~63u;
-  if ((uint64_t)blockIdx.x * wpb * per >= count) return;  // whole workgroup idle
+  // each workgroup takes one contiguous slice (a multiple of its size), in
+  // steps of blockDim.x rays, 64 per wave: neighbouring rays mostly share a
+  // job, so the per-wave tallies rarely change owner, and the workgroup
+  // reserves queue space for its daughters with one atomic per step
+  const uint32_t per = ((count + gridDim.x - 1) / gridDim.x + blockDim.x - 1) / blockDim.x * blockDim.x;
+  const uint64_t wg0 = (uint64_t)blockIdx.x * per;
+  if (wg0 >= count) return;  // whole workgroup idle
+  const uint32_t wg1 = (uint32_t)min((uint64_t)count, wg0 + per);
   for (int i = threadIdx.x; i < nY; i += blockDim.x) s_yld[i] = gp(tb.yld)[i];
   for (int i = threadIdx.x; i < tb.ncdf; i += blockDim.x) {
     s_cE[i] = gp(tb.cdfE)[i];
@@ -752,11 +789,10 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
   wt.eh = s_eh + w * a.n_ebins;
   wt.ah = s_ah + w * a.n_abins;
   int tag = -1;
-  const uint64_t seg0 = (uint64_t)(blockIdx.x * wpb + w) * per;
-  const uint32_t seg1 = (uint32_t)min((uint64_t)count, seg0 + per);
-  for (uint32_t base = (uint32_t)min(seg0, (uint64_t)count); base < seg1; base += 64u) {
+  for (uint32_t step = (uint32_t)wg0; step < wg1; step += blockDim.x) {
+    const uint32_t base = step + (uint32_t)w * 64u;
     const uint32_t item = base + lane;
-    const bool active = item < count;
+    const bool active = item < wg1;
 
     float ox = 0.f, oy = 0.f, oz = 0.f, dx = 0.f, dy = 0.f, dz = -1.f, E = 0.f;
     uint32_t path = 0, ci = 0;
@@ -778,7 +814,7 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
     (void)oy;
     (void)oz;
     const int j0 = __shfl(job, 0, 64);
-    if (j0 != tag) {
+    if (base < wg1 && j0 != tag) {  // lane 0 active: the wave has rays this step
       if (tag >= 0) {
         if (shared)
           flush_wave_lds(wt, jt_cnt(jtab, tag), lane);
@@ -878,13 +914,21 @@ __global__ __launch_bounds__(256) void k_shade(ShadeArgs a) {
       }
     }
 
-    // ---- daughters: one queue reservation per wave
+    // ---- daughters: one queue reservation per workgroup step
     const uint32_t incl = wave_incl_scan((uint32_t)nd, lane);
-    const uint32_t total = __shfl(incl, 63, 64);
-    if (total == 0u) continue;
-    uint32_t obase = 0;
-    if (lane == 0) obase = __hip_atomic_fetch_add(gp(a.count_out), total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    obase = __shfl(obase, 0, 64);
+    if (lane == 63) s_wtot[w] = incl;
+    __syncthreads();
+    if (w == 0) {
+      const uint32_t v = lane < (uint32_t)wpb ? s_wtot[lane] : 0u;
+      const uint32_t inc2 = wave_incl_scan(v, lane);
+      const uint32_t T = __shfl(inc2, 63, 64);
+      uint32_t b = 0;
+      if (lane == 0 && T) b = __hip_atomic_fetch_add(gp(a.count_out), T, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      b = __shfl(b, 0, 64);
+      if (lane < (uint32_t)wpb) s_wbase[lane] = b + inc2 - v;
+    }
+    __syncthreads();
+    const uint32_t obase = s_wbase[w];
     if (nd > 0) {
       const uint32_t first = obase + incl - (uint32_t)nd;
       const uint64_t pid = J.pid0 + (a.chunk_lo + ci - J.gbase);
@@ -1064,9 +1108,15 @@ hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int
   return hipGetLastError();
 }
 
-hipError_t launch_shade(const ShadeArgs& a, int grid, int block, hipStream_t s) {
+hipError_t launch_shade(const ShadeArgs& a, int n_cu, int block, hipStream_t s) {
   const size_t lds = shade_lds_bytes(a.tb, a.n_ebins, a.n_abins, block, a.j_hi - a.j_lo + 1);
-  k_shade<<<grid, block, lds, s>>>(a);
+  // every workgroup resident at once: the waves take equal contiguous slices,
+  // so a second round of workgroups would double the kernel's time
+  int per_cu = 0;
+  hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_shade, block, lds);
+  if (e != hipSuccess) return e;
+  if (per_cu < 1) return hipErrorInvalidConfiguration;
+  k_shade<<<n_cu * per_cu, block, lds, s>>>(a);
   return hipGetLastError();
 }
 
