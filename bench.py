@@ -264,13 +264,20 @@ def cpu_baseline(ctx, sid, tid, mesh, tab, cfg, points, npp, gpu_prim_s, seconds
     cores = min(cores, 16)
     E, th = points[len(points) // 2]
     seed = cfg["rng"] * 1000 + len(points) // 2
+    # pilot on enough primaries to keep every thread busy, then size the sample
+    pilot = 16 * cores
     t = time.perf_counter()
-    oracle.trace(mesh, tab, E, th, 32, seed=seed, max_gen=cfg["max_gen"], n_threads=cores)
-    per = (time.perf_counter() - t) / 32
+    oracle.trace(mesh, tab, E, th, pilot, seed=seed, max_gen=cfg["max_gen"], n_threads=cores)
+    per = (time.perf_counter() - t) / pilot
     n = int(max(64, min(npp, seconds / max(per, 1e-9))))
     t = time.perf_counter()
     o = oracle.trace(mesh, tab, E, th, n, seed=seed, max_gen=cfg["max_gen"], n_threads=cores, per_primary=True)
     dt = time.perf_counter() - t
+    # one core, on a prefix of the same ids (about a tenth of the time budget)
+    n1 = int(max(8, min(n, 0.1 * seconds / max(per * cores, 1e-9))))
+    t = time.perf_counter()
+    o1 = oracle.trace(mesh, tab, E, th, n1, seed=seed, max_gen=cfg["max_gen"], n_threads=1)
+    dt1 = time.perf_counter() - t
     pp = torch.zeros(n, dtype=torch.int32, device="cuda:0")
     g = ctx.trace(sid, tid, E, th, n, seed=seed, max_gen=cfg["max_gen"], per_primary=pp)
     ppg = pp.cpu().numpy().astype(np.int64)
@@ -285,6 +292,8 @@ def cpu_baseline(ctx, sid, tid, mesh, tab, cfg, points, npp, gpu_prim_s, seconds
         "kind": "oracle",
         "sample": f"primary ids 0..{n - 1} at E={E:g} eV, theta={th:g} deg on the same mesh ({dt:.1f} s)",
         "tri_tests_per_s": o["n_tri_tests"] / dt,
+        "one_core": {"primaries_per_s": n1 / dt1, "tri_tests_per_s": o1["n_tri_tests"] / dt1,
+                     "sample": f"primary ids 0..{n1 - 1} ({dt1:.1f} s)"},
         "paired_parity": {"oracle_yield": o["yield"], "gpu_yield": g["yield"],
                           "same_escape_count_frac": float((diff == 0).mean()), "paired_z": float(z)},
     }

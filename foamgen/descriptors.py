@@ -30,35 +30,34 @@ def mean_curvature(f):
     return -0.5 * div
 
 
-def _runs(mask_1d_rows, periodic):
-    """Lengths of True runs along the last axis of a 2-D boolean array."""
-    out = []
-    for row in mask_1d_rows:
-        if not row.any():
-            continue
-        if row.all():
-            out.append(row.size)
-            continue
-        r = row
-        if periodic:
-            # rotate so the row starts at a solid site: runs do not wrap
-            k = int(np.argmin(r))
-            r = np.roll(r, -k)
-        d = np.diff(np.concatenate([[0], r.astype(np.int8), [0]]))
-        starts = np.nonzero(d == 1)[0]
-        ends = np.nonzero(d == -1)[0]
-        out.extend((ends - starts).tolist())
-    return out
+def _runs(rows, periodic):
+    """Lengths of True runs along the last axis of a 2-D boolean array (as a
+    multiset: order is not meaningful).  Periodic rows are first rotated to
+    start at a solid site so that no run wraps; an all-void row is one run."""
+    M = np.asarray(rows, dtype=bool)
+    if M.size == 0:
+        return np.zeros(0, dtype=np.int64)
+    L = M.shape[1]
+    full = M.all(axis=1)
+    A = M[M.any(axis=1) & ~full]
+    if periodic and A.shape[0]:
+        k = np.argmin(A, axis=1)
+        A = np.take_along_axis(A, (k[:, None] + np.arange(L)[None, :]) % L, axis=1)
+    P = np.zeros((A.shape[0], L + 2), dtype=np.int8)
+    P[:, 1:-1] = A
+    d = np.diff(P, axis=1)
+    starts = np.nonzero(d == 1)[1]
+    ends = np.nonzero(d == -1)[1]  # row-major order: pairs with starts
+    return np.concatenate([ends - starts, np.full(int(full.sum()), L, dtype=np.int64)])
 
 
 def chord_lengths(void):
     nx, ny, nz = void.shape
     inner = void[:, :, 1:nz - 1]
-    runs = []
-    runs += _runs(inner.transpose(1, 2, 0).reshape(-1, nx), True)
-    runs += _runs(inner.transpose(0, 2, 1).reshape(-1, ny), True)
-    runs += _runs(inner.reshape(-1, nz - 2), False)
-    return np.asarray(runs, dtype=np.float64)
+    runs = [_runs(inner.transpose(1, 2, 0).reshape(-1, nx), True),
+            _runs(inner.transpose(0, 2, 1).reshape(-1, ny), True),
+            _runs(inner.reshape(-1, nz - 2), False)]
+    return np.concatenate(runs).astype(np.float64)
 
 
 def foam_descriptors(mesh, field, tau):

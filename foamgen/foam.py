@@ -75,10 +75,12 @@ def foam_field(n: int, porosity: float, ell: float = 2.0, seed: int = 0, nz: int
     return f, tau
 
 
-def make_grf_foam(n: int, porosity: float, ell: float = 2.0, seed: int = 0, nz: int | None = None) -> Mesh:
-    """Periodic GRF nanofoam mesh in a box [0, n) x [0, n) x [0, nz-1]."""
+def make_grf_foam(n: int, porosity: float, ell: float = 2.0, seed: int = 0, nz: int | None = None,
+                  field=None) -> Mesh:
+    """Periodic GRF nanofoam mesh in a box [0, n) x [0, n) x [0, nz-1].
+    `field` may pass in foam_field's (field, tau) for the same arguments."""
     nz = n if nz is None else nz
-    f, tau = foam_field(n, porosity, ell, seed, nz)
+    f, tau = foam_field(n, porosity, ell, seed, nz) if field is None else field
     verts, tris, canon = marching_cubes_periodic(f, tau)
     void_frac = float((f[:, :, 1 : nz - 1] < tau).mean())
     return Mesh(

@@ -16,24 +16,30 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import time
 
 import numpy as np
 
 import foamgen as fg
-from foamgen.descriptors import foam_descriptors
 
 GRID_E = [50.0, 100.0, 250.0, 500.0, 1000.0]
 GRID_THETA = [0.0, 20.0, 40.0, 60.0, 80.0]
 
 
-def make_foam(seed: int, rng: np.random.Generator, sizes=(40, 48, 56)):
-    """One foam of the batched-workload family: porosity ~ U[0.2, 0.8]."""
-    n = int(rng.choice(sizes))
-    p = float(rng.uniform(0.2, 0.8))
-    field, tau = fg.foam_field(n, p, 2.0, seed=seed)
-    mesh = fg.make_grf_foam(n, p, 2.0, seed=seed)
-    return mesh, foam_descriptors(mesh, field, tau)
+def foam_specs(first_seed: int, count: int, rng: np.random.Generator, sizes=(40, 48, 56)):
+    """(seed, grid, porosity) of `count` foams of the batched-workload family:
+    grid uniform over `sizes`, porosity ~ U[0.2, 0.8]."""
+    return [(first_seed + i, int(rng.choice(sizes)), float(rng.uniform(0.2, 0.8))) for i in range(count)]
+
+
+def generate(specs, pool=None):
+    """Meshes and descriptors of the specs, in worker processes when a pool is given."""
+    from foamgen.batch import foam_with_descriptors
+
+    if pool is None:
+        return [foam_with_descriptors(sp) for sp in specs]
+    return pool.map(foam_with_descriptors, specs, chunksize=1)
 
 
 def features(desc, E, theta_deg):
@@ -138,57 +144,88 @@ def bench_inference(ctx, srg_id: int, n_in: int = 8, n: int = 1_000_000, reps: i
             "frac": flops / (ms * 1e-3) / 2.5e15}
 
 
+def _traced_batches(device, tab, specs, points, batch_foams, pool, max_gen, log, what):
+    """Generate the foams of `specs` in batches, trace each batch's jobs in a
+    context of its own (so its scenes are freed), and return per job
+    (descriptors, E, theta, yield, sigma, n_primaries) plus the tracing time.
+    points(foam index) -> list of (E, theta, n_primaries, seed)."""
+    import paper_1806_00205_amd as rt
+
+    rows, t_trace, t_gen, prim = [], 0.0, 0.0, 0
+    for b0 in range(0, len(specs), batch_foams):
+        t0 = time.time()
+        foams = generate(specs[b0:b0 + batch_foams], pool)
+        t_gen += time.time() - t0
+        ctx = rt.Context(device)
+        try:
+            tid = ctx.load_tables(tab)
+            jobs, meta = [], []
+            for k, (mesh, d) in enumerate(foams):
+                sid = ctx.load_scene(mesh)
+                for E, th, n, sd in points(b0 + k):
+                    jobs.append((sid, float(E), float(th), int(n), int(sd)))
+                    meta.append((d, float(E), float(th)))
+            del foams
+            t0 = time.time()
+            y, sig, res = rtmc_yields(ctx, tid, jobs, max_gen=max_gen)
+            t_trace += time.time() - t0
+            prim += sum(r["n_primaries"] for r in res)
+        finally:
+            ctx.close()
+        rows.extend((d, E, th, yy, ss) for (d, E, th), yy, ss in zip(meta, y, sig))
+        log(f"[srg] {what}: {min(b0 + batch_foams, len(specs))}/{len(specs)} foams")
+    return rows, t_trace, t_gen, prim
+
+
 def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primaries=20000,
-                   judge_primaries=100000, steps=4000, seed=0, log=print):
+                   judge_primaries=100000, steps=4000, seed=0, log=print, sizes=(40, 48, 56), workers=0,
+                   batch_foams=64, max_gen=6):
     """Train on RTMC yields of n_train foams, judge on n_test held-out foams."""
     rng = np.random.default_rng(seed)
     tab = fg.make_tables("vaughan")
-    tid = ctx.load_tables(tab)
-    t0 = time.time()
-    train_desc, train_jobs = [], []
-    for i in range(n_train):
-        mesh, d = make_foam(10000 + i, rng)
-        sid = ctx.load_scene(mesh)
-        E = np.exp(rng.uniform(np.log(50.0), np.log(1000.0), size=points_per_foam))
-        th = rng.uniform(0.0, 80.0, size=points_per_foam)
-        for e, t in zip(E, th):
-            train_jobs.append((sid, float(e), float(t), train_primaries, int(rng.integers(1, 2 ** 62))))
-            train_desc.append((d, e, t))
-    t_gen = time.time() - t0
-    log(f"[srg] {n_train} training foams generated in {t_gen:.1f} s")
-    t0 = time.time()
-    y_train, s_train, res = rtmc_yields(ctx, tid, train_jobs)
-    t_rtmc = time.time() - t0
-    prim = sum(r["n_primaries"] for r in res)
-    log(f"[srg] {len(train_jobs)} training yields traced in {t_rtmc:.2f} s ({prim / t_rtmc:.3g} primaries/s)")
-    F_train = features(np.array([d for d, _, _ in train_desc]), [e for _, e, _ in train_desc],
-                       [t for _, _, t in train_desc])
+    pool = None
+    if workers and workers > 1:
+        import multiprocessing as mp
+
+        pool = mp.get_context("spawn").Pool(workers)
+    try:
+        train_specs = foam_specs(10000, n_train, rng, sizes)
+        test_specs = foam_specs(90000, n_test, rng, sizes)
+        # training points: E log-uniform in [50, 1000] eV, theta uniform in [0, 80] deg
+        tp = []
+        for _ in range(n_train):
+            E = np.exp(rng.uniform(np.log(50.0), np.log(1000.0), size=points_per_foam))
+            th = rng.uniform(0.0, 80.0, size=points_per_foam)
+            tp.append([(e, t, train_primaries, int(rng.integers(1, 2 ** 62))) for e, t in zip(E, th)])
+        # held-out foams: the 5 x 5 grid
+        jp = [[(e, t, judge_primaries, int(rng.integers(1, 2 ** 62))) for e in GRID_E for t in GRID_THETA]
+              for _ in range(n_test)]
+        train, t_rtmc, t_gen, prim = _traced_batches(ctx.device, tab, train_specs, lambda i: tp[i], batch_foams,
+                                                     pool, max_gen, log, "training foams")
+        log(f"[srg] {len(train)} training yields traced in {t_rtmc:.2f} s ({prim / t_rtmc:.3g} primaries/s); "
+            f"foams generated in {t_gen:.1f} s")
+        test, t_judge, t_gen2, prim_t = _traced_batches(ctx.device, tab, test_specs, lambda i: jp[i], batch_foams,
+                                                        pool, max_gen, log, "held-out foams")
+    finally:
+        if pool is not None:
+            pool.close()
+            pool.join()
+    F_train = features(np.array([r[0] for r in train]), [r[1] for r in train], [r[2] for r in train])
+    y_train = np.array([r[3] for r in train])
     model = Surrogate(ctx, seed=seed)
     t0 = time.time()
     losses = model.fit(F_train, y_train, steps=steps, seed=seed, log=log)
     t_train = time.time() - t0
     log(f"[srg] trained {steps} steps in {t_train:.2f} s")
 
-    # held-out foams judged by RTMC on the 5 x 5 grid
-    test_desc, test_jobs, test_grid = [], [], []
-    for i in range(n_test):
-        mesh, d = make_foam(90000 + i, rng)
-        sid = ctx.load_scene(mesh)
-        test_grid.append(mesh.meta["n"])
-        for e in GRID_E:
-            for t in GRID_THETA:
-                test_jobs.append((sid, e, t, judge_primaries, int(rng.integers(1, 2 ** 62))))
-                test_desc.append((d, e, t))
-    t0 = time.time()
-    y_test, s_test, res_t = rtmc_yields(ctx, tid, test_jobs)
-    t_judge = time.time() - t0
-    prim_t = sum(r["n_primaries"] for r in res_t)
-    F_test = features(np.array([d for d, _, _ in test_desc]), [e for _, e, _ in test_desc],
-                      [t for _, _, t in test_desc])
+    F_test = features(np.array([r[0] for r in test]), [r[1] for r in test], [r[2] for r in test])
+    y_test = np.array([r[3] for r in test])
+    s_test = np.array([r[4] for r in test])
+    test_grid = [sp[1] for sp in test_specs]
     y_hat = model.predict(F_test)
     err = np.abs(y_hat - y_test)
     ok = model.in_support(F_test)
-    # timing of one million surrogate queries (the held-out features, repeated)
+    # one million surrogate queries (the held-out features, repeated), end to end
     Fq = np.repeat(F_test, int(math.ceil(1e6 / len(F_test))), axis=0)[:1_000_000]
     import torch
 
@@ -207,14 +244,17 @@ def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primar
     rtmc_rate = prim_t / t_judge
     rtmc_yield_s = rtmc_rate / n_matched
     out = {
-        "n_train_foams": n_train, "train_yields": len(train_jobs), "train_primaries_per_yield": train_primaries,
-        "n_test_foams": n_test, "test_points": len(test_jobs), "judge_primaries_per_yield": judge_primaries,
+        "n_train_foams": n_train, "train_yields": len(train), "train_primaries_per_yield": train_primaries,
+        "foam_grids": list(sizes),
+        "n_test_foams": n_test, "test_points": len(test), "judge_primaries_per_yield": judge_primaries,
         "mae": mae, "p95_abs_err": float(np.quantile(err, 0.95)), "max_abs_err": float(err.max()),
         "mae_in_support": float(err[ok].mean()) if ok.any() else None, "in_support_frac": float(ok.mean()),
         "judge_sigma_median": float(np.median(s_test)),
+        "train_sigma_median": float(np.median([r[4] for r in train])),
         "mae_by_grid": {str(n): float(err[np.repeat(np.array(test_grid) == n, 25)].mean())
                         for n in sorted(set(test_grid))},
-        "final_loss": losses[-1][1], "train_seconds": t_train, "gen_seconds": t_gen,
+        "final_loss": losses[-1][1], "train_seconds": t_train, "gen_seconds": t_gen + t_gen2,
+        "rtmc_train_seconds": t_rtmc, "rtmc_judge_seconds": t_judge,
         "surrogate_queries_per_s": 1e6 / t_q, "rtmc_primaries_per_s": rtmc_rate,
         "rtmc_primaries_for_matched_error": n_matched, "rtmc_yields_per_s_matched_error": rtmc_yield_s,
         "gain": (1e6 / t_q) / rtmc_yield_s,
@@ -231,12 +271,20 @@ def main():
     ap.add_argument("--points", type=int, default=64)
     ap.add_argument("--test-foams", type=int, default=64)
     ap.add_argument("--steps", type=int, default=4000)
+    ap.add_argument("--train-primaries", type=int, default=100000)
+    ap.add_argument("--judge-primaries", type=int, default=1000000)
+    ap.add_argument("--sizes", default="64,96,128,192", help="foam grids (voxels per side)")
+    ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
+    ap.add_argument("--batch-foams", type=int, default=32)
     args = ap.parse_args()
     import paper_1806_00205_amd as rt
 
     ctx = rt.Context(0)
     res, _ = run_experiment(ctx, n_train=args.train_foams, points_per_foam=args.points, n_test=args.test_foams,
-                            steps=args.steps)
+                            train_primaries=args.train_primaries, judge_primaries=args.judge_primaries,
+                            steps=args.steps, sizes=tuple(int(x) for x in args.sizes.split(",")),
+                            workers=args.workers, batch_foams=args.batch_foams,
+                            log=lambda m: print(m, flush=True))
     print(json.dumps(res))
     if args.out:
         with open(args.out, "w") as f:

@@ -78,3 +78,41 @@ def test_chung_everhart_closed_forms():
     assert fg.ce_inverse(0.5) == pytest.approx(4.5, rel=1e-12)
     t = fg.make_tables("vaughan")
     assert t.cdf_F[0] == 0 and t.cdf_F[-1] == 1 and np.all(np.diff(t.cdf_F) >= 0)
+
+
+def test_chord_lengths_match_a_walk_along_every_line():
+    """Void chord lengths (a surrogate input) against walking each lattice line."""
+    from foamgen.descriptors import chord_lengths
+    rng = np.random.default_rng(3)
+    v = rng.random((5, 4, 7)) < 0.55
+    v[1, 2, :] = True  # an all-void column
+    nx, ny, nz = v.shape
+    inner = v[:, :, 1:nz - 1]
+
+    def walk(line, periodic):
+        if line.all():
+            return [len(line)]
+        if not line.any():
+            return []
+        if periodic:
+            line = np.roll(line, -int(np.argmin(line)))
+        out, c = [], 0
+        for x in line:
+            if x:
+                c += 1
+            elif c:
+                out.append(c)
+                c = 0
+        return out + ([c] if c else [])
+
+    ref = []
+    for y in range(ny):
+        for z in range(nz - 2):
+            ref += walk(inner[:, y, z], True)
+    for x in range(nx):
+        for z in range(nz - 2):
+            ref += walk(inner[x, :, z], True)
+    for x in range(nx):
+        for y in range(ny):
+            ref += walk(inner[x, y, :], False)
+    assert sorted(chord_lengths(v).tolist()) == sorted(ref)
