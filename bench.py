@@ -29,6 +29,10 @@ PEAK_HBM_GBPS = 8000.0  # MI355X published HBM3E bandwidth
 Q_READ_BYTES = 24  # traversal reads origin + direction of a queued ray (6 x 32-bit streams)
 HIT_BYTES = 28  # one hit record: 7 x 32-bit streams
 NODE_BYTES = 64
+# LBVH build per triangle: Morton codes (48 read + 12 written), 8 radix passes
+# (8 + 24 bytes each), triangle gather (4 + 48 + 48), hierarchy (24 key reads
+# + 16 link writes), bottom-up bounds (48 triangle read + 64 node write + 12)
+BUILD_BYTES_PER_TRI = 60 + 8 * 32 + 100 + 40 + 124
 TRI_BYTES = 48
 
 CONFIGS = {
@@ -178,10 +182,29 @@ def main():
             "achievable_copy_gbps": achievable,
         },
     }
+    out["bvh_build"] = bench_build(ctx, mesh)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(ctx, sid, tid, mesh, tab, cfg, points, npp, prim_s, args.cpu_seconds)
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def bench_build(ctx, mesh, reps: int = 3):
+    """Mesh ingest (host arrays -> device) and the device LBVH build of the
+    same mesh, after the timed region; the build time is the library's own
+    HIP-event figure."""
+    ingest, build = [], []
+    for _ in range(reps):
+        t = time.perf_counter()
+        sid = ctx.load_mesh(mesh.verts, mesh.tris, mesh.box_lo, mesh.box_hi, mesh.flags)
+        ingest.append((time.perf_counter() - t) * 1e3)
+        ctx.build_bvh(sid)
+        build.append(ctx.scene_info(sid)["build_ms"])
+    b = sorted(build)[reps // 2]
+    n = mesh.n_tris
+    return {"n_tris": n, "ingest_ms": sorted(ingest)[reps // 2], "build_ms": b, "tris_per_s": n / (b * 1e-3),
+            "alg_bytes_per_tri": BUILD_BYTES_PER_TRI,
+            "alg_gbps": BUILD_BYTES_PER_TRI * n / (b * 1e-3) / 1e9}
 
 
 def bench_batched(args, cfg, npp):

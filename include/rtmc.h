@@ -184,6 +184,19 @@ rtmc_status rtmc_get_scene_info(rtmc_ctx* ctx, int32_t scene_id, rtmc_scene_info
  *   Either may be NULL. */
 rtmc_status rtmc_bvh_download(rtmc_ctx* ctx, int32_t scene_id, float* nodes, float* tris);
 
+/* Copy the 4-wide nodes that traversal reads (for inspection and tests).
+ * Node i (one per binary internal node; traversal reaches those of even
+ * binary depth from node 0) holds the children of binary node i, each inner
+ * child replaced by its two children.  wide: host uint32 [n_nodes * 16]:
+ *   words 0-2: float origin o (x, y, z); word 3: bytes 0-2 the biased
+ *     exponents e + 127 of the per-axis scales s = 2^e;
+ *   words 4-7: child links (bit 31 set: leaf, low bits: sorted triangle
+ *     index; else a node index; 0xFFFFFFFF: unused slot);
+ *   words 8-13: lo_x, lo_y, lo_z, hi_x, hi_y, hi_z, each four bytes q (byte j
+ *     for child j); a bound decodes as fmaf(q, s, o) and contains the exact
+ *     child box; words 14-15 zero. */
+rtmc_status rtmc_bvh_download_wide(rtmc_ctx* ctx, int32_t scene_id, uint32_t* wide);
+
 /* Upload flat-surface tables; returns the table id in *table_id. */
 rtmc_status rtmc_load_tables(rtmc_ctx* ctx, const rtmc_tables* t, int32_t* table_id);
 

@@ -29,7 +29,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5:
 
 EXPORTS = [
     "rtmc_create", "rtmc_destroy", "rtmc_last_error", "rtmc_set_stream", "rtmc_load_mesh", "rtmc_build_bvh",
-    "rtmc_get_scene_info", "rtmc_bvh_download", "rtmc_load_tables", "rtmc_trace", "rtmc_trace_batch",
+    "rtmc_get_scene_info", "rtmc_bvh_download", "rtmc_bvh_download_wide", "rtmc_load_tables", "rtmc_trace", "rtmc_trace_batch",
     "rtmc_first_hit", "rtmc_sort_pairs_u64", "rtmc_set_launch", "rtmc_get_launch", "rtmc_autotune",
     "rtmc_copy_probe", "rtmc_srg_create", "rtmc_srg_param_count", "rtmc_srg_get_params", "rtmc_srg_set_params",
     "rtmc_srg_gradient", "rtmc_srg_train_step", "rtmc_srg_predict",
@@ -117,6 +117,7 @@ def load_library(path: str = LIB_PATH):
         "rtmc_build_bvh": ([P, i32], C.c_int),
         "rtmc_get_scene_info": ([P, i32, C.POINTER(SceneInfo)], C.c_int),
         "rtmc_bvh_download": ([P, i32, P, P], C.c_int),
+        "rtmc_bvh_download_wide": ([P, i32, P], C.c_int),
         "rtmc_load_tables": ([P, C.POINTER(Tables), C.POINTER(i32)], C.c_int),
         "rtmc_trace": ([P, i32, i32, dbl, dbl, u64, u64, C.POINTER(TraceOpts), C.POINTER(Result)], C.c_int),
         "rtmc_trace_batch": ([P, i32, C.POINTER(Job), i64, i32, C.POINTER(Result)], C.c_int),
@@ -231,6 +232,13 @@ class Context:
         tris = np.zeros((info["n_tris"], 12), dtype=np.float32)
         self._chk(self.lib.rtmc_bvh_download(self.h, scene, _ptr(nodes), _ptr(tris)))
         return nodes, tris
+
+    def bvh_download_wide(self, scene: int):
+        """The 4-wide nodes traversal reads, as uint32 [n_nodes, 16]."""
+        info = self.scene_info(scene)
+        wide = np.zeros((info["n_nodes"], 16), dtype=np.uint32)
+        self._chk(self.lib.rtmc_bvh_download_wide(self.h, scene, _ptr(wide)))
+        return wide
 
     # ---------------------------------------------------------------- tables
     def load_tables(self, tab) -> int:

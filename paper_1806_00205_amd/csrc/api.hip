@@ -30,7 +30,8 @@ struct Scene {
   uint32_t flags = 0;
   DevBuf tris_in;  // compacted, caller order (freed after the build)
   DevBuf tris;     // Morton order
-  DevBuf nodes;
+  DevBuf nodes;    // binary LBVH (64 B per node)
+  DevBuf nodes4;   // quantized 4-wide nodes collapsed from it (64 B per node), what traversal reads
   int64_t n_nodes = 0;
   int built = 0, depth = 0;
   double build_ms = 0.0;
@@ -135,7 +136,7 @@ rtmc_status check_scene(rtmc_ctx* c, int32_t id, bool need_bvh) {
 
 DevScene dev_scene(const Scene& s) {
   DevScene d;
-  d.nodes = reinterpret_cast<const float4*>(s.nodes.p);
+  d.nodes = reinterpret_cast<const float4*>(s.nodes4.p);
   d.tris = reinterpret_cast<const float4*>(s.tris.p);
   for (int a = 0; a < 3; ++a) {
     d.lo[a] = (float)s.lo[a];
@@ -163,6 +164,10 @@ DevTables dev_tables(const Tables& t) {
 }
 
 int grid_of(const rtmc_ctx* c, const rtmc_launch_cfg& cfg) { return c->n_cu * cfg.wg_per_cu; }
+
+// Traversal stack entries a ray can need in a BVH of `depth` binary levels:
+// a 4-wide node spans two of them and pushes at most three children.
+int stack_need(int depth) { return 3 * ((depth + 1) / 2) + 2; }
 
 struct HostJob {
   int32_t scene;
@@ -247,7 +252,7 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins;
   const int ncnt = 2 * (kMaxGen + 2);
   int gdepth = kGlobalStack;
-  for (auto& j : jobs) gdepth = std::max(gdepth, c->scenes[j.scene].depth + 2);
+  for (auto& j : jobs) gdepth = std::max(gdepth, stack_need(c->scenes[j.scene].depth));
   bool multi = false;
   for (auto& j : jobs) multi = multi || j.scene != jobs[0].scene;
   multi = multi || jobs.size() > 1;
@@ -396,7 +401,7 @@ rtmc_status prepare_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   st = ensure(c, c->err_word, 16);
   if (st) return st;
   int gdepth = kGlobalStack;
-  for (auto& j : jobs) gdepth = std::max(gdepth, c->scenes[j.scene].depth + 2);
+  for (auto& j : jobs) gdepth = std::max(gdepth, stack_need(c->scenes[j.scene].depth));
   const size_t waves = (size_t)grid_of(c, cfg) * (cfg.block / 64);
   st = ensure(c, c->gstack, waves * gdepth * 64 * 4);
   if (st) return st;
@@ -433,7 +438,7 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
                                    (uint64_t)(uintptr_t)c->counters.p, (uint64_t)(uintptr_t)c->ppc.p,
                                    (uint64_t)(uintptr_t)c->gstack.p, (uint64_t)(uintptr_t)c->err_word.p, c->qcap};
       int gd = kGlobalStack;
-      for (auto& j : jobs) gd = std::max(gd, c->scenes[j.scene].depth + 2);
+      for (auto& j : jobs) gd = std::max(gd, stack_need(c->scenes[j.scene].depth));
       key.push_back((uint64_t)gd);
       bool multi = jobs.size() > 1;
       key.push_back(multi ? 1u : 0u);
@@ -585,6 +590,7 @@ void rtmc_destroy(rtmc_ctx* c) {
     dev_free(c, s.tris_in);
     dev_free(c, s.tris);
     dev_free(c, s.nodes);
+    dev_free(c, s.nodes4);
   }
   for (auto& t : c->tables) dev_free(c, t.buf);
   for (auto& g : c->srgs) {
@@ -708,7 +714,7 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
     return RTMC_OK;
   }
   const int64_t nn = std::max<int64_t>(n - 1, 1);
-  DevBuf tris, nodes, keys, vals, keys2, vals2, parent, flags, hist, depth;
+  DevBuf tris, nodes, nodes4, keys, vals, keys2, vals2, parent, flags, hist, depth;
   auto cleanup = [&]() {
     dev_free(c, keys);
     dev_free(c, vals);
@@ -719,19 +725,22 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
     dev_free(c, hist);
     dev_free(c, depth);
   };
-  if (ensure(c, tris, (size_t)n * 48) || ensure(c, nodes, (size_t)nn * 64) || ensure(c, keys, (size_t)n * 8) ||
+  if (ensure(c, tris, (size_t)n * 48) || ensure(c, nodes, (size_t)nn * 64) || ensure(c, nodes4, (size_t)nn * 64) ||
+      ensure(c, keys, (size_t)n * 8) ||
       ensure(c, vals, (size_t)n * 4) || ensure(c, keys2, (size_t)n * 8) || ensure(c, vals2, (size_t)n * 4) ||
       ensure(c, parent, (size_t)(nn + n) * 4) || ensure(c, flags, (size_t)nn * 4) ||
       ensure(c, hist, radix_hist_words(n) * 4) || ensure(c, depth, 16)) {
     cleanup();
     dev_free(c, tris);
     dev_free(c, nodes);
+    dev_free(c, nodes4);
     return RTMC_ENOMEM;
   }
   BvhBuild b;
   b.tris_in = reinterpret_cast<const float4*>(s.tris_in.p);
   b.tris_out = reinterpret_cast<float4*>(tris.p);
   b.nodes = reinterpret_cast<float4*>(nodes.p);
+  b.nodes4 = reinterpret_cast<float4*>(nodes4.p);
   b.keys = reinterpret_cast<uint64_t*>(keys.p);
   b.vals = reinterpret_cast<uint32_t*>(vals.p);
   b.keys_alt = reinterpret_cast<uint64_t*>(keys2.p);
@@ -757,11 +766,13 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
   if (e != hipSuccess) {
     dev_free(c, tris);
     dev_free(c, nodes);
+    dev_free(c, nodes4);
     return fail(c, RTMC_EDEVICE, "BVH build: %s", hipGetErrorString(e));
   }
   dev_free(c, s.tris_in);
   s.tris = tris;
   s.nodes = nodes;
+  s.nodes4 = nodes4;
   s.n_nodes = nn;
   s.depth = (int)d;
   s.build_ms = ms;
@@ -795,6 +806,17 @@ rtmc_status rtmc_bvh_download(rtmc_ctx* c, int32_t scene_id, float* nodes, float
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (nodes && s.n_nodes) HIPCHK(c, hipMemcpy(nodes, s.nodes.p, (size_t)s.n_nodes * 64, hipMemcpyDeviceToHost));
   if (tris && s.n_tris) HIPCHK(c, hipMemcpy(tris, s.tris.p, (size_t)s.n_tris * 48, hipMemcpyDeviceToHost));
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_bvh_download_wide(rtmc_ctx* c, int32_t scene_id, uint32_t* wide) {
+  rtmc_status st = check_scene(c, scene_id, true);
+  if (st) return st;
+  if (!wide) return fail(c, RTMC_EINVAL, "null pointer");
+  const Scene& s = c->scenes[scene_id];
+  HIPCHK(c, hipSetDevice(c->device));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (s.n_nodes) HIPCHK(c, hipMemcpy(wide, s.nodes4.p, (size_t)s.n_nodes * 64, hipMemcpyDeviceToHost));
   return RTMC_OK;
 }
 
@@ -920,10 +942,12 @@ rtmc_status rtmc_first_hit(rtmc_ctx* c, int32_t scene_id, const float* rays, int
   if (n == 0) return RTMC_OK;
   HIPCHK(c, hipSetDevice(c->device));
   const Scene& s = c->scenes[scene_id];
-  const int gdepth = std::max(kGlobalStack, s.depth + 2);
+  const int gdepth = std::max(kGlobalStack, stack_need(s.depth));
   const int block = c->cfg.block;
   const int grid = grid_of(c, c->cfg);
   const size_t waves = (size_t)grid * (block / 64);
+  // the 32-bit work counter may run past n by one block claim per wave
+  if ((uint64_t)n + (uint64_t)waves * kClaimMax > 0xFFFFFFF0ull) return fail(c, RTMC_EINVAL, "too many rays");
   st = ensure(c, c->gstack, waves * gdepth * 64 * 4);
   if (st) return st;
   // job 0 carries the scene; hit records go to scratch except code and t

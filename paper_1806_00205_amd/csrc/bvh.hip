@@ -300,6 +300,116 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
   return hipGetLastError();
 }
 
+// 4-wide node of binary internal node i: i's children, each internal child
+// replaced by its own two children (leaves stay as they are), so 2 to 4
+// slots.  Traversal starts at node 0 and only ever reaches the nodes of even
+// binary depth; the others are built too (one thread per node, no depth
+// bookkeeping) and never read.
+//
+// A node is 64 bytes (four float4): the origin o of the union box and three
+// power-of-two scales s = 2^e (e biased by 127 in bytes 0..2 of word 3);
+// the four child links (kEmpty: unused slot); the child boxes quantized to
+// bytes, lo_x[4] lo_y[4] lo_z[4] hi_x[4] in float4 2 and hi_y[4] hi_z[4] in
+// float4 3.  A child's box decodes as fmaf(q, s, o) per bound -- the very
+// operation traversal performs -- and the builder moves each code outwards
+// until that decoded box contains the exact one, so traversal stays
+// conservative.
+__device__ inline void load_node(const float4* nodes, int64_t i, float b0[6], float b1[6], uint32_t& l0,
+                                 uint32_t& l1) {
+  const float4 n0 = nodes[4 * i], n1 = nodes[4 * i + 1], n2 = nodes[4 * i + 2], n3 = nodes[4 * i + 3];
+  b0[0] = n0.x;
+  b0[1] = n0.y;
+  b0[2] = n0.z;
+  b0[3] = n0.w;
+  b0[4] = n1.x;
+  b0[5] = n1.y;
+  b1[0] = n1.z;
+  b1[1] = n1.w;
+  b1[2] = n2.x;
+  b1[3] = n2.y;
+  b1[4] = n2.z;
+  b1[5] = n2.w;
+  l0 = __float_as_uint(n3.x);
+  l1 = __float_as_uint(n3.y);
+}
+
+__device__ inline float pow2f(int e) { return __uint_as_float((uint32_t)(e + 127) << 23); }
+
+// Power-of-two scale for an axis of extent w (>= 0): 255 steps cover w.
+__device__ inline int axis_exp(float o, float hi) {
+  const float w = fmaxf(hi - o, 1e-30f);
+  int e;
+  frexpf(w / 255.0f, &e);  // w / 255 < 2^e
+  e = max(-126, min(127, e));
+  while (e < 127 && fmaf(255.0f, pow2f(e), o) < hi) ++e;
+  return e;
+}
+
+__device__ inline uint32_t q_lo(float v, float o, float sc) {
+  int q = (int)floorf((v - o) / sc);
+  q = max(0, min(255, q));
+  while (q > 0 && fmaf((float)q, sc, o) > v) --q;
+  return (uint32_t)q;
+}
+
+__device__ inline uint32_t q_hi(float v, float o, float sc) {
+  int q = (int)ceilf((v - o) / sc);
+  q = max(0, min(255, q));
+  while (q < 255 && fmaf((float)q, sc, o) < v) ++q;
+  return (uint32_t)q;
+}
+
+__global__ void k_collapse4(const float4* __restrict__ nodes, int64_t nn, float4* __restrict__ nodes4) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nn) return;
+  float b[4][6];
+  uint32_t c[4];
+  int k = 0;
+  float cb[2][6];
+  uint32_t cl[2];
+  load_node(nodes, i, cb[0], cb[1], cl[0], cl[1]);
+  for (int side = 0; side < 2; ++side) {
+    if (cl[side] & kLeafBit) {
+      for (int q = 0; q < 6; ++q) b[k][q] = cb[side][q];
+      c[k++] = cl[side];
+    } else {
+      float g0[6], g1[6];
+      uint32_t m0, m1;
+      load_node(nodes, cl[side], g0, g1, m0, m1);
+      for (int q = 0; q < 6; ++q) b[k][q] = g0[q];
+      c[k++] = m0;
+      for (int q = 0; q < 6; ++q) b[k][q] = g1[q];
+      c[k++] = m1;
+    }
+  }
+  const int used = k;
+  for (; k < 4; ++k) c[k] = kEmpty;
+  float o[3], sc[3];
+  int e[3];
+  for (int a = 0; a < 3; ++a) {
+    float lo = b[0][a], hi = b[0][3 + a];
+    for (int j = 1; j < used; ++j) {
+      lo = fminf(lo, b[j][a]);
+      hi = fmaxf(hi, b[j][3 + a]);
+    }
+    o[a] = lo;
+    e[a] = axis_exp(lo, hi);
+    sc[a] = pow2f(e[a]);
+  }
+  uint32_t ql[3] = {0u, 0u, 0u}, qh[3] = {0u, 0u, 0u};
+  for (int j = 0; j < used; ++j)
+    for (int a = 0; a < 3; ++a) {
+      ql[a] |= q_lo(b[j][a], o[a], sc[a]) << (8 * j);
+      qh[a] |= q_hi(b[j][3 + a], o[a], sc[a]) << (8 * j);
+    }
+  float4* out = nodes4 + 4 * i;
+  const uint32_t ex = (uint32_t)(e[0] + 127) | ((uint32_t)(e[1] + 127) << 8) | ((uint32_t)(e[2] + 127) << 16);
+  out[0] = make_float4(o[0], o[1], o[2], __uint_as_float(ex));
+  out[1] = make_float4(__uint_as_float(c[0]), __uint_as_float(c[1]), __uint_as_float(c[2]), __uint_as_float(c[3]));
+  out[2] = make_float4(__uint_as_float(ql[0]), __uint_as_float(ql[1]), __uint_as_float(ql[2]), __uint_as_float(qh[0]));
+  out[3] = make_float4(__uint_as_float(qh[1]), __uint_as_float(qh[2]), 0.0f, 0.0f);
+}
+
 hipError_t build_bvh(BvhBuild& b, hipStream_t s) {
   const int32_t n = b.n;
   if (n <= 0) return hipSuccess;
@@ -315,6 +425,7 @@ hipError_t build_bvh(BvhBuild& b, hipStream_t s) {
   k_gather_tris<<<g, TB, 0, s>>>(b.tris_in, perm, n, b.tris_out);
   if (n == 1) {
     k_single<<<1, 1, 0, s>>>(b.tris_out, b.nodes);
+    k_collapse4<<<1, 64, 0, s>>>(b.nodes, 1, b.nodes4);
     return hipGetLastError();
   }
   const int gi = (n - 1 + TB - 1) / TB;
@@ -325,6 +436,7 @@ hipError_t build_bvh(BvhBuild& b, hipStream_t s) {
   if (e != hipSuccess) return e;
   k_refit<<<g, TB, 0, s>>>(b.tris_out, n, b.nodes, b.parent, b.flags);
   k_depth<<<g, TB, 0, s>>>(b.parent, n, b.depth);
+  k_collapse4<<<gi, TB, 0, s>>>(b.nodes, (int64_t)(n - 1), b.nodes4);
   return hipGetLastError();
 }
 

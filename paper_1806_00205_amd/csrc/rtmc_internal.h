@@ -19,6 +19,7 @@
 namespace rtmc {
 
 constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // unused child slot of a 4-wide node
 constexpr int kMaxGen = 10;
 constexpr int kWrapMax = 10000;
 constexpr float kSpawnEps = 1e-4f;
@@ -54,7 +55,7 @@ enum TallySlot {
 constexpr double kFixScale = 1048576.0;  // 2^20
 
 struct DevScene {
-  const float4* nodes;
+  const float4* nodes;  // quantized 4-wide nodes, 4 float4 each
   const float4* tris;
   float lo[3], hi[3];
   int32_t n_tris;
@@ -205,7 +206,8 @@ hipError_t mlp_infer(const MlpInfer& p, hipStream_t s);
 struct BvhBuild {
   const float4* tris_in;  // [3 n] unsorted, compacted
   float4* tris_out;       // [3 n] sorted
-  float4* nodes;          // [4 max(n - 1, 1)]
+  float4* nodes;          // [4 max(n - 1, 1)] binary nodes
+  float4* nodes4;         // [4 max(n - 1, 1)] quantized 4-wide nodes (traversal)
   uint64_t* keys;         // [n]
   uint32_t* vals;         // [n]
   uint64_t* keys_alt;     // [n]

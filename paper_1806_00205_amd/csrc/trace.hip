@@ -399,70 +399,125 @@ __device__ inline void seg_begin(Trav& s, const DevScene& sc) {
   s.sp = 0;
 }
 
-// One node of the traversal.  Returns true when the segment's traversal has
-// finished (stack empty).  The stack keeps its first sd entries in LDS (lstk,
-// stride 64 words) and the rest in global memory (gstk, stride 64 words).
+__device__ inline void tri_candidate(Trav& s, const LaneScene& L, uint32_t k, uint32_t& tests) {
+  const GAS f4v* T = (const GAS f4v*)L.tris + 3 * (size_t)k;
+  const f4v a = T[0], b = T[1], c = T[2];
+  ++tests;
+  float t, b1, b2;
+  if (tri_test(s.r, a, b, c, s.t, t, b1, b2)) {
+    const int32_t oid = (int32_t)__float_as_uint(a.w);
+    // closest hit; equal distances go to the lower caller index
+    if (t < s.t || (t == s.t && oid < s.oid)) {
+      s.t = t;
+      s.b1 = b1;
+      s.b2 = b2;
+      s.idx = (int32_t)k;
+      s.oid = oid;
+    }
+  }
+}
+
+// Push onto the lane's stack: the first sd entries in LDS (lstk, stride 64
+// words), the rest in global memory (gstk, stride 64 words).
+__device__ inline bool push(Trav& s, LAS uint32_t* lstk, GAS uint32_t* gstk, int sd, int gd, uint32_t v) {
+  if (s.sp < sd)
+    lstk[s.sp * 64] = v;
+  else if (s.sp < sd + gd)
+    gstk[(s.sp - sd) * 64] = v;
+  else
+    return false;
+  ++s.sp;
+  return true;
+}
+
+__device__ inline void cswap(float& da, uint32_t& na, float& db, uint32_t& nb) {
+  const bool sw = db < da;
+  const float d = sw ? db : da;
+  const uint32_t n = sw ? nb : na;
+  db = sw ? da : db;
+  nb = sw ? na : nb;
+  da = d;
+  na = n;
+}
+
+// Byte j of a quantized bound, decoded exactly as the builder checked it.
+__device__ inline float dq(uint32_t w, int j, float sc, float o) {
+  return fmaf((float)((w >> (8 * j)) & 0xFFu), sc, o);
+}
+
+// One 4-wide node of the traversal.  Returns true when the segment's
+// traversal has finished (stack empty).  Leaf children whose boxes the ray
+// enters are tested at once (which can shorten the ray before the inner
+// children are kept); the inner children hit are visited nearest first, the
+// others pushed farthest first so they pop in order of entry distance.
 __device__ inline bool trav_step(Trav& s, const LaneScene& L, LAS uint32_t* lstk, GAS uint32_t* gstk, int sd,
                                  int gd, uint32_t& visits, uint32_t& tests, bool& ovf) {
   const GAS f4v* N = (const GAS f4v*)L.nodes + 4 * (size_t)s.node;
-  const f4v n0 = N[0], n1 = N[1], n2 = N[2], n3 = N[3];
+  const f4v q0 = N[0], lk = N[1], q2 = N[2], q3 = N[3];
   ++visits;
-  float tl, tr;
-  bool hl = box_test(s.r, n0.x, n0.y, n0.z, n0.w, n1.x, n1.y, s.t, tl);
-  bool hr = box_test(s.r, n1.z, n1.w, n2.x, n2.y, n2.z, n2.w, s.t, tr);
-  const uint32_t cl = __float_as_uint(n3.x), cr = __float_as_uint(n3.y);
-#pragma unroll
-  for (int side = 0; side < 2; ++side) {
-    const bool leafhit = side == 0 ? (hl && (cl & kLeafBit)) : (hr && (cr & kLeafBit));
-    if (leafhit) {
-      const uint32_t k = (side == 0 ? cl : cr) & ~kLeafBit;
-      const GAS f4v* T = (const GAS f4v*)L.tris + 3 * (size_t)k;
-      const f4v a = T[0], b = T[1], c = T[2];
-      ++tests;
-      float t, b1, b2;
-      if (tri_test(s.r, a, b, c, s.t, t, b1, b2)) {
-        const int32_t oid = (int32_t)__float_as_uint(a.w);
-        // closest hit; equal distances go to the lower caller index
-        if (t < s.t || (t == s.t && oid < s.oid)) {
-          s.t = t;
-          s.b1 = b1;
-          s.b2 = b2;
-          s.idx = (int32_t)k;
-          s.oid = oid;
-        }
-      }
-      if (side == 0)
-        hl = false;
-      else
-        hr = false;
-    }
+  const uint32_t ex = __float_as_uint(q0.w);
+  const float sx = __uint_as_float((ex & 0xFFu) << 23), sy = __uint_as_float(((ex >> 8) & 0xFFu) << 23),
+              sz = __uint_as_float(((ex >> 16) & 0xFFu) << 23);
+  const uint32_t qlx = __float_as_uint(q2.x), qly = __float_as_uint(q2.y), qlz = __float_as_uint(q2.z),
+                 qhx = __float_as_uint(q2.w), qhy = __float_as_uint(q3.x), qhz = __float_as_uint(q3.y);
+#define CHILD_BOX(j)                                                                                      \
+  dq(qlx, j, sx, q0.x), dq(qly, j, sy, q0.y), dq(qlz, j, sz, q0.z), dq(qhx, j, sx, q0.x), dq(qhy, j, sy, q0.y), \
+      dq(qhz, j, sz, q0.z)
+  float d0, d1, d2, d3;
+  uint32_t c0 = __float_as_uint(lk.x), c1 = __float_as_uint(lk.y), c2 = __float_as_uint(lk.z),
+           c3 = __float_as_uint(lk.w);
+  bool h0 = box_test(s.r, CHILD_BOX(0), s.t, d0) && c0 != kEmpty;
+  bool h1 = box_test(s.r, CHILD_BOX(1), s.t, d1) && c1 != kEmpty;
+  bool h2 = box_test(s.r, CHILD_BOX(2), s.t, d2) && c2 != kEmpty;
+  bool h3 = box_test(s.r, CHILD_BOX(3), s.t, d3) && c3 != kEmpty;
+#undef CHILD_BOX
+  if (h0 && (c0 & kLeafBit)) {
+    tri_candidate(s, L, c0 & ~kLeafBit, tests);
+    h0 = false;
   }
-  if (hl && hr) {
-    const bool lnear = tl <= tr;
-    const uint32_t farc = lnear ? cr : cl;
-    s.node = lnear ? cl : cr;
-    if (s.sp < sd) {
-      lstk[s.sp * 64] = farc;
-    } else if (s.sp < sd + gd) {
-      gstk[(s.sp - sd) * 64] = farc;
-    } else {
+  if (h1 && (c1 & kLeafBit)) {
+    tri_candidate(s, L, c1 & ~kLeafBit, tests);
+    h1 = false;
+  }
+  if (h2 && (c2 & kLeafBit)) {
+    tri_candidate(s, L, c2 & ~kLeafBit, tests);
+    h2 = false;
+  }
+  if (h3 && (c3 & kLeafBit)) {
+    tri_candidate(s, L, c3 & ~kLeafBit, tests);
+    h3 = false;
+  }
+  // inner children entered before the (possibly shortened) closest hit
+  d0 = h0 && d0 <= s.t ? d0 : INFINITY;
+  d1 = h1 && d1 <= s.t ? d1 : INFINITY;
+  d2 = h2 && d2 <= s.t ? d2 : INFINITY;
+  d3 = h3 && d3 <= s.t ? d3 : INFINITY;
+  const int cnt = (d0 < INFINITY) + (d1 < INFINITY) + (d2 < INFINITY) + (d3 < INFINITY);
+  if (cnt == 0) {
+    if (s.sp == 0) return true;
+    --s.sp;
+    s.node = s.sp < sd ? lstk[s.sp * 64] : gstk[(s.sp - sd) * 64];
+    return false;
+  }
+  if (cnt > 1) {
+    // sorting network on (distance, child), ascending; misses sort last
+    cswap(d0, c0, d1, c1);
+    cswap(d2, c2, d3, c3);
+    cswap(d0, c0, d2, c2);
+    cswap(d1, c1, d3, c3);
+    cswap(d1, c1, d2, c2);
+    bool ok = true;
+    if (cnt >= 4) ok = ok && push(s, lstk, gstk, sd, gd, c3);
+    if (cnt >= 3) ok = ok && push(s, lstk, gstk, sd, gd, c2);
+    ok = ok && push(s, lstk, gstk, sd, gd, c1);
+    if (!ok) {
       ovf = true;
       return true;
     }
-    ++s.sp;
+    s.node = c0;
     return false;
   }
-  if (hl) {
-    s.node = cl;
-    return false;
-  }
-  if (hr) {
-    s.node = cr;
-    return false;
-  }
-  if (s.sp == 0) return true;
-  --s.sp;
-  s.node = s.sp < sd ? lstk[s.sp * 64] : gstk[(s.sp - sd) * 64];
+  s.node = d0 < INFINITY ? c0 : (d1 < INFINITY ? c1 : (d2 < INFINITY ? c2 : c3));
   return false;
 }
 

@@ -84,6 +84,84 @@ def _check_bvh(nodes, tris, n):
         assert seen_node[0] == 0 and np.all(seen_node[1:] == 1)
 
 
+def _decode(q, s, o):
+    """fmaf(q, s, o) in FP32: q * s is exact (byte times a power of two) and
+    its sum with an FP32 origin is exact in FP64 here, so one rounding to
+    FP32 reproduces the fused operation."""
+    return np.float32(np.float64(q) * np.float64(s) + np.float64(o))
+
+
+def _check_wide(wide, nodes, tris, n):
+    """Quantized 4-wide nodes against the binary tree they are collapsed from:
+    node i holds the children of binary node i with inner children replaced by
+    theirs; every decoded box contains its child's exact box; the nodes reached
+    from node 0 reference every triangle exactly once."""
+    links = nodes[:, 12:14].view(np.uint32)
+    boxes = nodes[:, :12].reshape(-1, 2, 6)
+    tb = tris.reshape(-1, 3, 4)[:, :, :3]
+    tri_box = np.concatenate([tb.min(axis=1), tb.max(axis=1)], axis=1)
+    leaf_bit = np.uint32(0x80000000)
+    empty = np.uint32(0xFFFFFFFF)
+
+    def slots_of(i):
+        out = []
+        for side in range(2):
+            link = links[i, side]
+            if link & leaf_bit:
+                out.append((link, boxes[i, side]))
+            else:
+                for s2 in range(2):
+                    out.append((links[link, s2], boxes[link, s2]))
+        return out
+
+    seen = np.zeros(n, dtype=np.int64)
+    stack = [0]
+    while stack:
+        i = stack.pop()
+        w = wide[i]
+        o = w[0:3].view(np.float32)
+        sc = [np.float32(2.0) ** (int((w[3] >> (8 * a)) & 0xFF) - 127) for a in range(3)]
+        expect = slots_of(i)
+        assert 2 <= len(expect) <= 4
+        for j in range(4):
+            link = w[4 + j]
+            if j >= len(expect):
+                assert link == empty
+                continue
+            el, ebox = expect[j]
+            assert link == el
+            q = [(w[8 + k] >> np.uint32(8 * j)) & np.uint32(0xFF) for k in range(6)]
+            lo = [_decode(q[a], sc[a], o[a]) for a in range(3)]
+            hi = [_decode(q[3 + a], sc[a], o[a]) for a in range(3)]
+            assert np.all(np.array(lo) <= ebox[:3]) and np.all(np.array(hi) >= ebox[3:]), (i, j)
+            # quantisation keeps boxes tight: at most two steps of 2^e beyond the exact bound
+            for a in range(3):
+                assert ebox[a] - lo[a] <= 2 * sc[a] and hi[a] - ebox[3 + a] <= 2 * sc[a]
+            if link & leaf_bit:
+                k = int(link & ~leaf_bit)
+                assert np.all(ebox[:3] <= tri_box[k, :3]) and np.all(ebox[3:] >= tri_box[k, 3:])
+                seen[k] += 1
+            else:
+                stack.append(int(link))
+    assert np.all(seen == 1) if n > 1 else seen[0] == 2
+
+
+@pytest.mark.parametrize("n,p,seed", [(8, 0.5, 1), (16, 0.5, 0), (24, 0.7, 2)])
+def test_wide_nodes(ctx, n, p, seed):
+    m = fg.make_grf_foam(n, p, 2.0, seed=seed)
+    sid = ctx.load_scene(m)
+    nodes, tris = ctx.bvh_download(sid)
+    _check_wide(ctx.bvh_download_wide(sid), nodes, tris, m.n_tris)
+
+
+def test_wide_node_of_one_triangle(ctx):
+    m = fg.flat_plane()
+    sid = ctx.load_mesh(m.verts, m.tris[:1], m.box_lo, m.box_hi, m.flags)
+    ctx.build_bvh(sid)
+    nodes, tris = ctx.bvh_download(sid)
+    _check_wide(ctx.bvh_download_wide(sid), nodes, tris, 1)
+
+
 @pytest.mark.parametrize("n,p,seed", [(8, 0.5, 1), (16, 0.5, 0), (24, 0.7, 2)])
 def test_bvh_structure(ctx, n, p, seed):
     m = fg.make_grf_foam(n, p, 2.0, seed=seed)
