@@ -471,21 +471,20 @@ __device__ inline bool trav_step(Trav& s, const LaneScene& L, LAS uint32_t* lstk
   bool h2 = box_test(s.r, CHILD_BOX(2), s.t, d2) && c2 != kEmpty;
   bool h3 = box_test(s.r, CHILD_BOX(3), s.t, d3) && c3 != kEmpty;
 #undef CHILD_BOX
-  if (h0 && (c0 & kLeafBit)) {
-    tri_candidate(s, L, c0 & ~kLeafBit, tests);
-    h0 = false;
-  }
-  if (h1 && (c1 & kLeafBit)) {
-    tri_candidate(s, L, c1 & ~kLeafBit, tests);
-    h1 = false;
-  }
-  if (h2 && (c2 & kLeafBit)) {
-    tri_candidate(s, L, c2 & ~kLeafBit, tests);
-    h2 = false;
-  }
-  if (h3 && (c3 & kLeafBit)) {
-    tri_candidate(s, L, c3 & ~kLeafBit, tests);
-    h3 = false;
+  // leaf children hit: one loop over the lane's own leaves, so the wave runs
+  // as many triangle tests as its busiest lane rather than one per slot
+  // that any lane needs
+  uint32_t lm = (uint32_t)(h0 && (c0 & kLeafBit)) | ((uint32_t)(h1 && (c1 & kLeafBit)) << 1) |
+                ((uint32_t)(h2 && (c2 & kLeafBit)) << 2) | ((uint32_t)(h3 && (c3 & kLeafBit)) << 3);
+  h0 = h0 && !(lm & 1u);
+  h1 = h1 && !(lm & 2u);
+  h2 = h2 && !(lm & 4u);
+  h3 = h3 && !(lm & 8u);
+  while (lm) {
+    const uint32_t j = (uint32_t)__builtin_ctz(lm);
+    lm &= lm - 1u;
+    const uint32_t cj = j == 0 ? c0 : (j == 1 ? c1 : (j == 2 ? c2 : c3));
+    tri_candidate(s, L, cj & ~kLeafBit, tests);
   }
   // inner children entered before the (possibly shortened) closest hit
   d0 = h0 && d0 <= s.t ? d0 : INFINITY;
