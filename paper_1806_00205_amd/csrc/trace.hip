@@ -1059,47 +1059,88 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
 // Sum over the chunk's primaries of (escape count)^2 for the yield's standard
 // error, and the optional per-primary output.  Each wave takes a contiguous
 // slice of the chunk, so its items change job rarely: lanes accumulate in
-// registers and the wave reduces once per job it touches.
-__global__ void k_chunk_reduce(const DevJob* jobs, int32_t j_lo, int32_t j_hi, const uint32_t* __restrict__ ppc,
-                               uint32_t n, uint64_t chunk_lo) {
+// registers and the wave reduces once per job it touches.  The workgroup's
+// waves then combine their sums for the job of its last item in LDS, so a
+// single-job chunk costs one atomic per workgroup on the job's counter.
+__global__ __launch_bounds__(256) void k_chunk_reduce(const DevJob* jobs, int32_t j_lo, int32_t j_hi,
+                                                      const uint32_t* __restrict__ ppc, uint32_t n,
+                                                      uint64_t chunk_lo) {
+  __shared__ unsigned long long s_sum[4];
+  __shared__ int s_job[4];
   const uint32_t lane = lane_id();
+  const uint32_t w = threadIdx.x >> 6;
   const uint32_t wpb = blockDim.x >> 6;
   const uint32_t total_waves = gridDim.x * wpb;
   const uint64_t per = (((uint64_t)n + total_waves - 1) / total_waves + 63) & ~63ull;
-  const uint64_t b = (uint64_t)(blockIdx.x * wpb + (threadIdx.x >> 6)) * per;
-  if (b >= n) return;
-  const uint32_t e = (uint32_t)(b + per < n ? b + per : n);
-  int tag = find_job(jobs, j_lo, j_hi, chunk_lo + b);
-  uint64_t end = tag < j_hi ? gp(jobs)[tag + 1].gbase : ~0ull;
+  const uint64_t b = (uint64_t)(blockIdx.x * wpb + w) * per;
+  int tag = -1;
   unsigned long long acc = 0;
-  for (uint32_t i0 = (uint32_t)b; i0 < e; i0 += 64) {
-    const uint32_t i = i0 + lane;
-    const bool ok = i < e;
-    const uint64_t g = chunk_lo + i;
-    const uint32_t c = ok ? gp(ppc)[i] : 0u;
-    const uint64_t g_last = chunk_lo + (i0 + 63 < e ? i0 + 63 : e - 1);
-    if (g_last < end) {
-      acc += (unsigned long long)c * c;
-      uint32_t* pp = gp(jobs)[tag].pp_escaped;
-      if (pp && ok) gp(pp)[g - gp(jobs)[tag].gbase] = c;
-    } else {
-      // the wave's items reach into later jobs
-      const int j = ok ? find_job(jobs, tag, j_hi, g) : tag;
-      if (j == tag)
-        acc += (unsigned long long)c * c;
-      else if (c)
-        gadd(&jobs[j].tally[T_C2], (unsigned long long)c * c);
-      uint32_t* pp = gp(jobs)[j].pp_escaped;
-      if (pp && ok) gp(pp)[g - gp(jobs)[j].gbase] = c;
-      const unsigned long long sum = wave_sum(acc);
-      if (lane == 0 && sum) gadd(&jobs[tag].tally[T_C2], sum);
-      acc = 0;
-      tag = find_job(jobs, tag, j_hi, g_last);
-      end = tag < j_hi ? gp(jobs)[tag + 1].gbase : ~0ull;
+  if (b < n) {
+    const uint32_t e = (uint32_t)(b + per < n ? b + per : n);
+    tag = find_job(jobs, j_lo, j_hi, chunk_lo + b);
+    uint64_t end = tag < j_hi ? gp(jobs)[tag + 1].gbase : ~0ull;
+    uint32_t* pp = gp(jobs)[tag].pp_escaped;
+    uint64_t pbase = gp(jobs)[tag].gbase;
+    for (uint32_t i4 = (uint32_t)b; i4 < e; i4 += 256) {
+      // four loads in flight per lane, then the items in order
+      uint32_t cv[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i = i4 + 64u * k + lane;
+        cv[k] = i < e ? gp(ppc)[i] : 0u;
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const uint32_t i0 = i4 + 64u * k;
+        if (i0 >= e) break;
+        const uint32_t i = i0 + lane;
+        const bool ok = i < e;
+        const uint64_t g = chunk_lo + i;
+        const uint32_t c = cv[k];
+        const uint64_t g_last = chunk_lo + (i0 + 63 < e ? i0 + 63 : e - 1);
+        if (g_last < end) {
+          acc += (unsigned long long)c * c;
+          if (pp && ok) gp(pp)[g - pbase] = c;
+        } else {
+          // the wave's items reach into later jobs
+          const int j = ok ? find_job(jobs, tag, j_hi, g) : tag;
+          if (j == tag)
+            acc += (unsigned long long)c * c;
+          else if (c)
+            gadd(&jobs[j].tally[T_C2], (unsigned long long)c * c);
+          uint32_t* pj = gp(jobs)[j].pp_escaped;
+          if (pj && ok) gp(pj)[g - gp(jobs)[j].gbase] = c;
+          const unsigned long long sum = wave_sum(acc);
+          if (lane == 0 && sum) gadd(&jobs[tag].tally[T_C2], sum);
+          acc = 0;
+          tag = find_job(jobs, tag, j_hi, g_last);
+          end = tag < j_hi ? gp(jobs)[tag + 1].gbase : ~0ull;
+          pp = gp(jobs)[tag].pp_escaped;
+          pbase = gp(jobs)[tag].gbase;
+        }
+      }
     }
   }
   const unsigned long long sum = wave_sum(acc);
-  if (lane == 0 && sum) gadd(&jobs[tag].tally[T_C2], sum);
+  if (lane == 0) {
+    s_sum[w] = sum;
+    s_job[w] = tag;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // waves with the same final job add together (the slices are in order)
+    unsigned long long run = 0;
+    int cur = -1;
+    for (uint32_t k = 0; k < wpb; ++k) {
+      if (s_job[k] != cur) {
+        if (cur >= 0 && run) gadd(&jobs[cur].tally[T_C2], run);
+        cur = s_job[k];
+        run = 0;
+      }
+      run += s_sum[k];
+    }
+    if (cur >= 0 && run) gadd(&jobs[cur].tally[T_C2], run);
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, size_t n) {
@@ -1193,7 +1234,7 @@ hipError_t launch_chunk_reduce(const DevJob* jobs, int32_t j_lo, int32_t j_hi, c
                                uint64_t chunk_lo, hipStream_t s) {
   if (n == 0) return hipSuccess;
   int grid = (int)((n + 255) / 256);
-  if (grid > 4096) grid = 4096;
+  if (grid > 1024) grid = 1024;
   k_chunk_reduce<<<grid, 256, 0, s>>>(jobs, j_lo, j_hi, ppc, n, chunk_lo);
   return hipGetLastError();
 }
