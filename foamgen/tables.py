@@ -38,6 +38,8 @@ class Tables:
     cdf_F: np.ndarray  # float32 [n_cdf]
     Ec: float = 10.0
     meta: dict = field(default_factory=dict)
+    esee: np.ndarray | None = None  # float32 [n_E, n_theta]: E_SEE for the paper's emission rule
+    emission: int = 0  # 0: energies from the CDF, cosine law; 1: the paper's one/two-daughter rule
 
     @property
     def n_E(self) -> int:
@@ -76,6 +78,14 @@ def paper_w_yield(E, alpha_deg):
     return g
 
 
+def paper_w_esee(E, alpha_deg):
+    """Secondary energy fit E_SEE(E, alpha) of section 2.2 (flat tungsten), in eV;
+    alpha in degrees (the fit's sin(E) takes E as printed)."""
+    E = np.asarray(E, dtype=np.float64)
+    a = np.asarray(alpha_deg, dtype=np.float64)
+    return 0.195 * E + 1.6e-4 * E * E + 0.148 * a * np.sin(E) + 3.44e-15 * E * a ** 7 - 6.54
+
+
 def ce_cdf(E, phi=4.5):
     """Chung-Everhart CDF for density proportional to E / (E + phi)^4."""
     s = phi / (np.asarray(E, dtype=np.float64) + phi)
@@ -105,21 +115,34 @@ def _ce_table(n_cdf: int, E_top: float, phi: float):
 
 def make_tables(kind: str = "vaughan", n_E: int = 128, n_theta: int = 46, E_min: float = 1.0,
                 E_max: float = 1.0e4, n_cdf: int = 512, phi: float = 4.5, Ec: float = 10.0,
-                const: float = 1.0, dmax: float = 1.4, Emax: float = 650.0) -> Tables:
+                const: float = 1.0, dmax: float = 1.4, Emax: float = 650.0, emission: str | None = None,
+                esee_const: float | None = None) -> Tables:
+    """Flat-surface tables.  kind 'paper_w' is the paper's own tungsten fits
+    (Eq. seey and E_SEE) with the paper's emission rule; emission='paper'
+    selects that rule for any kind (E_SEE from the fit, or esee_const)."""
     Eax = np.exp(np.linspace(np.log(E_min), np.log(E_max), n_E))
     tax = np.linspace(0.0, 90.0, n_theta)
     if kind == "vaughan":
         y = vaughan_yield(Eax[:, None], tax[None, :], dmax=dmax, Emax=Emax)
     elif kind == "paper_w":
         y = np.clip(paper_w_yield(Eax[:, None], tax[None, :]), 0.0, 6.99)
+        emission = "paper" if emission is None else emission
     elif kind == "constant":
         y = np.full((n_E, n_theta), const)
     else:
         raise ValueError(kind)
     cE, cF = _ce_table(n_cdf, E_max, phi)
+    esee = None
+    if emission == "paper":
+        es = (np.full((n_E, n_theta), esee_const) if esee_const is not None
+              else paper_w_esee(Eax[:, None], tax[None, :]))
+        esee = np.ascontiguousarray(es, dtype=np.float32)
+    elif emission not in (None, "spectrum"):
+        raise ValueError(emission)
     return Tables(yld=np.ascontiguousarray(y, dtype=np.float32), E_min=E_min, E_max=E_max,
                   cdf_E=cE, cdf_F=cF, Ec=Ec,
-                  meta=dict(kind=kind, phi=phi, const=const, dmax=dmax, Emax=Emax))
+                  meta=dict(kind=kind, phi=phi, const=const, dmax=dmax, Emax=Emax),
+                  esee=esee, emission=1 if emission == "paper" else 0)
 
 
 def bilinear_reference(t: Tables, E, alpha_deg):

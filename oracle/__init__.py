@@ -52,7 +52,7 @@ class _MeshIn(C.Structure):
 class _TablesIn(C.Structure):
     _fields_ = [("yld", C.c_void_p), ("n_E", C.c_int32), ("n_theta", C.c_int32), ("E_min", C.c_double),
                 ("E_max", C.c_double), ("cdf_E", C.c_void_p), ("cdf_F", C.c_void_p), ("n_cdf", C.c_int32),
-                ("Ec", C.c_double)]
+                ("Ec", C.c_double), ("esee", C.c_void_p), ("emission", C.c_int32)]
 
 
 class _Job(C.Structure):
@@ -154,6 +154,10 @@ def _tables_in(tab, keep):
     ti.cdf_F = _ptr(cf)
     ti.n_cdf = ce.shape[0]
     ti.Ec = tab.Ec
+    ti.emission = int(getattr(tab, "emission", 0))
+    es = getattr(tab, "esee", None)
+    if es is not None:
+        ti.esee = _ptr(keep.add(np.ascontiguousarray(es, dtype=np.float32)))
     return ti
 
 

@@ -40,6 +40,15 @@
  *   - directions: cosine law about the element normal (sin^2 beta uniform),
  *     azimuth uniform; frame by the branchless construction of Duff et al.
  *     (JCGT 2017).
+ *   - the paper's own emission rule (section 2.2, emission mode 1): a lone
+ *     daughter gets E_SEE(E, alpha) and a cosine-law direction; a pair
+ *     shares one xi: E1 = E_SEE sqrt(xi) at sin^2 beta1 = xi, E2 = cos^2
+ *     beta1 E_SEE at beta2 = pi/2 - beta1; azimuths uniform and independent.
+ *     More than two daughters (the fit exceeds 2 only outside 50-1000 eV)
+ *     come in further pairs, an odd one last by the lone rule.  Each
+ *     energy is clamped to [0, energy still available] (the fits go
+ *     negative at low E and above the parent at high E).  Draw 2 + d serves
+ *     daughter d (xi of a pair from its first daughter's draw, word 1).
  *   - E_c only stops re-emission at a hit; every daughter is traced.
  *   - a ray of generation max_gen that hits is absorbed without emission.
  *   - primaries start at a uniform point of the top face z_max; azimuth
@@ -342,10 +351,12 @@ typedef struct {
   const float* cdfF;
   int32_t ncdf;
   double Ec;
+  const float* esee;
+  int32_t emission;
 } otab;
 
-/* Yield at (E, alpha): bilinear in (ln E, alpha) on the table grid, clamped. */
-static double tab_yield(const otab* T, double E, double alpha) {
+/* Table value at (E, alpha): bilinear in (ln E, alpha) on the grid, clamped. */
+static double tab_grid(const otab* T, const float* tbl, double E, double alpha) {
   double x = (log(E) - log(T->Emin)) / (log(T->Emax) - log(T->Emin)) * (T->nE - 1);
   if (x < 0.0) x = 0.0;
   if (x > T->nE - 1) x = T->nE - 1;
@@ -358,10 +369,12 @@ static double tab_yield(const otab* T, double E, double alpha) {
   int j = (int)floor(y);
   if (j > T->nth - 2) j = T->nth - 2;
   double fy = y - j;
-  double y00 = T->yld[(int64_t)i * T->nth + j], y10 = T->yld[(int64_t)(i + 1) * T->nth + j];
-  double y01 = T->yld[(int64_t)i * T->nth + j + 1], y11 = T->yld[(int64_t)(i + 1) * T->nth + j + 1];
+  double y00 = tbl[(int64_t)i * T->nth + j], y10 = tbl[(int64_t)(i + 1) * T->nth + j];
+  double y01 = tbl[(int64_t)i * T->nth + j + 1], y11 = tbl[(int64_t)(i + 1) * T->nth + j + 1];
   return (1 - fx) * (1 - fy) * y00 + fx * (1 - fy) * y10 + (1 - fx) * fy * y01 + fx * fy * y11;
 }
+
+static double tab_yield(const otab* T, double E, double alpha) { return tab_grid(T, T->yld, E, alpha); }
 
 /* Piecewise-linear CDF through the tabulated points. */
 static double tab_cdf(const otab* T, double E) {
@@ -417,6 +430,8 @@ typedef struct {
   const float* cdf_F;
   int32_t n_cdf;
   double Ec;
+  const float* esee; /* E_SEE on the yield grid (emission 1), else unused */
+  int32_t emission;  /* 0: spectrum (CDF) + cosine law; 1: the paper's one/two-daughter rule */
 } orc_tables_in;
 
 typedef struct {
@@ -497,7 +512,9 @@ int orc_trace(const orc_mesh_in* mi, const orc_tables_in* ti, const orc_job* job
   omesh m;
   int st = mesh_build(&m, mi->verts, mi->n_verts, mi->tris, mi->n_tris, mi->lo, mi->hi, mi->flags);
   if (st) return st;
-  otab T = {ti->yld, ti->n_E, ti->n_theta, ti->E_min, ti->E_max, ti->cdf_E, ti->cdf_F, ti->n_cdf, ti->Ec};
+  if (ti->emission < 0 || ti->emission > 1 || (ti->emission == 1 && !ti->esee)) return ORC_EINVAL;
+  otab T = {ti->yld, ti->n_E, ti->n_theta, ti->E_min, ti->E_max, ti->cdf_E, ti->cdf_F, ti->n_cdf, ti->Ec,
+            ti->esee, ti->emission};
   const int nthreads_req = job->n_threads;
 #ifdef _OPENMP
   if (nthreads_req > 0) omp_set_num_threads(nthreads_req);
@@ -590,13 +607,34 @@ int orc_trace(const orc_mesh_in* mi, const orc_tables_in* ti, const orc_job* job
         double fl = floor(delta);
         int nd = (int)fl + (u1[0] < delta - fl ? 1 : 0);
         double Eav = ray.E;
+        /* the paper's rule (section 2.2): E_SEE at (E, alpha) from its table */
+        const double es = T.emission == 1 ? tab_grid(&T, T.esee, ray.E, alpha) : 0.0;
+        double xi_pair = 0.0;
         for (int d = 0; d < nd; ++d) {
           double u[4];
           draw4(job->seed, pid, ray.path, 2u + (uint32_t)d, u);
-          double Ed = tab_cdf_inv(&T, u[0] * tab_cdf(&T, Eav));
+          double Ed, s2; /* energy and sin^2 of the polar angle about the normal */
+          if (T.emission == 0) {
+            Ed = tab_cdf_inv(&T, u[0] * tab_cdf(&T, Eav));
+            s2 = u[1];
+          } else if (d % 2 == 1) {
+            /* second of a pair: beta2 = pi/2 - beta1, E2 = cos^2(beta1) E_SEE */
+            Ed = (1.0 - xi_pair) * es;
+            s2 = 1.0 - xi_pair;
+          } else if (d + 1 < nd) {
+            /* first of a pair: E1 = E_SEE sqrt(xi), beta1 = asin(sqrt(xi)) */
+            xi_pair = u[1];
+            Ed = es * sqrt(xi_pair);
+            s2 = xi_pair;
+          } else {
+            /* a lone daughter: energy E_SEE, cosine-law direction */
+            Ed = es;
+            s2 = u[1];
+          }
+          if (Ed < 0.0) Ed = 0.0;
           if (Ed > Eav) Ed = Eav;
           Eav -= Ed;
-          double sb = sqrt(u[1]), cb = sqrt(1.0 - u[1]), ph = 2.0 * PI * u[2];
+          double sb = sqrt(s2), cb = sqrt(1.0 - s2), ph = 2.0 * PI * u[2];
           double t1[3], t2[3];
           onb(p.n, t1, t2);
           oray dr;

@@ -92,6 +92,41 @@ def pin_philox(o):
     return all(list(o.philox4x32_10(c, k)) == out for c, k, out in load_kat(os.path.join(GOLD, "philox4x32_10_kat.txt")))
 
 
+def _paper_flat(o, const, n, seed=41):
+    tab = fg.make_tables("constant", const=const, emission="paper", esee_const=100.0)
+    return o.trace(fg.flat_plane(), tab, 500.0, 0.0, n, seed=seed, max_gen=1, per_primary=True)
+
+
+def pin_paper_lone(o):
+    r = _paper_flat(o, 1.0, 2000)
+    return bool(np.all(r["per_primary"]["e_esc"] == 100.0))
+
+
+def pin_paper_pair_sum(o):
+    from tests.test_oracle_paper_mode import _pair_sum_cdf
+    n = 20000
+    r = _paper_flat(o, 2.0, n)
+    s = np.sort(r["per_primary"]["e_esc"] / 100.0)
+    if s[0] < 1.0 - 1e-12 or s[-1] > 1.25 + 1e-12:
+        return False
+    return bool(np.max(np.abs(np.arange(1, n + 1) / n - _pair_sum_cdf(s))) < 1.63 / math.sqrt(n))
+
+
+def pin_paper_slot(o):
+    from tests.test_oracle_paper_mode import _slot_clear
+    w, h, tw = 2.0, 3.0, 1.0
+    x = (np.arange(1000) + 0.5) / 1000 * w
+    xi = (np.arange(2000) + 0.5) / 2000
+    X, XI = np.meshgrid(x, xi, indexing="ij")
+    b1 = np.arcsin(np.sqrt(XI))
+    p2 = tw / (w + tw) + w / (w + tw) * float((_slot_clear(X, b1, w, h) * _slot_clear(X, np.pi / 2 - b1, w, h)).mean())
+    n = 40000
+    tab = fg.make_tables("constant", const=2.0, emission="paper", esee_const=100.0)
+    r = o.trace(fg.trench(w=w, h=h, tw=tw), tab, 500.0, 0.0, n, seed=43, max_gen=1, per_primary=True)
+    est = float((r["per_primary"]["escaped"] == 2).mean())
+    return abs(est - p2) <= 4.0 * math.sqrt(p2 * (1 - p2) / n)
+
+
 MUTANTS = [
     ("cull the wrong side",
      "if (det <= DET_EPS * norm3(L1) * norm3(L2) * dn) continue;",
@@ -112,7 +147,7 @@ MUTANTS = [
     ("bilinear term dropped",
      "(1 - fx) * fy * y01 + fx * fy * y11;", "(1 - fx) * fy * y01;", pin_flat_yield),
     ("sin(beta) uniform instead of sin^2(beta)",
-     "double sb = sqrt(u[1]), cb = sqrt(1.0 - u[1])", "double sb = u[1], cb = sqrt(1.0 - u[1] * u[1])",
+     "double sb = sqrt(s2), cb = sqrt(1.0 - s2)", "double sb = s2, cb = sqrt(1.0 - s2 * s2)",
      pin_cosine_law),
     ("daughter energy not taken from the parent",
      "          Eav -= Ed;\n", "\n", pin_conservation),
@@ -121,6 +156,14 @@ MUTANTS = [
      pin_trench),
     ("Philox key schedule dropped",
      "      k[0] += 0x9E3779B9u;\n", "\n", pin_philox),
+    ("paper rule: second daughter's energy from a fresh xi",
+     "Ed = (1.0 - xi_pair) * es;", "Ed = (1.0 - u[1]) * es;", pin_paper_pair_sum),
+    ("paper rule: first daughter's energy without the square root",
+     "Ed = es * sqrt(xi_pair);", "Ed = es * xi_pair;", pin_paper_pair_sum),
+    ("paper rule: second daughter at the first one's angle",
+     "s2 = 1.0 - xi_pair;", "s2 = xi_pair;", pin_paper_slot),
+    ("paper rule: lone daughter's energy from the spectrum",
+     "Ed = es;\n", "Ed = tab_cdf_inv(&T, u[0] * tab_cdf(&T, Eav));\n", pin_paper_lone),
 ]
 
 
