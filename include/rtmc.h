@@ -76,7 +76,20 @@ typedef struct {
  *       the piecewise-linear CDF through them.  2 <= n_cdf <= 1024.
  *   Ec: emission cut-off (work function + Fermi energy, section 2.2): a ray
  *       with E <= Ec that hits a surface emits nothing.
+ *   emission: how daughters get energies and directions.
+ *     RTMC_EMIT_SPECTRUM: energies from the CDF above, each truncated to the
+ *       energy the parent still has; directions by the cosine law.
+ *     RTMC_EMIT_PAPER: the paper's rule (section 2.2) with E_SEE from esee:
+ *       a lone daughter takes E_SEE and a cosine-law direction; a pair
+ *       shares one xi, E1 = E_SEE sqrt(xi) at sin^2 beta1 = xi and E2 =
+ *       cos^2 beta1 E_SEE at beta2 = pi/2 - beta1; further daughters come in
+ *       pairs, an odd one last alone; every energy is clamped to [0, energy
+ *       still available].  Azimuths are uniform.
+ *   esee[i * n_theta + j]: E_SEE (eV) on the yield grid, finite, looked up
+ *       like the yield; required for RTMC_EMIT_PAPER, else may be NULL.
  * All arrays are host memory, copied. */
+#define RTMC_EMIT_SPECTRUM 0
+#define RTMC_EMIT_PAPER 1
 typedef struct {
   int32_t n_E, n_theta;
   double E_min, E_max;
@@ -85,6 +98,8 @@ typedef struct {
   const float* cdf_E;
   const float* cdf_F;
   double Ec;
+  const float* esee;
+  int32_t emission;
 } rtmc_tables;
 
 /* Options of one trace.  NULL selects max_gen 6, 256 energy bins, 90 angle

@@ -50,7 +50,7 @@ class Allocator(C.Structure):
 class Tables(C.Structure):
     _fields_ = [("n_E", C.c_int32), ("n_theta", C.c_int32), ("E_min", C.c_double), ("E_max", C.c_double),
                 ("yield_", C.c_void_p), ("n_cdf", C.c_int32), ("cdf_E", C.c_void_p), ("cdf_F", C.c_void_p),
-                ("Ec", C.c_double)]
+                ("Ec", C.c_double), ("esee", C.c_void_p), ("emission", C.c_int32)]
 
 
 class TraceOpts(C.Structure):
@@ -245,8 +245,12 @@ class Context:
         y = np.ascontiguousarray(tab.yld, dtype=np.float32)
         ce = np.ascontiguousarray(tab.cdf_E, dtype=np.float32)
         cf = np.ascontiguousarray(tab.cdf_F, dtype=np.float32)
+        emission = int(getattr(tab, "emission", 0))
+        es = getattr(tab, "esee", None)
+        es = np.ascontiguousarray(es, dtype=np.float32) if es is not None else None
         t = Tables(y.shape[0], y.shape[1], float(tab.E_min), float(tab.E_max), _ptr(y).value, ce.shape[0],
-                   _ptr(ce).value, _ptr(cf).value, float(tab.Ec))
+                   _ptr(ce).value, _ptr(cf).value, float(tab.Ec), _ptr(es).value if es is not None else None,
+                   emission)
         tid = C.c_int32()
         self._chk(self.lib.rtmc_load_tables(self.h, C.byref(t), C.byref(tid)))
         return tid.value

@@ -48,8 +48,8 @@ struct Surrogate {
 };
 
 struct Tables {
-  DevBuf buf;  // yield | cdf_E | cdf_F
-  int32_t nE = 0, nth = 0, ncdf = 0;
+  DevBuf buf;  // yield | cdf_E | cdf_F | esee (paper emission)
+  int32_t nE = 0, nth = 0, ncdf = 0, emission = 0;
   double Emin = 0, Emax = 0, Ec = 0;
   int max_d = 1;
 };
@@ -160,6 +160,8 @@ DevTables dev_tables(const Tables& t) {
   d.invdlogE = (float)((t.nE - 1) / (std::log(t.Emax) - std::log(t.Emin)));
   d.thscale = (float)((t.nth - 1) / 90.0);
   d.Ec = (float)t.Ec;
+  d.esee = t.emission == RTMC_EMIT_PAPER ? d.cdfF + t.ncdf : nullptr;
+  d.emission = t.emission;
   return d;
 }
 
@@ -836,6 +838,13 @@ rtmc_status rtmc_load_tables(rtmc_ctx* c, const rtmc_tables* t, int32_t* table_i
     if (!finite_f(y) || y < 0.f || y >= 7.f) return fail(c, RTMC_EINVAL, "yield value %lld not in [0, 7)", (long long)i);
     ymax = std::max(ymax, y);
   }
+  if (t->emission != RTMC_EMIT_SPECTRUM && t->emission != RTMC_EMIT_PAPER)
+    return fail(c, RTMC_EINVAL, "unknown emission mode %d", t->emission);
+  if (t->emission == RTMC_EMIT_PAPER) {
+    if (!t->esee) return fail(c, RTMC_EINVAL, "the paper's emission rule needs esee");
+    for (int64_t i = 0; i < (int64_t)t->n_E * t->n_theta; ++i)
+      if (!finite_f(t->esee[i])) return fail(c, RTMC_EINVAL, "esee value %lld not finite", (long long)i);
+  }
   if (t->cdf_E[0] != 0.f || t->cdf_F[0] != 0.f || t->cdf_F[t->n_cdf - 1] != 1.f)
     return fail(c, RTMC_EINVAL, "CDF must start at (0, 0) and end at F = 1");
   for (int k = 1; k < t->n_cdf; ++k) {
@@ -852,10 +861,13 @@ rtmc_status rtmc_load_tables(rtmc_ctx* c, const rtmc_tables* t, int32_t* table_i
   tb.Emax = t->E_max;
   tb.Ec = t->Ec;
   tb.max_d = std::max(1, (int)std::ceil(ymax));
-  std::vector<float> h((size_t)tb.nE * tb.nth + 2 * (size_t)tb.ncdf);
-  std::memcpy(h.data(), t->yield, sizeof(float) * tb.nE * tb.nth);
-  std::memcpy(h.data() + (size_t)tb.nE * tb.nth, t->cdf_E, sizeof(float) * tb.ncdf);
-  std::memcpy(h.data() + (size_t)tb.nE * tb.nth + tb.ncdf, t->cdf_F, sizeof(float) * tb.ncdf);
+  tb.emission = t->emission;
+  const size_t ny = (size_t)tb.nE * tb.nth;
+  std::vector<float> h(ny + 2 * (size_t)tb.ncdf + (tb.emission == RTMC_EMIT_PAPER ? ny : 0));
+  std::memcpy(h.data(), t->yield, sizeof(float) * ny);
+  std::memcpy(h.data() + ny, t->cdf_E, sizeof(float) * tb.ncdf);
+  std::memcpy(h.data() + ny + tb.ncdf, t->cdf_F, sizeof(float) * tb.ncdf);
+  if (tb.emission == RTMC_EMIT_PAPER) std::memcpy(h.data() + ny + 2 * (size_t)tb.ncdf, t->esee, sizeof(float) * ny);
   HIPCHK(c, hipSetDevice(c->device));
   if (ensure(c, tb.buf, h.size() * 4)) return RTMC_ENOMEM;
   HIPCHK(c, hipMemcpyAsync(tb.buf.p, h.data(), h.size() * 4, hipMemcpyHostToDevice, c->stream));

@@ -20,6 +20,7 @@ namespace rtmc {
 
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // unused child slot of a 4-wide node
+constexpr int32_t kEmitPaper = 1;         // DevTables::emission of the paper's one/two-daughter rule
 constexpr int kMaxGen = 10;
 constexpr int kWrapMax = 10000;
 constexpr float kSpawnEps = 1e-4f;
@@ -66,7 +67,9 @@ struct DevTables {
   const float* yld;
   const float* cdfE;
   const float* cdfF;
+  const float* esee;  // E_SEE on the yield grid (paper emission), else null
   int32_t nE, nth, ncdf;
+  int32_t emission;   // RTMC_EMIT_SPECTRUM or RTMC_EMIT_PAPER
   float logEmin, invdlogE, thscale, Ec;
 };
 

@@ -168,7 +168,10 @@ __device__ inline bool tri_test(const RayP& r, f4v a, f4v b, f4v c, float tbest,
 
 // ---------------------------------------------------------------- tables (LDS)
 
-__device__ inline float table_yield(const LAS float* yld, const DevTables& tb, float E, float alpha) {
+// Value of a table on the yield grid at (E, alpha): bilinear in (ln E, alpha),
+// clamped at the edges (the yield from LDS, E_SEE from global memory).
+template <typename P>
+__device__ inline float table_yield(P yld, const DevTables& tb, float E, float alpha) {
   float x = (logf(E) - tb.logEmin) * tb.invdlogE;
   x = fminf(fmaxf(x, 0.0f), (float)(tb.nE - 1));
   int i = min((int)floorf(x), tb.nE - 2);
@@ -176,8 +179,8 @@ __device__ inline float table_yield(const LAS float* yld, const DevTables& tb, f
   float y = fminf(fmaxf(alpha * tb.thscale, 0.0f), (float)(tb.nth - 1));
   int j = min((int)floorf(y), tb.nth - 2);
   const float fy = y - (float)j;
-  const LAS float* row0 = yld + i * tb.nth + j;
-  const LAS float* row1 = row0 + tb.nth;
+  const P row0 = yld + i * tb.nth + j;
+  const P row1 = row0 + tb.nth;
   return (1.0f - fx) * (1.0f - fy) * row0[0] + fx * (1.0f - fy) * row1[0] + (1.0f - fx) * fy * row0[1] +
          fx * fy * row1[1];
 }
@@ -882,6 +885,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     unsigned long long* gt = J.tally;
 
     int nd = 0;
+    float alpha = 0.f;
     float px = 0.f, py = 0.f, pz = 0.f, nx = 0.f, ny = 0.f, nz = 1.f;
     if (active) {
       const int32_t code = gp(a.hit.code)[item];
@@ -956,7 +960,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
             tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E), jt, job);
           } else {
             const float cosa = fminf(fmaxf(-(dx * nx + dy * ny + dz * nz), 0.0f), 1.0f);
-            const float alpha = acosf(cosa) * kDeg;
+            alpha = acosf(cosa) * kDeg;
             const float delta = table_yield(s_yld, tb, E, alpha);
             const uint64_t pid = J.pid0 + (a.chunk_lo + ci - J.gbase);
             const U4 u = philox(J.seed, (uint32_t)pid, (uint32_t)(pid >> 32), path, 1u);
@@ -993,13 +997,30 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
       const float Lx = J.sc.hi[0] - J.sc.lo[0], Ly = J.sc.hi[1] - J.sc.lo[1];
       const bool periodic = (J.sc.flags & 1u) != 0;
       uint32_t dropped = 0;
+      // the paper's rule: E_SEE at (E, alpha); a pair shares one xi
+      const bool paper = tb.emission == kEmitPaper;
+      const float es = paper ? table_yield((const GAS float*)tb.esee, tb, E, alpha) : 0.0f;
+      float xi_pair = 0.0f;
       for (int d = 0; d < nd; ++d) {
         const U4 u = philox(J.seed, (uint32_t)pid, (uint32_t)(pid >> 32), path, 2u + (uint32_t)d);
-        float Ed = cdf_inv(s_cE, s_cF, tb.ncdf, u01(u.x) * cdf_at(s_cE, s_cF, tb.ncdf, Eav));
-        Ed = fminf(Ed, Eav);
+        float Ed, xb;  // energy and sin^2 of the angle from the normal
+        if (!paper) {
+          Ed = cdf_inv(s_cE, s_cF, tb.ncdf, u01(u.x) * cdf_at(s_cE, s_cF, tb.ncdf, Eav));
+          xb = u01(u.y);
+        } else if (d & 1) {  // second of a pair: beta2 = pi/2 - beta1, E2 = cos^2(beta1) E_SEE
+          Ed = (1.0f - xi_pair) * es;
+          xb = 1.0f - xi_pair;
+        } else if (d + 1 < nd) {  // first of a pair: E1 = E_SEE sqrt(xi), beta1 = asin(sqrt(xi))
+          xi_pair = u01(u.y);
+          Ed = es * sqrtf(xi_pair);
+          xb = xi_pair;
+        } else {  // a lone daughter
+          Ed = es;
+          xb = u01(u.y);
+        }
+        Ed = fminf(fmaxf(Ed, 0.0f), Eav);
         Eav -= Ed;
         fx_left -= to_fx(Ed);
-        const float xb = u01(u.y);
         const float sb = sqrtf(xb), cb = sqrtf(1.0f - xb);
         const float ph = 2.0f * kPi * u01(u.z);
         const float cp = cosf(ph), sp = sinf(ph);
