@@ -6,6 +6,7 @@ consume what it produces.
 """
 from .foam import (Mesh, PERIODIC_XY, SUBSTRATE, flat_plane, foam_field, grf_field,
                    make_grf_foam, random_soup, surface_rays, top_rays, trench)
+from .cage import cage_solid_fraction, make_cage
 from .mc import marching_cubes_periodic
 from .tables import (Tables, bilinear_reference, ce_cdf, ce_inverse, make_tables,
                      paper_w_yield, vaughan_yield)

@@ -133,3 +133,21 @@ def test_paper_mode_needs_esee(ctx):
     tab.esee[3, 4] = np.nan
     with pytest.raises(rt.RtmcError):
         ctx.load_tables(tab)
+
+
+@pytest.mark.parametrize("a,kind", [(0.2, "paper_w"), (0.1, "vaughan")])
+def test_cage_parity(ctx, torch, oracle_lib, a, kind):
+    """The open cubic cage on its substrate: per-primary escape counts as the oracle's."""
+    m = fg.make_cage(a, 16.0, 2)
+    tab = fg.make_tables(kind)
+    sid = ctx.load_scene(m)
+    tid = ctx.load_tables(tab)
+    n = 8000
+    pp = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    g = ctx.trace(sid, tid, 400.0, 0.0, n, seed=13, max_gen=8, per_primary=pp)
+    o = oracle_lib.trace(m, tab, 400.0, 0.0, n, seed=13, max_gen=8, per_primary=True)
+    same = (pp.cpu().numpy().astype(np.int64) == o["per_primary"]["escaped"].astype(np.int64)).mean()
+    assert same >= 0.995, same
+    sig = math.sqrt(g["yield_sigma"] ** 2 + o["yield_sigma"] ** 2)
+    assert abs(g["yield"] - o["yield"]) <= 3 * sig
+    assert g["n_substrate"] > 0 and g["n_wraps"] > 0

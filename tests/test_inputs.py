@@ -116,3 +116,46 @@ def test_chord_lengths_match_a_walk_along_every_line():
         for y in range(ny):
             ref += walk(inner[x, y, :], False)
     assert sorted(chord_lengths(v).tolist()) == sorted(ref)
+
+
+@pytest.mark.parametrize("a,n", [(0.1, 4), (0.2, 2), (0.25, 1)])
+def test_cage_is_the_union_of_its_struts(a, n):
+    """Open cubic cage: watertight modulo periodicity except where it stands on
+    the substrate, normals into the void, enclosed volume exactly that of the
+    struts, no surface on a face of the periodic cell."""
+    ell = 16.0
+    m = fg.make_cage(a, ell, n)
+    V = m.verts.astype(np.float64)
+    c = m.meta["canon"]
+    e = Counter()
+    for tri in m.tris:
+        for u, v in ((tri[0], tri[1]), (tri[1], tri[2]), (tri[2], tri[0])):
+            e[(c[u], c[v])] += 1
+    for (u, v), k in e.items():
+        if e.get((v, u), 0) != k:  # open edges only on the substrate plane
+            assert V[c == u][0][2] == 0.0 and V[c == v][0][2] == 0.0
+    P = V[m.tris]
+    s = np.cross(P[:, 1] - P[:, 0], P[:, 2] - P[:, 0])
+    t = a * ell
+    top = n * ell + t
+    exact = (n + 1) * t * (2 * t * ell - t * t) + t * t * (top - (n + 1) * t)
+    assert (s[:, 2] * P[:, :, 2].mean(axis=1)).sum() / 2 == pytest.approx(exact, rel=1e-5)  # FP32 vertices
+
+    def solid(p):
+        band = lambda x: (x % ell < t / 2) | (x % ell > ell - t / 2)
+        layer = np.zeros(len(p), dtype=bool)
+        for k in range(n + 1):
+            layer |= (p[:, 2] > k * ell) & (p[:, 2] < k * ell + t)
+        return ((band(p[:, 1]) & layer) | (band(p[:, 0]) & layer)
+                | (band(p[:, 0]) & band(p[:, 1]) & (p[:, 2] < top)) | (p[:, 2] < 0))
+
+    cen = P.mean(axis=1)
+    nrm = s / np.linalg.norm(s, axis=1, keepdims=True)
+    assert not solid(cen + 1e-3 * nrm).any()
+    assert solid(cen - 1e-3 * nrm).all()
+    # nothing on the periodic cell's faces, the substrate plane included
+    assert not np.any(np.all(P[:, :, 0] == 0.0, axis=1) | np.all(P[:, :, 0] == ell, axis=1))
+    assert not np.any(np.all(P[:, :, 1] == 0.0, axis=1) | np.all(P[:, :, 1] == ell, axis=1))
+    assert not np.any(np.all(P[:, :, 2] == 0.0, axis=1))
+    assert m.meta["v_f_paper"] == pytest.approx(a * a)
+    assert fg.cage_solid_fraction(a) == pytest.approx(3 * a * a - 2 * a ** 3)
