@@ -58,7 +58,7 @@ class _TablesIn(C.Structure):
 class _Job(C.Structure):
     _fields_ = [("E0", C.c_double), ("theta_deg", C.c_double), ("pid0", C.c_uint64),
                 ("n_primaries", C.c_uint64), ("seed", C.c_uint64), ("max_gen", C.c_int32),
-                ("n_ebins", C.c_int32), ("n_abins", C.c_int32), ("n_threads", C.c_int32)]
+                ("n_ebins", C.c_int32), ("n_abins", C.c_int32), ("n_threads", C.c_int32), ("n_zbins", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -75,7 +75,7 @@ def _bind(path):
     lib.orc_first_hit.argtypes = [C.POINTER(_MeshIn), C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p,
                                   C.c_void_p, C.c_int32]
     lib.orc_trace.argtypes = [C.POINTER(_MeshIn), C.POINTER(_TablesIn), C.POINTER(_Job), C.POINTER(_Result)] + \
-        [C.c_void_p] * 6
+        [C.c_void_p] * 7
     lib.orc_table_yield.argtypes = [C.POINTER(_TablesIn), C.c_double, C.c_double]
     lib.orc_table_yield.restype = C.c_double
     lib.orc_sample_energy.argtypes = [C.POINTER(_TablesIn), C.c_double, C.c_double]
@@ -193,22 +193,23 @@ def first_hit(mesh, rays, n_threads: int = 0, _lib=None):
 
 def trace(mesh, tab, E0: float, theta_deg: float, n_primaries: int, seed: int, max_gen: int = 6,
           pid0: int = 0, n_ebins: int = 256, n_abins: int = 90, n_threads: int = 0, per_primary: bool = False,
-          _lib=None):
+          n_zbins: int = 0, _lib=None):
     """FP64 RTMC over primaries pid0 .. pid0 + n - 1; returns a dict."""
     lib = _lib or _load()
     keep = _Keep()
     mi = _mesh_in(mesh, keep)
     ti = _tables_in(tab, keep)
     job = _Job(float(E0), float(theta_deg), int(pid0), int(n_primaries), int(seed), int(max_gen), int(n_ebins),
-               int(n_abins), int(n_threads))
+               int(n_abins), int(n_threads), int(n_zbins))
     res = _Result()
     eh = np.zeros(n_ebins, dtype=np.uint64)
     ah = np.zeros(n_abins, dtype=np.uint64)
+    zh = np.zeros(max(n_zbins, 1), dtype=np.uint64)
     pp = None
     if per_primary:
         pp = dict(escaped=np.zeros(n_primaries, dtype=np.uint32), e_esc=np.zeros(n_primaries),
                   e_dep=np.zeros(n_primaries), rays=np.zeros(n_primaries, dtype=np.uint32))
-    st = lib.orc_trace(C.byref(mi), C.byref(ti), C.byref(job), C.byref(res), _ptr(eh), _ptr(ah),
+    st = lib.orc_trace(C.byref(mi), C.byref(ti), C.byref(job), C.byref(res), _ptr(eh), _ptr(ah), _ptr(zh),
                        _ptr(pp["escaped"]) if pp else None, _ptr(pp["e_esc"]) if pp else None,
                        _ptr(pp["e_dep"]) if pp else None, _ptr(pp["rays"]) if pp else None)
     if st != 0:
@@ -216,6 +217,8 @@ def trace(mesh, tab, E0: float, theta_deg: float, n_primaries: int, seed: int, m
     out = {f[0].rstrip("_"): getattr(res, f[0]) for f in _Result._fields_}
     out["e_hist"] = eh
     out["a_hist"] = ah
+    if n_zbins:
+        out["z_hist"] = zh
     if pp:
         out["per_primary"] = pp
     return out

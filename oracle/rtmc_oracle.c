@@ -53,6 +53,9 @@
  *   - a ray of generation max_gen that hits is absorbed without emission.
  *   - primaries start at a uniform point of the top face z_max; azimuth
  *     uniform; theta fixed, or uniform in [0, |theta|] when theta < 0.
+ *   - absorption depth (section 3.3, penetration profile): every ray of
+ *     any generation that ends on a surface (triangle or substrate) is one
+ *     absorption event at depth (z_max - z) / (z_max - z_min) in [0, 1].
  *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
  *     counter = (primary id low, primary id high, path code, draw), mapped
  *     to (0, 1] by ((u >> 8) + 1) * 2^-24.  Draw 0 is a primary's birth,
@@ -444,6 +447,7 @@ typedef struct {
   int32_t n_ebins; /* escaped-energy histogram over [0, E0] */
   int32_t n_abins; /* escape polar-angle histogram over [0, 90) deg */
   int32_t n_threads;
+  int32_t n_zbins; /* absorption-depth histogram over [0, 1] (0: none) */
 } orc_job;
 
 typedef struct {
@@ -504,9 +508,10 @@ typedef struct {
 /* Full RTMC over primaries pid0 .. pid0 + n - 1.  Per-primary arrays
  * (escape count, escaped energy, deposited energy, rays) are optional. */
 int orc_trace(const orc_mesh_in* mi, const orc_tables_in* ti, const orc_job* job, orc_result* res,
-              uint64_t* e_hist, uint64_t* a_hist, uint32_t* pp_escaped, double* pp_e_esc, double* pp_e_dep,
-              uint32_t* pp_rays) {
-  if (job->max_gen < 0 || job->max_gen > 10 || !(job->E0 > 0.0) || job->n_ebins < 1 || job->n_abins < 1)
+              uint64_t* e_hist, uint64_t* a_hist, uint64_t* z_hist, uint32_t* pp_escaped, double* pp_e_esc,
+              double* pp_e_dep, uint32_t* pp_rays) {
+  if (job->max_gen < 0 || job->max_gen > 10 || !(job->E0 > 0.0) || job->n_ebins < 1 || job->n_abins < 1 ||
+      job->n_zbins < 0 || (job->n_zbins > 0 && !z_hist))
     return ORC_EINVAL;
   if (ti->n_E < 2 || ti->n_theta < 2 || ti->n_cdf < 2) return ORC_EINVAL;
   omesh m;
@@ -519,11 +524,12 @@ int orc_trace(const orc_mesh_in* mi, const orc_tables_in* ti, const orc_job* job
 #ifdef _OPENMP
   if (nthreads_req > 0) omp_set_num_threads(nthreads_req);
 #endif
-  const int NE = job->n_ebins, NA = job->n_abins;
+  const int NE = job->n_ebins, NA = job->n_abins, NZ = job->n_zbins;
   uint64_t g_rays = 0, g_esc = 0, g_abs = 0, g_trunc = 0, g_lost = 0, g_sub = 0, g_wraps = 0, g_tests = 0;
   double g_eesc = 0.0, g_edep = 0.0, g_c2 = 0.0;
   memset(e_hist, 0, sizeof(uint64_t) * NE);
   memset(a_hist, 0, sizeof(uint64_t) * NA);
+  if (NZ) memset(z_hist, 0, sizeof(uint64_t) * NZ);
   int failed = 0;
 #pragma omp parallel
   {
@@ -531,9 +537,10 @@ int orc_trace(const orc_mesh_in* mi, const orc_tables_in* ti, const orc_job* job
     double l_eesc = 0.0, l_edep = 0.0, l_c2 = 0.0;
     uint64_t* lh_e = (uint64_t*)calloc((size_t)NE, sizeof(uint64_t));
     uint64_t* lh_a = (uint64_t*)calloc((size_t)NA, sizeof(uint64_t));
+    uint64_t* lh_z = (uint64_t*)calloc((size_t)(NZ > 0 ? NZ : 1), sizeof(uint64_t));
     size_t cap = 64;
     oray* q = (oray*)malloc(sizeof(oray) * cap);
-    if (!lh_e || !lh_a || !q) {
+    if (!lh_e || !lh_a || !lh_z || !q) {
 #pragma omp atomic write
       failed = 1;
     }
@@ -587,6 +594,14 @@ int orc_trace(const orc_mesh_in* mi, const orc_tables_in* ti, const orc_job* job
           continue;
         }
         if (p.kind == OUT_SUBSTRATE) l_sub++;
+        if (NZ) {
+          /* the ray ends on a surface: its depth below the top of the cell,
+             as a fraction of the cell height (section 3.3, penetration) */
+          int zb = (int)floor((m.hi[2] - p.P[2]) / (m.hi[2] - m.lo[2]) * NZ);
+          if (zb < 0) zb = 0;
+          if (zb > NZ - 1) zb = NZ - 1;
+          lh_z[zb]++;
+        }
         if (ray.gen >= job->max_gen) {
           l_trunc++;
           e_dep += ray.E;
@@ -700,9 +715,12 @@ int orc_trace(const orc_mesh_in* mi, const orc_tables_in* ti, const orc_job* job
         for (int b = 0; b < NE; ++b) e_hist[b] += lh_e[b];
       if (lh_a)
         for (int b = 0; b < NA; ++b) a_hist[b] += lh_a[b];
+      if (lh_z)
+        for (int b = 0; b < NZ; ++b) z_hist[b] += lh_z[b];
     }
     free(lh_e);
     free(lh_a);
+    free(lh_z);
     free(q);
   }
   free(m.t);

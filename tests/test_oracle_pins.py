@@ -278,3 +278,27 @@ def test_foam_yield_falls_with_porosity(oracle_lib):
         ys.append(oracle_lib.trace(m, tab, 500.0, 0.0, 4000, seed=2)["yield"])
     flat = float(fg.bilinear_reference(tab, 500.0, 0.0))
     assert ys[1] < ys[0] < flat
+
+
+def test_absorption_depth_on_a_flat_plane(oracle_lib):
+    """Every primary ends on the plane z0 = 1 of a cell spanning z in [0, 5]:
+    one absorption event per primary at depth 0.8; daughters all escape."""
+    n = 3000
+    for const in (0.0, 2.0):
+        tab = fg.make_tables("constant", const=const)
+        r = oracle_lib.trace(fg.flat_plane(L=4.0, z0=1.0, height=4.0), tab, 300.0, 0.0, n, seed=3, max_gen=6,
+                             n_zbins=10)
+        z = r["z_hist"]
+        assert z[8] == n and z.sum() == n
+
+
+def test_absorption_depth_in_a_slot(oracle_lib):
+    """Slot of width 2 between walls 1 thick and 3 high, cell z in [-1, 5]:
+    at normal incidence a primary ends on a wall top (depth 1/3) with
+    probability 1/3, on the floor (depth 5/6) otherwise."""
+    n = 30000
+    r = oracle_lib.trace(fg.trench(w=2.0, h=3.0, tw=1.0), fg.make_tables("constant", const=0.0), 300.0, 0.0, n,
+                         seed=5, max_gen=1, n_zbins=7)
+    z = r["z_hist"]
+    assert z.sum() == n and z[2] + z[5] == n
+    assert abs(z[2] / n - 1 / 3) <= 4 * math.sqrt(2 / 9 / n)
