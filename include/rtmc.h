@@ -113,6 +113,10 @@ typedef struct {
   uint64_t* e_hist;      /* host, n_ebins counts, may be NULL */
   uint64_t* a_hist;      /* host, n_abins counts, may be NULL */
   uint32_t* pp_escaped;  /* device, n_primaries escape counts indexed by primary id - pid0, may be NULL */
+  int32_t n_zbins;       /* absorption-depth histogram (section 3.3): every ray of any generation that
+                            ends on a surface counts once at depth (z_max - z) / (z_max - z_min), in
+                            n_zbins bins over [0, 1]; 0 means none; <= 256 */
+  uint64_t* z_hist;      /* host, n_zbins counts, may be NULL */
 } rtmc_trace_opts;
 
 typedef struct {

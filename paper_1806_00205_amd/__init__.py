@@ -55,7 +55,8 @@ class Tables(C.Structure):
 
 class TraceOpts(C.Structure):
     _fields_ = [("max_gen", C.c_int32), ("n_ebins", C.c_int32), ("n_abins", C.c_int32), ("pid0", C.c_uint64),
-                ("e_hist", C.c_void_p), ("a_hist", C.c_void_p), ("pp_escaped", C.c_void_p)]
+                ("e_hist", C.c_void_p), ("a_hist", C.c_void_p), ("pp_escaped", C.c_void_p), ("n_zbins", C.c_int32),
+                ("z_hist", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -257,18 +258,23 @@ class Context:
 
     # ---------------------------------------------------------------- tracing
     def trace(self, scene: int, table: int, E: float, theta: float, n_primaries: int, seed: int, max_gen: int = 6,
-              n_ebins: int = 256, n_abins: int = 90, pid0: int = 0, per_primary=None) -> dict:
-        """Full RTMC; per_primary may be a uint32/int32 torch tensor of n_primaries on the GPU."""
+              n_ebins: int = 256, n_abins: int = 90, pid0: int = 0, per_primary=None, n_zbins: int = 0) -> dict:
+        """Full RTMC; per_primary may be a uint32/int32 torch tensor of n_primaries on the GPU;
+        n_zbins > 0 adds the absorption-depth histogram ("z_hist")."""
         eh = np.zeros(n_ebins, dtype=np.uint64)
         ah = np.zeros(n_abins, dtype=np.uint64)
+        zh = np.zeros(max(n_zbins, 1), dtype=np.uint64)
         pp = per_primary.data_ptr() if per_primary is not None else None
-        o = TraceOpts(int(max_gen), int(n_ebins), int(n_abins), int(pid0), _ptr(eh).value, _ptr(ah).value, pp)
+        o = TraceOpts(int(max_gen), int(n_ebins), int(n_abins), int(pid0), _ptr(eh).value, _ptr(ah).value, pp,
+                      int(n_zbins), _ptr(zh).value)
         r = Result()
         self._chk(self.lib.rtmc_trace(self.h, scene, table, float(E), float(theta), int(n_primaries), int(seed),
                                       C.byref(o), C.byref(r)))
         d = r.to_dict()
         d["e_hist"] = eh
         d["a_hist"] = ah
+        if n_zbins:
+            d["z_hist"] = zh
         return d
 
     def trace_batch(self, table: int, jobs, max_gen: int = 6) -> list:

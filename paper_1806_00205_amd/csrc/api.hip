@@ -244,14 +244,15 @@ std::vector<ChunkPlan> plan_chunks(const std::vector<HostJob>& jobs, uint32_t ch
 // Enqueue the launch sequence of a batch of jobs with a given chunk size:
 // per chunk and generation, traversal then shading.
 rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJob>& jobs, int max_gen,
-                          int n_ebins, int n_abins, const rtmc_launch_cfg& cfg, uint32_t chunk, hipStream_t s,
+                          int n_ebins, int n_abins, int n_zbins, const rtmc_launch_cfg& cfg, uint32_t chunk,
+                          hipStream_t s,
                           uint64_t total, bool timed, uint64_t* n_launch) {
   const int block = cfg.block;
   const int grid = grid_of(c, cfg);
   const std::vector<ChunkPlan> plan = plan_chunks(jobs, chunk);
   const uint64_t n_chunks = plan.size();
   (void)total;
-  const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins;
+  const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins + n_zbins;
   const int ncnt = 2 * (kMaxGen + 2);
   int gdepth = kGlobalStack;
   for (auto& j : jobs) gdepth = std::max(gdepth, stack_need(c->scenes[j.scene].depth));
@@ -302,6 +303,7 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   sa.max_gen = max_gen;
   sa.n_ebins = n_ebins;
   sa.n_abins = n_abins;
+  sa.n_zbins = n_zbins;
   sa.hit = hr;
   sa.err = errw;
 
@@ -357,10 +359,11 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
 }
 
 rtmc_status prepare_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJob>& jobs, int n_ebins, int n_abins,
+                          int n_zbins,
                           const rtmc_launch_cfg& cfg, uint64_t* total_out) {
   // job table
   std::vector<DevJob> dj(jobs.size());
-  const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins;
+  const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins + n_zbins;
   rtmc_status st = ensure(c, c->tally, tw * jobs.size() * 8);
   if (st) return st;
   uint64_t g = 0;
@@ -411,16 +414,16 @@ rtmc_status prepare_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
 }
 
 rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs, int max_gen, int n_ebins,
-                      int n_abins, bool use_graph, TraceOut& out) {
+                      int n_abins, int n_zbins, bool use_graph, TraceOut& out) {
   const Tables& tb = c->tables[table_id];
   rtmc_launch_cfg cfg = c->cfg;
-  const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins;
+  const size_t tw = (size_t)T_NCOUNT + n_ebins + n_abins + n_zbins;
   for (int attempt = 0;; ++attempt) {
     uint64_t total = 0;
-    rtmc_status st = prepare_trace(c, tb, jobs, n_ebins, n_abins, cfg, &total);
+    rtmc_status st = prepare_trace(c, tb, jobs, n_ebins, n_abins, n_zbins, cfg, &total);
     if (st) return st;
     const size_t lds_t = traverse_lds_bytes(cfg.lds_stack, cfg.block);
-    const size_t lds_s = shade_lds_bytes(dev_tables(tb), n_ebins, n_abins, kShadeBlock, kShadeJobs);
+    const size_t lds_s = shade_lds_bytes(dev_tables(tb), n_ebins + n_abins + n_zbins, kShadeBlock, kShadeJobs);
     if (lds_t > c->lds_per_block || lds_s > c->lds_per_block)
       return fail(c, RTMC_EINVAL, "launch needs %zu / %zu bytes of LDS per workgroup (device limit %zu)", lds_t,
                   lds_s, c->lds_per_block);
@@ -432,7 +435,8 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
       // device buffers it names, not on the job table's contents, which are
       // uploaded to the same buffer before every launch.
       std::vector<uint64_t> key = {(uint64_t)jobs.size(), total, (uint64_t)max_gen, (uint64_t)n_ebins,
-                                   (uint64_t)n_abins, (uint64_t)cfg.block, (uint64_t)cfg.wg_per_cu,
+                                   (uint64_t)n_abins, (uint64_t)n_zbins, (uint64_t)cfg.block,
+                                   (uint64_t)cfg.wg_per_cu,
                                    (uint64_t)cfg.lds_stack, (uint64_t)cfg.chunk, (uint64_t)cfg.refill,
                                    (uint64_t)cfg.occupancy, (uint64_t)table_id, (uint64_t)(uintptr_t)c->jobs.p,
                                    (uint64_t)(uintptr_t)c->tally.p, (uint64_t)(uintptr_t)c->queue[0].p,
@@ -454,7 +458,8 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
         }
         hipGraph_t graph = nullptr;
         HIPCHK(c, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
-        st = enqueue_trace(c, tb, jobs, max_gen, n_ebins, n_abins, cfg, (uint32_t)cfg.chunk, s, total, false, &nl);
+        st = enqueue_trace(c, tb, jobs, max_gen, n_ebins, n_abins, n_zbins, cfg, (uint32_t)cfg.chunk, s, total,
+                           false, &nl);
         hipError_t ce = hipStreamEndCapture(s, &graph);
         if (st) {
           if (graph) (void)hipGraphDestroy(graph);
@@ -479,7 +484,8 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
     } else {
       HIPCHK(c, hipEventRecord(c->ev0, s));
       uint64_t nl = 0;
-      st = enqueue_trace(c, tb, jobs, max_gen, n_ebins, n_abins, cfg, (uint32_t)cfg.chunk, s, total, true, &nl);
+      st = enqueue_trace(c, tb, jobs, max_gen, n_ebins, n_abins, n_zbins, cfg, (uint32_t)cfg.chunk, s, total, true,
+                         &nl);
       if (st) return st;
       HIPCHK(c, hipEventRecord(c->ev1, s));
       HIPCHK(c, hipStreamSynchronize(s));
@@ -515,8 +521,8 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
   }
 }
 
-void fill_result(const unsigned long long* t, const HostJob& j, int n_ebins, int n_abins, uint64_t* eh,
-                 uint64_t* ah, const TraceOut& to, rtmc_result* r) {
+void fill_result(const unsigned long long* t, const HostJob& j, int n_ebins, int n_abins, int n_zbins, uint64_t* eh,
+                 uint64_t* ah, uint64_t* zh, const TraceOut& to, rtmc_result* r) {
   std::memset(r, 0, sizeof(*r));
   r->n_primaries = j.n;
   r->n_rays = t[T_RAYS];
@@ -548,6 +554,8 @@ void fill_result(const unsigned long long* t, const HostJob& j, int n_ebins, int
     for (int b = 0; b < n_ebins; ++b) eh[b] = t[T_NCOUNT + b];
   if (ah)
     for (int b = 0; b < n_abins; ++b) ah[b] = t[T_NCOUNT + n_ebins + b];
+  if (zh)
+    for (int b = 0; b < n_zbins; ++b) zh[b] = t[T_NCOUNT + n_ebins + n_abins + b];
 }
 
 bool finite_f(float x) { return std::isfinite(x); }
@@ -884,14 +892,15 @@ rtmc_status rtmc_trace(rtmc_ctx* c, int32_t scene_id, int32_t table_id, double E
   c->err.clear();
   if (table_id < 0 || table_id >= (int32_t)c->tables.size()) return fail(c, RTMC_EINVAL, "unknown table id %d", table_id);
   if (!out) return fail(c, RTMC_EINVAL, "null result");
-  rtmc_trace_opts o{6, 256, 90, 0, nullptr, nullptr, nullptr};
+  rtmc_trace_opts o{6, 256, 90, 0, nullptr, nullptr, nullptr, 0, nullptr};
   if (opts) {
     o = *opts;
     if (o.n_ebins == 0) o.n_ebins = 256;
     if (o.n_abins == 0) o.n_abins = 90;
   }
   if (o.max_gen < 0 || o.max_gen > kMaxGen) return fail(c, RTMC_EINVAL, "max_gen %d not in [0, 10]", o.max_gen);
-  if (o.n_ebins < 1 || o.n_ebins > kMaxEbins || o.n_abins < 1 || o.n_abins > kMaxAbins)
+  if (o.n_ebins < 1 || o.n_ebins > kMaxEbins || o.n_abins < 1 || o.n_abins > kMaxAbins || o.n_zbins < 0 ||
+      o.n_zbins > kMaxZbins)
     return fail(c, RTMC_EINVAL, "histogram bins out of range");
   if (!(E_eV > 0.0) || !std::isfinite(E_eV) || !std::isfinite(theta_deg) || theta_deg > 90.0 || theta_deg < -90.0)
     return fail(c, RTMC_EINVAL, "bad energy or angle");
@@ -902,12 +911,13 @@ rtmc_status rtmc_trace(rtmc_ctx* c, int32_t scene_id, int32_t table_id, double E
     std::memset(out, 0, sizeof(*out));
     if (o.e_hist) std::memset(o.e_hist, 0, 8 * (size_t)o.n_ebins);
     if (o.a_hist) std::memset(o.a_hist, 0, 8 * (size_t)o.n_abins);
+    if (o.z_hist && o.n_zbins) std::memset(o.z_hist, 0, 8 * (size_t)o.n_zbins);
     return RTMC_OK;
   }
   TraceOut to;
-  st = run_trace(c, table_id, jobs, o.max_gen, o.n_ebins, o.n_abins, false, to);
+  st = run_trace(c, table_id, jobs, o.max_gen, o.n_ebins, o.n_abins, o.n_zbins, false, to);
   if (st) return st;
-  fill_result(to.tally.data(), jobs[0], o.n_ebins, o.n_abins, o.e_hist, o.a_hist, to, out);
+  fill_result(to.tally.data(), jobs[0], o.n_ebins, o.n_abins, o.n_zbins, o.e_hist, o.a_hist, o.z_hist, to, out);
   return RTMC_OK;
 }
 
@@ -936,11 +946,11 @@ rtmc_status rtmc_trace_batch(rtmc_ctx* c, int32_t table_id, const rtmc_job* jobs
     return RTMC_OK;
   }
   TraceOut to;
-  rtmc_status st = run_trace(c, table_id, hj, max_gen, 256, 90, true, to);
+  rtmc_status st = run_trace(c, table_id, hj, max_gen, 256, 90, 0, true, to);
   if (st) return st;
   const size_t tw = (size_t)T_NCOUNT + 256 + 90;
   for (int64_t i = 0; i < n_jobs; ++i)
-    fill_result(to.tally.data() + tw * i, hj[i], 256, 90, nullptr, nullptr, to, &outs[i]);
+    fill_result(to.tally.data() + tw * i, hj[i], 256, 90, 0, nullptr, nullptr, nullptr, to, &outs[i]);
   return RTMC_OK;
 }
 

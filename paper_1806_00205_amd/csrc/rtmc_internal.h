@@ -26,6 +26,7 @@ constexpr int kWrapMax = 10000;
 constexpr float kSpawnEps = 1e-4f;
 constexpr int kMaxEbins = 1024;
 constexpr int kMaxAbins = 360;
+constexpr int kMaxZbins = 256;
 constexpr int kMaxYield = 8192;
 constexpr int kMaxCdf = 1024;
 constexpr int kGlobalStack = 64;  // minimum traversal stack entries per lane beyond the LDS part
@@ -135,7 +136,7 @@ struct ShadeArgs {
   uint32_t* count_out;
   uint32_t* ppc;  // per-primary escape counts of the chunk
   int32_t gen, max_gen;
-  int32_t n_ebins, n_abins;
+  int32_t n_ebins, n_abins, n_zbins;  // histogram bins: escaped energy, escape angle, absorption depth
   int32_t j_lo, j_hi;  // jobs overlapping the chunk
   HitRecs hit;
   uint32_t* err;  // bit 0: queue overflow
@@ -144,7 +145,7 @@ struct ShadeArgs {
 // host-side launchers (defined in the .hip files)
 size_t traverse_lds_bytes(int lds_stack, int block);
 // LDS of a shading workgroup; n_jobs = jobs of the chunk (tallied in LDS when <= kShadeJobs)
-size_t shade_lds_bytes(const DevTables& tb, int n_ebins, int n_abins, int block, int n_jobs);
+size_t shade_lds_bytes(const DevTables& tb, int n_hist, int block, int n_jobs);  // n_hist: all histogram bins
 hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int grid, int block, hipStream_t s);
 hipError_t launch_shade(const ShadeArgs& a, int n_cu, int block, hipStream_t s);  // grid = n_cu x occupancy
 hipError_t launch_primaries(const DevJob* jobs, int32_t j_lo, int32_t j_hi, uint64_t chunk_lo, uint32_t n,

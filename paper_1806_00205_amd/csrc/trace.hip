@@ -251,6 +251,7 @@ struct WaveTally {
   unsigned long long e_esc, e_dep;
   LAS uint32_t* eh;  // LDS [n_ebins]
   LAS uint32_t* ah;  // LDS [n_abins]
+  LAS uint32_t* zh;  // LDS [n_zbins]
 };
 
 __device__ inline void gadd(unsigned long long* g, unsigned long long v) {
@@ -263,7 +264,7 @@ __device__ inline void ladd(LAS T* p, T v) {
 }
 
 // Workgroup-wide LDS tally blocks, one per job of the chunk (when few enough):
-// [T_NCOUNT u64 counters][n_ebins u32][n_abins u32] per job.
+// [T_NCOUNT u64 counters][n_ebins u32][n_abins u32][n_zbins u32] per job.
 struct JobTab {
   LAS unsigned char* base;
   int stride, n_eb, n_ab, j_lo, J;
@@ -318,7 +319,7 @@ __device__ inline void flush_wave_lds(WaveTally& wt, LAS unsigned long long* cnt
   wt.e_dep = 0ull;
 }
 
-__device__ inline void flush_wave(WaveTally& wt, unsigned long long* g, int n_eb, int n_ab, uint32_t lane) {
+__device__ inline void flush_wave(WaveTally& wt, unsigned long long* g, int n_eb, int n_ab, int n_zb, uint32_t lane) {
 #pragma unroll
   for (int k = 0; k < T_NCOUNT; ++k) {
     if (k == T_E_ESC_FX || k == T_E_DEP_FX || k == T_C2 || k == T_SPARE) continue;
@@ -343,6 +344,11 @@ __device__ inline void flush_wave(WaveTally& wt, unsigned long long* g, int n_eb
     const uint32_t v = wt.ah[i];
     if (v) gadd(g + T_NCOUNT + n_eb + i, (unsigned long long)v);
     wt.ah[i] = 0u;
+  }
+  for (int i = lane; i < n_zb; i += 64) {
+    const uint32_t v = wt.zh[i];
+    if (v) gadd(g + T_NCOUNT + n_eb + n_ab + i, (unsigned long long)v);
+    wt.zh[i] = 0u;
   }
   wave_sync();
 }
@@ -804,10 +810,11 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
   size_t off = ((size_t)(nY + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
   LAS uint32_t* s_eh = (LAS uint32_t*)(lds + off);
   LAS uint32_t* s_ah = s_eh + wpb * a.n_ebins;
+  LAS uint32_t* s_zh = s_ah + wpb * a.n_abins;
   __shared__ uint32_t s_wtot[16], s_wbase[16];  // per-wave daughter totals and queue offsets of a step
   JobTab jtab;
   jtab.base = lds + off;
-  jtab.stride = (T_NCOUNT * 8 + (a.n_ebins + a.n_abins) * 4 + 7) & ~7;
+  jtab.stride = (T_NCOUNT * 8 + (a.n_ebins + a.n_abins + a.n_zbins) * 4 + 7) & ~7;
   jtab.n_eb = a.n_ebins;
   jtab.n_ab = a.n_abins;
   jtab.j_lo = a.j_lo;
@@ -835,6 +842,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
   } else {
     for (int i = threadIdx.x; i < wpb * a.n_ebins; i += blockDim.x) s_eh[i] = 0u;
     for (int i = threadIdx.x; i < wpb * a.n_abins; i += blockDim.x) s_ah[i] = 0u;
+    for (int i = threadIdx.x; i < wpb * a.n_zbins; i += blockDim.x) s_zh[i] = 0u;
   }
   __syncthreads();
 
@@ -845,6 +853,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
   wt.e_dep = 0ull;
   wt.eh = s_eh + w * a.n_ebins;
   wt.ah = s_ah + w * a.n_abins;
+  wt.zh = s_zh + w * a.n_zbins;
   int tag = -1;
   for (uint32_t step = (uint32_t)wg0; step < wg1; step += blockDim.x) {
     const uint32_t base = step + (uint32_t)w * 64u;
@@ -876,7 +885,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
         if (shared)
           flush_wave_lds(wt, jt_cnt(jtab, tag), lane);
         else
-          flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, lane);
+          flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, a.n_zbins, lane);
       }
       tag = j0;
     }
@@ -950,6 +959,18 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
             ny = (float)(qy * il);
             nz = (float)(qz * il);
           }
+        }
+        if (a.n_zbins > 0) {
+          // the ray ends on a surface: its depth below the top of the cell, as
+          // a fraction of the cell height (section 3.3, penetration profile)
+          int zb = (int)floorf((J.sc.hi[2] - pz) / (J.sc.hi[2] - J.sc.lo[2]) * (float)a.n_zbins);
+          zb = min(max(zb, 0), a.n_zbins - 1);
+          if (shared)
+            ladd(jt_eh(jtab, job) + a.n_ebins + a.n_abins + zb, 1u);
+          else if (mine)
+            ladd(wt.zh + zb, 1u);
+          else
+            gadd(gt + T_NCOUNT + a.n_ebins + a.n_abins + zb, 1ull);
         }
         if (gen >= a.max_gen) {
           tally_cnt(mine, wt, gt, T_TRUNCATED, 1ull, jt, job);
@@ -1063,7 +1084,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     if (tag >= 0) flush_wave_lds(wt, jt_cnt(jtab, tag), lane);
     __syncthreads();
     // the workgroup's job blocks to global memory, nonzero entries only
-    const int slots = T_NCOUNT + a.n_ebins + a.n_abins;
+    const int slots = T_NCOUNT + a.n_ebins + a.n_abins + a.n_zbins;
     for (int i = threadIdx.x; i < jtab.J * slots; i += blockDim.x) {
       const int j = i / slots, k = i % slots;
       const LAS unsigned char* blk = jtab.base + (size_t)j * jtab.stride;
@@ -1073,7 +1094,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
       if (v) gadd(a.jobs[jtab.j_lo + j].tally + k, v);
     }
   } else if (tag >= 0) {
-    flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, lane);
+    flush_wave(wt, a.jobs[tag].tally, a.n_ebins, a.n_abins, a.n_zbins, lane);
   }
 }
 
@@ -1198,12 +1219,12 @@ __global__ __launch_bounds__(256) void k_copy_probe(float4* __restrict__ dst4, c
 
 size_t traverse_lds_bytes(int lds_stack, int block) { return (size_t)(block / 64) * lds_stack * 64 * 4; }
 
-size_t shade_lds_bytes(const DevTables& tb, int n_ebins, int n_abins, int block, int n_jobs) {
+size_t shade_lds_bytes(const DevTables& tb, int n_hist, int block, int n_jobs) {
   const int wpb = block / 64;
   size_t off = ((size_t)(tb.nE * tb.nth + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
-  const size_t per_wave = (size_t)wpb * (n_ebins + n_abins) * 4;
+  const size_t per_wave = (size_t)wpb * n_hist * 4;
   const size_t per_job = n_jobs <= kShadeJobs
-                             ? (size_t)n_jobs * ((T_NCOUNT * 8 + (n_ebins + n_abins) * 4 + 7) & ~7)
+                             ? (size_t)n_jobs * ((T_NCOUNT * 8 + n_hist * 4 + 7) & ~7)
                              : 0;
   return off + (per_wave > per_job ? per_wave : per_job);
 }
@@ -1225,7 +1246,7 @@ hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int
 }
 
 hipError_t launch_shade(const ShadeArgs& a, int n_cu, int block, hipStream_t s) {
-  const size_t lds = shade_lds_bytes(a.tb, a.n_ebins, a.n_abins, block, a.j_hi - a.j_lo + 1);
+  const size_t lds = shade_lds_bytes(a.tb, a.n_ebins + a.n_abins + a.n_zbins, block, a.j_hi - a.j_lo + 1);
   // every workgroup resident at once: the waves take equal contiguous slices,
   // so a second round of workgroups would double the kernel's time
   int per_cu = 0;

@@ -151,3 +151,37 @@ def test_cage_parity(ctx, torch, oracle_lib, a, kind):
     sig = math.sqrt(g["yield_sigma"] ** 2 + o["yield_sigma"] ** 2)
     assert abs(g["yield"] - o["yield"]) <= 3 * sig
     assert g["n_substrate"] > 0 and g["n_wraps"] > 0
+
+
+def test_absorption_depth_flat_and_slot(ctx):
+    """Depth histogram: the flat plane's single depth, and the slot's wall-top /
+    floor split at normal incidence (section 3.3)."""
+    n = 3000
+    sid = ctx.load_scene(fg.flat_plane(L=4.0, z0=1.0, height=4.0))
+    for const in (0.0, 2.0):
+        tid = ctx.load_tables(fg.make_tables("constant", const=const))
+        z = ctx.trace(sid, tid, 300.0, 0.0, n, seed=3, max_gen=6, n_zbins=10)["z_hist"]
+        assert z[8] == n and z.sum() == n
+    n = 30000
+    sid = ctx.load_scene(fg.trench(w=2.0, h=3.0, tw=1.0))
+    tid = ctx.load_tables(fg.make_tables("constant", const=0.0))
+    z = ctx.trace(sid, tid, 300.0, 0.0, n, seed=5, max_gen=1, n_zbins=7)["z_hist"]
+    assert z.sum() == n and z[2] + z[5] == n
+    assert abs(z[2] / n - 1 / 3) <= 4 * math.sqrt(2 / 9 / n)
+
+
+@pytest.mark.parametrize("theta", [0.0, -80.0])
+def test_absorption_depth_parity_on_a_foam(ctx, oracle_lib, theta):
+    """Same primaries on the 16^3 foam: the GPU's depth histogram is the oracle's
+    up to FP32 placement of hit points at bin edges."""
+    m = fg.make_grf_foam(16, 0.5, 2.0, seed=0)
+    tab = fg.make_tables("vaughan")
+    sid = ctx.load_scene(m)
+    tid = ctx.load_tables(tab)
+    n = 6000
+    g = ctx.trace(sid, tid, 100.0, theta, n, seed=11, n_zbins=32)
+    o = oracle_lib.trace(m, tab, 100.0, theta, n, seed=11, n_zbins=32)
+    gz, oz = g["z_hist"].astype(np.int64), o["z_hist"].astype(np.int64)
+    assert gz.sum() == g["n_absorbed"] + g["n_truncated"]
+    assert oz.sum() == o["n_absorbed"] + o["n_truncated"]
+    assert np.abs(gz - oz).sum() <= 0.005 * oz.sum() + 2
