@@ -174,6 +174,9 @@ def main():
             "frac": achieved / PEAK_HBM_GBPS,
             "traffic": (traffic["fetch_plus_write_bytes_per_alg_byte"] * alg_bytes / max(tot["launches"], 1)
                         if traffic else None),
+            # from the same committed counter summary (null once the kernel has changed)
+            "valu_issue": traffic.get("valu_issue") if traffic else None,
+            "l2_hit": traffic.get("l2_hit") if traffic else None,
             "kernel": "k_traverse",
             "kernel_ms_total": tot["kms"],
             "shade_ms_total": tot["sms"],
