@@ -168,8 +168,8 @@ DevTables dev_tables(const Tables& t) {
 int grid_of(const rtmc_ctx* c, const rtmc_launch_cfg& cfg) { return c->n_cu * cfg.wg_per_cu; }
 
 // Traversal stack entries a ray can need in a BVH of `depth` binary levels:
-// a 4-wide node spans two of them and pushes at most three children.
-int stack_need(int depth) { return 3 * ((depth + 1) / 2) + 2; }
+// each 4-wide node descends at least one level and pushes at most three children.
+int stack_need(int depth) { return 3 * depth + 2; }
 
 struct HostJob {
   int32_t scene;

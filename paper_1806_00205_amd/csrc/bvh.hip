@@ -300,11 +300,11 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
   return hipGetLastError();
 }
 
-// 4-wide node of binary internal node i: i's children, each internal child
-// replaced by its own two children (leaves stay as they are), so 2 to 4
-// slots.  Traversal starts at node 0 and only ever reaches the nodes of even
-// binary depth; the others are built too (one thread per node, no depth
-// bookkeeping) and never read.
+// 4-wide node of binary internal node i: i's two children, then, while fewer
+// than four slots are filled, the inner slot of largest surface area replaced
+// by its own two children (leaves stay as they are), so 2 to 4 slots.  Every
+// binary node gets its 4-wide node (one thread per node), so a slot may link
+// to a node of any depth; traversal reaches only the ones it links to.
 //
 // A node is 64 bytes (four float4): the origin o of the union box and three
 // power-of-two scales s = 2^e (e biased by 127 in bytes 0..2 of word 3);
@@ -369,18 +369,31 @@ __global__ void k_collapse4(const float4* __restrict__ nodes, int64_t nn, float4
   uint32_t cl[2];
   load_node(nodes, i, cb[0], cb[1], cl[0], cl[1]);
   for (int side = 0; side < 2; ++side) {
-    if (cl[side] & kLeafBit) {
-      for (int q = 0; q < 6; ++q) b[k][q] = cb[side][q];
-      c[k++] = cl[side];
-    } else {
-      float g0[6], g1[6];
-      uint32_t m0, m1;
-      load_node(nodes, cl[side], g0, g1, m0, m1);
-      for (int q = 0; q < 6; ++q) b[k][q] = g0[q];
-      c[k++] = m0;
-      for (int q = 0; q < 6; ++q) b[k][q] = g1[q];
-      c[k++] = m1;
+    for (int q = 0; q < 6; ++q) b[k][q] = cb[side][q];
+    c[k++] = cl[side];
+  }
+  // greedy: expand the inner slot of largest surface area until four slots
+  while (k < 4) {
+    int best = -1;
+    float ba = -1.0f;
+    for (int j = 0; j < k; ++j) {
+      if (c[j] & kLeafBit) continue;
+      const float dx = b[j][3] - b[j][0], dy = b[j][4] - b[j][1], dz = b[j][5] - b[j][2];
+      // unfused, so the choice is reproducible on the host
+      const float area = __fadd_rn(__fadd_rn(__fmul_rn(dx, dy), __fmul_rn(dy, dz)), __fmul_rn(dz, dx));
+      if (area > ba) {
+        ba = area;
+        best = j;
+      }
     }
+    if (best < 0) break;
+    float g0[6], g1[6];
+    uint32_t m0, m1;
+    load_node(nodes, c[best], g0, g1, m0, m1);
+    for (int q = 0; q < 6; ++q) b[best][q] = g0[q];
+    c[best] = m0;
+    for (int q = 0; q < 6; ++q) b[k][q] = g1[q];
+    c[k++] = m1;
   }
   const int used = k;
   for (; k < 4; ++k) c[k] = kEmpty;

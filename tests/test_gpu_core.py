@@ -93,9 +93,9 @@ def _decode(q, s, o):
 
 def _check_wide(wide, nodes, tris, n):
     """Quantized 4-wide nodes against the binary tree they are collapsed from:
-    node i holds the children of binary node i with inner children replaced by
-    theirs; every decoded box contains its child's exact box; the nodes reached
-    from node 0 reference every triangle exactly once."""
+    node i holds the children of binary node i, the largest inner slot
+    expanded until four; every decoded box contains its child's exact box; the
+    nodes reached from node 0 reference every triangle exactly once."""
     links = nodes[:, 12:14].view(np.uint32)
     boxes = nodes[:, :12].reshape(-1, 2, 6)
     tb = tris.reshape(-1, 3, 4)[:, :, :3]
@@ -104,14 +104,23 @@ def _check_wide(wide, nodes, tris, n):
     empty = np.uint32(0xFFFFFFFF)
 
     def slots_of(i):
-        out = []
-        for side in range(2):
-            link = links[i, side]
-            if link & leaf_bit:
-                out.append((link, boxes[i, side]))
-            else:
-                for s2 in range(2):
-                    out.append((links[link, s2], boxes[link, s2]))
+        # i's children, then the inner slot of largest surface area (FP32, first
+        # of equals) replaced by its two children until four slots are filled
+        out = [(links[i, 0], boxes[i, 0]), (links[i, 1], boxes[i, 1])]
+        while len(out) < 4:
+            best, ba = -1, np.float32(-1.0)
+            for j, (link, b) in enumerate(out):
+                if link & leaf_bit:
+                    continue
+                d = (b[3:] - b[:3]).astype(np.float32)
+                area = np.float32(np.float32(d[0] * d[1]) + np.float32(d[1] * d[2])) + np.float32(d[2] * d[0])
+                if area > ba:
+                    best, ba = j, area
+            if best < 0:
+                break
+            link = out[best][0]
+            out[best] = (links[link, 0], boxes[link, 0])
+            out.append((links[link, 1], boxes[link, 1]))
         return out
 
     seen = np.zeros(n, dtype=np.int64)
