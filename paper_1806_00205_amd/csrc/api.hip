@@ -48,8 +48,9 @@ struct Surrogate {
 };
 
 struct Tables {
-  DevBuf buf;  // yield | cdf_E | cdf_F | esee (paper emission)
+  DevBuf buf;  // yield | cdf_E | cdf_F | esee (paper emission) | guide F | guide E (uint16)
   int32_t nE = 0, nth = 0, ncdf = 0, emission = 0;
+  uint32_t e1bits = 0, eshift = 0;
   double Emin = 0, Emax = 0, Ec = 0;
   int max_d = 1;
 };
@@ -162,6 +163,11 @@ DevTables dev_tables(const Tables& t) {
   d.Ec = (float)t.Ec;
   d.esee = t.emission == RTMC_EMIT_PAPER ? d.cdfF + t.ncdf : nullptr;
   d.emission = t.emission;
+  const float* gbase = d.cdfF + t.ncdf + (t.emission == RTMC_EMIT_PAPER ? (size_t)t.nE * t.nth : 0);
+  d.gF = reinterpret_cast<const uint16_t*>(gbase);
+  d.gE = d.gF + kGuide;
+  d.e1bits = t.e1bits;
+  d.eshift = t.eshift;
   return d;
 }
 
@@ -871,7 +877,43 @@ rtmc_status rtmc_load_tables(rtmc_ctx* c, const rtmc_tables* t, int32_t* table_i
   tb.max_d = std::max(1, (int)std::ceil(ymax));
   tb.emission = t->emission;
   const size_t ny = (size_t)tb.nE * tb.nth;
-  std::vector<float> h(ny + 2 * (size_t)tb.ncdf + (tb.emission == RTMC_EMIT_PAPER ? ny : 0));
+  const size_t nf = ny + 2 * (size_t)tb.ncdf + (tb.emission == RTMC_EMIT_PAPER ? ny : 0);
+  // guide tables of the CDF look-ups (2 x kGuide uint16 = kGuide floats)
+  std::vector<float> h(nf + kGuide);
+  {
+    const int n = tb.ncdf;
+    std::vector<uint16_t> gF(kGuide), gE(kGuide);
+    // gF[b] = (smallest m >= 1 with cdf_F[m] >= b / kGuide) - 1
+    int m = 1;
+    for (int b = 0; b < kGuide; ++b) {
+      const float tb_ = (float)b / (float)kGuide;
+      while (m < n - 1 && !(t->cdf_F[m] >= tb_)) ++m;
+      gF[b] = (uint16_t)(m - 1);
+    }
+    // gE over the bit patterns of positive energies from cdf_E[1] to cdf_E[n - 1]
+    uint32_t e1, en;
+    std::memcpy(&e1, &t->cdf_E[1], 4);
+    std::memcpy(&en, &t->cdf_E[n - 1], 4);
+    uint32_t shift = 0;
+    while (((en - e1) >> shift) >= (uint32_t)kGuide) ++shift;
+    int k = 1;
+    for (int b = 0; b < kGuide; ++b) {
+      const uint64_t bits = (uint64_t)e1 + ((uint64_t)b << shift);
+      float v;
+      if (bits >= en) {
+        v = t->cdf_E[n - 1];
+      } else {
+        const uint32_t b32 = (uint32_t)bits;
+        std::memcpy(&v, &b32, 4);
+      }
+      while (k + 1 < n - 1 && t->cdf_E[k + 1] <= v) ++k;
+      gE[b] = (uint16_t)k;  // last node at or below v (v >= cdf_E[1])
+    }
+    tb.e1bits = e1;
+    tb.eshift = shift;
+    std::memcpy(h.data() + nf, gF.data(), 2 * kGuide);
+    std::memcpy(reinterpret_cast<char*>(h.data() + nf) + 2 * kGuide, gE.data(), 2 * kGuide);
+  }
   std::memcpy(h.data(), t->yield, sizeof(float) * ny);
   std::memcpy(h.data() + ny, t->cdf_E, sizeof(float) * tb.ncdf);
   std::memcpy(h.data() + ny + tb.ncdf, t->cdf_F, sizeof(float) * tb.ncdf);

@@ -29,6 +29,7 @@ constexpr int kMaxAbins = 360;
 constexpr int kMaxZbins = 256;
 constexpr int kMaxYield = 8192;
 constexpr int kMaxCdf = 1024;
+constexpr int kGuide = 1024;  // entries of each CDF guide table
 constexpr int kGlobalStack = 64;  // minimum traversal stack entries per lane beyond the LDS part
 constexpr int kClaimMax = 2048;   // largest block of rays one traversal wave claims at once
 constexpr int kShadeJobs = 8;     // chunks with at most this many jobs tally per workgroup in LDS
@@ -69,6 +70,12 @@ struct DevTables {
   const float* cdfE;
   const float* cdfF;
   const float* esee;  // E_SEE on the yield grid (paper emission), else null
+  // guide tables of the CDF look-ups (kGuide entries each): gF[b] = first
+  // segment whose upper CDF value reaches b / kGuide; gE[b] = last node at or
+  // below the energy with bit pattern e1bits + (b << eshift), e1bits = cdfE[1]
+  const uint16_t* gF;
+  const uint16_t* gE;
+  uint32_t e1bits, eshift;
   int32_t nE, nth, ncdf;
   int32_t emission;   // RTMC_EMIT_SPECTRUM or RTMC_EMIT_PAPER
   float logEmin, invdlogE, thscale, Ec;

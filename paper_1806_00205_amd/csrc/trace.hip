@@ -185,33 +185,31 @@ __device__ inline float table_yield(P yld, const DevTables& tb, float E, float a
          fx * fy * row1[1];
 }
 
-// piecewise-linear CDF at E
-__device__ inline float cdf_at(const LAS float* cE, const LAS float* cF, int n, float E) {
+// Piecewise-linear CDF at E.  The segment (last node at or below E) starts
+// from a guide table over the bit patterns of positive energies, which are
+// ordered like the energies, and moves forward; it is the segment a binary
+// search would find.
+__device__ inline float cdf_at(const LAS float* cE, const LAS float* cF, int n, const LAS uint16_t* gE,
+                               uint32_t e1bits, uint32_t eshift, float E) {
   if (E <= cE[0]) return cF[0];
   if (E >= cE[n - 1]) return cF[n - 1];
-  int lo = 0, hi = n - 1;  // cE[lo] <= E < cE[hi]
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (cE[mid] <= E)
-      lo = mid;
-    else
-      hi = mid;
+  int lo = 0;
+  if (E >= cE[1]) {
+    const uint32_t b = (__float_as_uint(E) - e1bits) >> eshift;
+    lo = gE[b < (uint32_t)kGuide ? b : (uint32_t)kGuide - 1u];
+    while (cE[lo + 1] <= E) ++lo;
   }
   return cF[lo] + (E - cE[lo]) / (cE[lo + 1] - cE[lo]) * (cF[lo + 1] - cF[lo]);
 }
 
-// energy where the piecewise-linear CDF first reaches c
-__device__ inline float cdf_inv(const LAS float* cE, const LAS float* cF, int n, float c) {
-  int lo = 0, hi = n - 1;  // smallest m >= 1 with cF[m] >= c lies in (lo, hi]
-  if (!(cF[hi] >= c)) return cE[n - 1];
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (cF[mid] >= c)
-      hi = mid;
-    else
-      lo = mid;
-  }
-  const int k = hi - 1;
+// Energy where the piecewise-linear CDF first reaches c (0 < c <= 1): the
+// first node m >= 1 with cF[m] >= c, starting from the guide table's lower
+// bound for c.
+__device__ inline float cdf_inv(const LAS float* cE, const LAS float* cF, int n, const LAS uint16_t* gF, float c) {
+  if (!(cF[n - 1] >= c)) return cE[n - 1];
+  const int b = min(max((int)(c * (float)kGuide), 0), kGuide - 1);
+  int k = gF[b];
+  while (!(cF[k + 1] >= c)) ++k;
   const float f0 = cF[k], f1 = cF[k + 1];
   if (f1 <= f0) return cE[k];
   return cE[k] + (c - f0) / (f1 - f0) * (cE[k + 1] - cE[k]);
@@ -807,7 +805,9 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
   LAS float* s_yld = (LAS float*)lds;
   LAS float* s_cE = s_yld + nY;
   LAS float* s_cF = s_cE + tb.ncdf;
-  size_t off = ((size_t)(nY + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
+  LAS uint16_t* s_gF = (LAS uint16_t*)(s_cF + tb.ncdf);
+  LAS uint16_t* s_gE = s_gF + kGuide;
+  size_t off = ((size_t)(nY + 2 * tb.ncdf) * 4 + 4 * kGuide + 15) & ~(size_t)15;
   LAS uint32_t* s_eh = (LAS uint32_t*)(lds + off);
   LAS uint32_t* s_ah = s_eh + wpb * a.n_ebins;
   LAS uint32_t* s_zh = s_ah + wpb * a.n_abins;
@@ -835,6 +835,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
   for (int i = threadIdx.x; i < tb.ncdf; i += blockDim.x) {
     s_cE[i] = gp(tb.cdfE)[i];
     s_cF[i] = gp(tb.cdfF)[i];
+  }
+  for (int i = threadIdx.x; i < kGuide; i += blockDim.x) {
+    s_gF[i] = gp(tb.gF)[i];
+    s_gE[i] = gp(tb.gE)[i];
   }
   if (shared) {
     const int words = jtab.J * jtab.stride / 4;
@@ -1026,7 +1030,8 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
         const U4 u = philox(J.seed, (uint32_t)pid, (uint32_t)(pid >> 32), path, 2u + (uint32_t)d);
         float Ed, xb;  // energy and sin^2 of the angle from the normal
         if (!paper) {
-          Ed = cdf_inv(s_cE, s_cF, tb.ncdf, u01(u.x) * cdf_at(s_cE, s_cF, tb.ncdf, Eav));
+          Ed = cdf_inv(s_cE, s_cF, tb.ncdf, s_gF,
+                       u01(u.x) * cdf_at(s_cE, s_cF, tb.ncdf, s_gE, tb.e1bits, tb.eshift, Eav));
           xb = u01(u.y);
         } else if (d & 1) {  // second of a pair: beta2 = pi/2 - beta1, E2 = cos^2(beta1) E_SEE
           Ed = (1.0f - xi_pair) * es;
@@ -1221,7 +1226,7 @@ size_t traverse_lds_bytes(int lds_stack, int block) { return (size_t)(block / 64
 
 size_t shade_lds_bytes(const DevTables& tb, int n_hist, int block, int n_jobs) {
   const int wpb = block / 64;
-  size_t off = ((size_t)(tb.nE * tb.nth + 2 * tb.ncdf) * 4 + 15) & ~(size_t)15;
+  size_t off = ((size_t)(tb.nE * tb.nth + 2 * tb.ncdf) * 4 + 4 * kGuide + 15) & ~(size_t)15;
   const size_t per_wave = (size_t)wpb * n_hist * 4;
   const size_t per_job = n_jobs <= kShadeJobs
                              ? (size_t)n_jobs * ((T_NCOUNT * 8 + n_hist * 4 + 7) & ~7)

@@ -389,3 +389,53 @@ def test_errors_are_reported(ctx, vaughan):
                    m.box_lo, m.box_hi, m.flags, {})
     s2 = ctx.load_scene(zero)
     assert ctx.scene_info(s2)["n_dropped"] == 1
+
+
+def test_batch_graph_replays_match_eager(ctx, tiny, vaughan):
+    """rtmc_trace_batch records its launch sequence once as a HIP graph and
+    replays it for later calls of the same shape: replay it several times,
+    with eager traces (other kernels, synchronisations) in between, and check
+    every replay against the eager single-job results."""
+    s1 = ctx.load_scene(tiny)
+    s2 = ctx.load_scene(fg.make_grf_foam(12, 0.7, 2.0, seed=5))
+    tid = ctx.load_tables(vaughan)
+    keys = ("n_rays", "n_escaped", "n_absorbed", "n_truncated", "n_lost", "n_tri_tests", "n_node_visits",
+            "e_escaped", "e_deposited")
+    for rep in range(4):
+        seeds = (11 + rep, 12 + rep, 13 + rep)
+        jobs = [(s1, 500.0, 0.0, 3000, seeds[0]), (s2, 150.0, 30.0, 2000, seeds[1]),
+                (s1, 900.0, -80.0, 2500, seeds[2])]
+        outs = ctx.trace_batch(tid, jobs, max_gen=6)
+        eager = [ctx.trace(s, tid, E, th, n, seed=sd, max_gen=6) for s, E, th, n, sd in jobs]
+        for b, r in zip(outs, eager):
+            for k in keys:
+                assert b[k] == r[k], (rep, k, b[k], r[k])
+
+
+def test_irregular_spectrum_table(ctx, oracle_lib):
+    """Secondary energies from an irregular CDF (uneven nodes, plateaus where F
+    stays flat, steep jumps): the GPU's look-ups land in the same segments as
+    the oracle's scan, so the escaped-energy histograms of the same primaries
+    agree bin by bin up to FP32 rounding."""
+    rng = np.random.default_rng(3)
+    n_cdf = 300
+    cE = np.concatenate([[0.0], np.sort(rng.uniform(0.05, 900.0, n_cdf - 1))]).astype(np.float32)
+    steps = rng.exponential(1.0, n_cdf - 1)
+    steps[rng.random(n_cdf - 1) < 0.2] = 0.0  # plateaus
+    steps[rng.integers(0, n_cdf - 1, 5)] *= 40.0  # jumps
+    cF = np.concatenate([[0.0], np.cumsum(steps)])
+    cF = (cF / cF[-1]).astype(np.float32)
+    cF[-1] = 1.0
+    assert np.all(np.diff(cE) > 0) and np.all(np.diff(cF) >= 0)
+    tab = fg.make_tables("constant", const=1.0)
+    tab.cdf_E, tab.cdf_F = cE, cF
+    sid = ctx.load_scene(fg.flat_plane())
+    tid = ctx.load_tables(tab)
+    n = 20000
+    E0 = 700.0
+    g = ctx.trace(sid, tid, E0, 0.0, n, seed=19, max_gen=1, n_ebins=350)
+    o = oracle_lib.trace(fg.flat_plane(), tab, E0, 0.0, n, seed=19, max_gen=1, n_ebins=350)
+    assert g["n_escaped"] == o["n_escaped"] == n
+    diff = np.abs(g["e_hist"].astype(np.int64) - o["e_hist"].astype(np.int64)).sum()
+    assert diff <= 0.002 * n, diff
+    assert g["e_escaped"] == pytest.approx(o["e_escaped"], rel=1e-4)
