@@ -304,6 +304,11 @@ class Context:
         self._chk(self.lib.rtmc_sort_pairs_u64(self.h, C.c_void_p(keys.data_ptr()), C.c_void_p(vals.data_ptr()),
                                                keys.numel(), int(key_bits)))
 
+    def set_stream(self, stream):
+        """Enqueue later work on a torch.cuda.Stream (use it as torch's current
+        stream too, so the caching allocator's stream matches)."""
+        self._chk(self.lib.rtmc_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
+
     def set_launch(self, block: int, wg_per_cu: int, lds_stack: int, chunk: int, refill: int = 16, occupancy: int = 0):
         self._chk(self.lib.rtmc_set_launch(self.h, C.byref(LaunchCfg(block, wg_per_cu, lds_stack, chunk, refill,
                                                                      occupancy))))

@@ -439,3 +439,76 @@ def test_irregular_spectrum_table(ctx, oracle_lib):
     diff = np.abs(g["e_hist"].astype(np.int64) - o["e_hist"].astype(np.int64)).sum()
     assert diff <= 0.002 * n, diff
     assert g["e_escaped"] == pytest.approx(o["e_escaped"], rel=1e-4)
+
+
+LAUNCHES = [(256, 6, 16, 1 << 24, 48, 0), (128, 12, 8, 5000, 24, 8), (64, 24, 24, 1 << 20, 64, 0),
+            (256, 2, 4, 3000, 1, 0)]
+
+
+def test_launch_shapes_do_not_change_results(ctx, tiny, vaughan):
+    """Block size, workgroups per CU, LDS stack depth, chunking, refill threshold
+    and the register-capped kernel change only speed: every tally, the
+    traversal work counters included, is identical."""
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    cfg = ctx.get_launch()
+    keys = ("n_rays", "n_escaped", "n_absorbed", "n_truncated", "n_lost", "n_substrate", "n_wraps",
+            "n_node_visits", "n_tri_tests", "n_spawned", "e_escaped", "e_deposited")
+    try:
+        ref = None
+        for launch in LAUNCHES:
+            ctx.set_launch(*launch)
+            r = ctx.trace(sid, tid, 400.0, -60.0, 12000, seed=23, max_gen=8)
+            got = {k: r[k] for k in keys}
+            got["e_hist"] = r["e_hist"].tolist()
+            if ref is None:
+                ref = got
+            assert got == ref, launch
+    finally:
+        ctx.set_launch(**cfg)
+
+
+def test_autotune_keeps_results(ctx, tiny, vaughan):
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    cfg = ctx.get_launch()
+    try:
+        before = ctx.trace(sid, tid, 300.0, 20.0, 8000, seed=29)
+        best = ctx.autotune(sid, tid, 300.0, 20.0, 20000)
+        assert best == ctx.get_launch()
+        assert best["block"] in (64, 128, 256) and best["wg_per_cu"] >= 1 and 1 <= best["refill"] <= 64
+        after = ctx.trace(sid, tid, 300.0, 20.0, 8000, seed=29)
+        for k in ("n_rays", "n_escaped", "n_node_visits", "n_tri_tests", "e_escaped"):
+            assert before[k] == after[k], k
+    finally:
+        ctx.set_launch(**cfg)
+
+
+def test_copy_probe_copies_and_measures(ctx, torch):
+    import ctypes as C
+    n = 1 << 22
+    src = torch.arange(n, dtype=torch.float32, device="cuda:0")
+    dst = torch.zeros_like(src)
+    ms = C.c_double()
+    st = ctx.lib.rtmc_copy_probe(ctx.h, C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), n * 4, 3,
+                                 C.byref(ms))
+    assert st == 0 and ms.value > 0
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    gbps = ctx.copy_probe(1 << 28, reps=3)
+    assert 500.0 < gbps < 10000.0
+
+
+def test_work_on_another_stream(ctx, torch, tiny, vaughan):
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    ref = ctx.trace(sid, tid, 600.0, 0.0, 5000, seed=31)
+    s = torch.cuda.Stream()
+    try:
+        with torch.cuda.stream(s):
+            ctx.set_stream(s)
+            r = ctx.trace(sid, tid, 600.0, 0.0, 5000, seed=31)
+    finally:
+        ctx.set_stream(torch.cuda.current_stream())
+    for k in ("n_rays", "n_escaped", "n_tri_tests", "e_escaped"):
+        assert r[k] == ref[k], k
