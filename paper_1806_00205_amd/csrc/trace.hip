@@ -133,6 +133,17 @@ __device__ inline bool box_test(const RayP& r, float lx, float ly, float lz, flo
   return t0 <= fminf(t1, tmax);
 }
 
+// Slab test with the entry (near) and exit (far) planes of each axis already
+// chosen from the sign of the ray's direction: the same distances as taking
+// the min and max of both planes, since rounding is monotone.
+__device__ inline bool box_test_nf(const RayP& r, float nx, float ny, float nz, float fx, float fy, float fz,
+                                   float tmax, float& tn) {
+  const float t0 = fmaxf(fmaxf((nx - r.ox) * r.ix, (ny - r.oy) * r.iy), fmaxf((nz - r.oz) * r.iz, 0.0f));
+  const float t1 = fminf(fminf((fx - r.ox) * r.ix, (fy - r.oy) * r.iy), (fz - r.oz) * r.iz) * kRobust;
+  tn = t0;
+  return t0 <= fminf(t1, tmax);
+}
+
 // Watertight ray/triangle test with back-face culling.  U, V, W are the
 // sheared edge functions (weights of V0, V1, V2); products are kept
 // unfused so that an edge shared by two triangles gets exactly opposite
@@ -467,16 +478,20 @@ __device__ inline bool trav_step(Trav& s, const LaneScene& L, LAS uint32_t* lstk
               sz = __uint_as_float(((ex >> 16) & 0xFFu) << 23);
   const uint32_t qlx = __float_as_uint(q2.x), qly = __float_as_uint(q2.y), qlz = __float_as_uint(q2.z),
                  qhx = __float_as_uint(q2.w), qhy = __float_as_uint(q3.x), qhz = __float_as_uint(q3.y);
+  // per axis, the bound the ray enters through and the one it leaves through
+  const bool px = s.r.ix >= 0.0f, py = s.r.iy >= 0.0f, pz = s.r.iz >= 0.0f;
+  const uint32_t qnx = px ? qlx : qhx, qfx = px ? qhx : qlx, qny = py ? qly : qhy, qfy = py ? qhy : qly,
+                 qnz = pz ? qlz : qhz, qfz = pz ? qhz : qlz;
 #define CHILD_BOX(j)                                                                                      \
-  dq(qlx, j, sx, q0.x), dq(qly, j, sy, q0.y), dq(qlz, j, sz, q0.z), dq(qhx, j, sx, q0.x), dq(qhy, j, sy, q0.y), \
-      dq(qhz, j, sz, q0.z)
+  dq(qnx, j, sx, q0.x), dq(qny, j, sy, q0.y), dq(qnz, j, sz, q0.z), dq(qfx, j, sx, q0.x), dq(qfy, j, sy, q0.y), \
+      dq(qfz, j, sz, q0.z)
   float d0, d1, d2, d3;
   uint32_t c0 = __float_as_uint(lk.x), c1 = __float_as_uint(lk.y), c2 = __float_as_uint(lk.z),
            c3 = __float_as_uint(lk.w);
-  bool h0 = box_test(s.r, CHILD_BOX(0), s.t, d0) && c0 != kEmpty;
-  bool h1 = box_test(s.r, CHILD_BOX(1), s.t, d1) && c1 != kEmpty;
-  bool h2 = box_test(s.r, CHILD_BOX(2), s.t, d2) && c2 != kEmpty;
-  bool h3 = box_test(s.r, CHILD_BOX(3), s.t, d3) && c3 != kEmpty;
+  bool h0 = box_test_nf(s.r, CHILD_BOX(0), s.t, d0) && c0 != kEmpty;
+  bool h1 = box_test_nf(s.r, CHILD_BOX(1), s.t, d1) && c1 != kEmpty;
+  bool h2 = box_test_nf(s.r, CHILD_BOX(2), s.t, d2) && c2 != kEmpty;
+  bool h3 = box_test_nf(s.r, CHILD_BOX(3), s.t, d3) && c3 != kEmpty;
 #undef CHILD_BOX
   // leaf children hit: one loop over the lane's own leaves, so the wave runs
   // as many triangle tests as its busiest lane rather than one per slot
