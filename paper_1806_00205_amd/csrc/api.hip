@@ -139,10 +139,15 @@ DevScene dev_scene(const Scene& s) {
   DevScene d;
   d.nodes = reinterpret_cast<const float4*>(s.nodes4.p);
   d.tris = reinterpret_cast<const float4*>(s.tris.p);
+  double w = 0.0;
   for (int a = 0; a < 3; ++a) {
     d.lo[a] = (float)s.lo[a];
     d.hi[a] = (float)s.hi[a];
+    w = std::max(w, std::max(std::fabs(s.lo[a]), std::fabs(s.hi[a])));
   }
+  // every vertex lies in the box; a quantized node plane overshoots the
+  // bound by less than one code step, at most 4/255 of it
+  d.wext = (float)(w * 1.03);
   d.n_tris = (int32_t)s.n_tris;
   d.flags = s.flags;
   return d;

@@ -310,10 +310,10 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
 // power-of-two scales s = 2^e (e biased by 127 in bytes 0..2 of word 3);
 // the four child links (kEmpty: unused slot); the child boxes quantized to
 // bytes, lo_x[4] lo_y[4] lo_z[4] hi_x[4] in float4 2 and hi_y[4] hi_z[4] in
-// float4 3.  A child's box decodes as fmaf(q, s, o) per bound -- the very
-// operation traversal performs -- and the builder moves each code outwards
-// until that decoded box contains the exact one, so traversal stays
-// conservative.
+// float4 3.  A child's box decodes as fmaf(q, s, o) per bound, and the
+// builder moves each code outwards until that decoded box contains the exact
+// one; traversal's slab distances to the decoded planes carry a margin that
+// covers their own rounding, so traversal stays conservative.
 __device__ inline void load_node(const float4* nodes, int64_t i, float b0[6], float b1[6], uint32_t& l0,
                                  uint32_t& l1) {
   const float4 n0 = nodes[4 * i], n1 = nodes[4 * i + 1], n2 = nodes[4 * i + 2], n3 = nodes[4 * i + 3];

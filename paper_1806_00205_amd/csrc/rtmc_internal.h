@@ -61,6 +61,7 @@ struct DevScene {
   const float4* nodes;  // quantized 4-wide nodes, 4 float4 each
   const float4* tris;
   float lo[3], hi[3];
+  float wext;  // bound on the magnitude of every coordinate of the scene and its node planes
   int32_t n_tris;
   uint32_t flags;
 };

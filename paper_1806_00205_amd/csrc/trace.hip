@@ -42,9 +42,9 @@ __device__ inline const GAS T* gp(const T* p) {
 
 constexpr float kPi = 3.14159265358979323846f;
 constexpr float kDeg = 57.295779513082320876f;  // 180 / pi
-// Conservative far-slab factor: 1 + 2 gamma(3) for the subtraction and the
-// product, widened for the 1-ulp hardware reciprocal of the direction.
-constexpr float kRobust = 1.0000008f;
+// Absolute margin of the node slab distances, per unit of coordinate
+// magnitude and of |1/d|: 1.05 * 2^-20 (see slab_margins).
+constexpr float kSlack = 1.05f / 1048576.0f;
 
 __device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
@@ -84,8 +84,9 @@ __device__ inline float u01(uint32_t u) { return (float)((u >> 8) + 1u) * 5.9604
 struct RayP {
   float ox, oy, oz, dx, dy, dz;
   float ix, iy, iz;
+  float w;  // slab margin of the current segment per unit of |1/d|
   float Sx, Sy, Sz;
-  int kx, ky, kz;
+  uint32_t kk;  // shear axes: kx | ky << 2 | kz << 4
 };
 
 __device__ inline float pick(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
@@ -113,33 +114,35 @@ __device__ inline void ray_setup(RayP& r, float dx, float dy, float dz) {
     kx = ky;
     ky = t;
   }
-  r.kx = kx;
-  r.ky = ky;
-  r.kz = kz;
+  r.kk = (uint32_t)kx | ((uint32_t)ky << 2) | ((uint32_t)kz << 4);
   // any per-ray shear is watertight as long as every triangle sees the same one
   r.Sz = __builtin_amdgcn_rcpf(dkz);
   r.Sx = pick(dx, dy, dz, kx) * r.Sz;
   r.Sy = pick(dx, dy, dz, ky) * r.Sz;
 }
 
-__device__ inline bool box_test(const RayP& r, float lx, float ly, float lz, float hx, float hy, float hz, float tmax,
-                                float& tn) {
-  const float tx0 = (lx - r.ox) * r.ix, tx1 = (hx - r.ox) * r.ix;
-  const float ty0 = (ly - r.oy) * r.iy, ty1 = (hy - r.oy) * r.iy;
-  const float tz0 = (lz - r.oz) * r.iz, tz1 = (hz - r.oz) * r.iz;
-  const float t0 = fmaxf(fmaxf(fminf(tx0, tx1), fminf(ty0, ty1)), fmaxf(fminf(tz0, tz1), 0.0f));
-  const float t1 = fminf(fminf(fmaxf(tx0, tx1), fmaxf(ty0, ty1)), fmaxf(tz0, tz1)) * kRobust;
-  tn = t0;
-  return t0 <= fminf(t1, tmax);
+// Margins of the fused slab distances of one segment.  A node's child plane
+// is at b = fma(q, s, o) (s a power of two, so q*s*ix is exact); its distance
+// is taken as fma(q, s*ix, (o - O)*ix -/+ m) in place of (b - O)*ix.  With
+// every coordinate (planes, node origins, ray origin) bounded by W in
+// magnitude, the rounding of b, of o - O and of the two fused operations
+// moves that distance by at most about 5 * 2^-24 * W * |ix|, and the
+// relative error of the reciprocal and the last rounding (3 ulp of a
+// distance of at most 2 W |ix|) by at most 6 * 2^-24 * W * |ix|.  The
+// margin m = 16.8 * 2^-24 * W * |ix| exceeds both together, so the near
+// distance never exceeds the exact one and the far distance never falls
+// short of it: the slab test is conservative without a relative factor.
+// W takes the scene's coordinate bound (which covers decoded planes and
+// node origins) and the segment origin, so rays from outside the cell are
+// covered too.
+__device__ inline void slab_margins(RayP& r, float wext) {
+  r.w = fmaxf(fmaxf(wext, fabsf(r.ox)), fmaxf(fabsf(r.oy), fabsf(r.oz))) * kSlack;
 }
 
-// Slab test with the entry (near) and exit (far) planes of each axis already
-// chosen from the sign of the ray's direction: the same distances as taking
-// the min and max of both planes, since rounding is monotone.
-__device__ inline bool box_test_nf(const RayP& r, float nx, float ny, float nz, float fx, float fy, float fz,
-                                   float tmax, float& tn) {
-  const float t0 = fmaxf(fmaxf((nx - r.ox) * r.ix, (ny - r.oy) * r.iy), fmaxf((nz - r.oz) * r.iz, 0.0f));
-  const float t1 = fminf(fminf((fx - r.ox) * r.ix, (fy - r.oy) * r.iy), (fz - r.oz) * r.iz) * kRobust;
+// Slab test of one child from its near and far distances per axis.
+__device__ inline bool box_hit(float nx, float ny, float nz, float fx, float fy, float fz, float tmax, float& tn) {
+  const float t0 = fmaxf(fmaxf(nx, ny), fmaxf(nz, 0.0f));
+  const float t1 = fminf(fminf(fx, fy), fz);
   tn = t0;
   return t0 <= fminf(t1, tmax);
 }
@@ -153,10 +156,11 @@ __device__ inline bool tri_test(const RayP& r, f4v a, f4v b, f4v c, float tbest,
   const float ax = a.x - r.ox, ay = a.y - r.oy, az = a.z - r.oz;
   const float bx = b.x - r.ox, by = b.y - r.oy, bz = b.z - r.oz;
   const float cx = c.x - r.ox, cy = c.y - r.oy, cz = c.z - r.oz;
-  const float Akz = pick(ax, ay, az, r.kz), Bkz = pick(bx, by, bz, r.kz), Ckz = pick(cx, cy, cz, r.kz);
-  const float Ax = fmaf(-r.Sx, Akz, pick(ax, ay, az, r.kx)), Ay = fmaf(-r.Sy, Akz, pick(ax, ay, az, r.ky));
-  const float Bx = fmaf(-r.Sx, Bkz, pick(bx, by, bz, r.kx)), By = fmaf(-r.Sy, Bkz, pick(bx, by, bz, r.ky));
-  const float Cx = fmaf(-r.Sx, Ckz, pick(cx, cy, cz, r.kx)), Cy = fmaf(-r.Sy, Ckz, pick(cx, cy, cz, r.ky));
+  const int kx = (int)(r.kk & 3u), ky = (int)((r.kk >> 2) & 3u), kz = (int)(r.kk >> 4);
+  const float Akz = pick(ax, ay, az, kz), Bkz = pick(bx, by, bz, kz), Ckz = pick(cx, cy, cz, kz);
+  const float Ax = fmaf(-r.Sx, Akz, pick(ax, ay, az, kx)), Ay = fmaf(-r.Sy, Akz, pick(ax, ay, az, ky));
+  const float Bx = fmaf(-r.Sx, Bkz, pick(bx, by, bz, kx)), By = fmaf(-r.Sy, Bkz, pick(bx, by, bz, ky));
+  const float Cx = fmaf(-r.Sx, Ckz, pick(cx, cy, cz, kx)), Cy = fmaf(-r.Sy, Ckz, pick(cx, cy, cz, ky));
   float U = __fsub_rn(__fmul_rn(Cx, By), __fmul_rn(Cy, Bx));
   float V = __fsub_rn(__fmul_rn(Ax, Cy), __fmul_rn(Ay, Cx));
   float W = __fsub_rn(__fmul_rn(Bx, Ay), __fmul_rn(By, Ax));
@@ -411,6 +415,7 @@ __device__ inline void seg_begin(Trav& s, const DevScene& sc) {
   float te0, te1, te2;
   exit_dists(s.r, sc, te0, te1, te2);
   s.t = fminf(fminf(te0, te1), te2);
+  slab_margins(s.r, sc.wext);
   s.idx = -1;
   s.oid = 0x7fffffff;
   s.node = 0;
@@ -458,11 +463,6 @@ __device__ inline void cswap(float& da, uint32_t& na, float& db, uint32_t& nb) {
   na = n;
 }
 
-// Byte j of a quantized bound, decoded exactly as the builder checked it.
-__device__ inline float dq(uint32_t w, int j, float sc, float o) {
-  return fmaf((float)((w >> (8 * j)) & 0xFFu), sc, o);
-}
-
 // One 4-wide node of the traversal.  Returns true when the segment's
 // traversal has finished (stack empty).  Leaf children whose boxes the ray
 // enters are tested at once (which can shorten the ray before the inner
@@ -473,25 +473,34 @@ __device__ inline bool trav_step(Trav& s, const LaneScene& L, LAS uint32_t* lstk
   const GAS f4v* N = (const GAS f4v*)L.nodes + 4 * (size_t)s.node;
   const f4v q0 = N[0], lk = N[1], q2 = N[2], q3 = N[3];
   ++visits;
+  const RayP& r = s.r;
+  // per axis: distance per code step (exact, the scale being a power of
+  // two) and the near and far distances of the node origin with the margin
   const uint32_t ex = __float_as_uint(q0.w);
-  const float sx = __uint_as_float((ex & 0xFFu) << 23), sy = __uint_as_float(((ex >> 8) & 0xFFu) << 23),
-              sz = __uint_as_float(((ex >> 16) & 0xFFu) << 23);
+  const float ax = __uint_as_float((ex & 0xFFu) << 23) * r.ix, ay = __uint_as_float(((ex >> 8) & 0xFFu) << 23) * r.iy,
+              az = __uint_as_float(((ex >> 16) & 0xFFu) << 23) * r.iz;
+  const float bx = q0.x - r.ox, by = q0.y - r.oy, bz = q0.z - r.oz;
+  const float mx = r.w * fabsf(r.ix), my = r.w * fabsf(r.iy), mz = r.w * fabsf(r.iz);
+  const float nbx = fmaf(bx, r.ix, -mx), nby = fmaf(by, r.iy, -my), nbz = fmaf(bz, r.iz, -mz);
+  const float fbx = fmaf(bx, r.ix, mx), fby = fmaf(by, r.iy, my), fbz = fmaf(bz, r.iz, mz);
   const uint32_t qlx = __float_as_uint(q2.x), qly = __float_as_uint(q2.y), qlz = __float_as_uint(q2.z),
                  qhx = __float_as_uint(q2.w), qhy = __float_as_uint(q3.x), qhz = __float_as_uint(q3.y);
   // per axis, the bound the ray enters through and the one it leaves through
-  const bool px = s.r.ix >= 0.0f, py = s.r.iy >= 0.0f, pz = s.r.iz >= 0.0f;
+  const bool px = r.ix >= 0.0f, py = r.iy >= 0.0f, pz = r.iz >= 0.0f;
   const uint32_t qnx = px ? qlx : qhx, qfx = px ? qhx : qlx, qny = py ? qly : qhy, qfy = py ? qhy : qly,
                  qnz = pz ? qlz : qhz, qfz = pz ? qhz : qlz;
-#define CHILD_BOX(j)                                                                                      \
-  dq(qnx, j, sx, q0.x), dq(qny, j, sy, q0.y), dq(qnz, j, sz, q0.z), dq(qfx, j, sx, q0.x), dq(qfy, j, sy, q0.y), \
-      dq(qfz, j, sz, q0.z)
+#define QB(w, j) ((float)(((w) >> (8 * (j))) & 0xFFu))
+#define CHILD_BOX(j)                                                                                           \
+  fmaf(QB(qnx, j), ax, nbx), fmaf(QB(qny, j), ay, nby), fmaf(QB(qnz, j), az, nbz), fmaf(QB(qfx, j), ax, fbx), \
+      fmaf(QB(qfy, j), ay, fby), fmaf(QB(qfz, j), az, fbz)
   float d0, d1, d2, d3;
   uint32_t c0 = __float_as_uint(lk.x), c1 = __float_as_uint(lk.y), c2 = __float_as_uint(lk.z),
            c3 = __float_as_uint(lk.w);
-  bool h0 = box_test_nf(s.r, CHILD_BOX(0), s.t, d0) && c0 != kEmpty;
-  bool h1 = box_test_nf(s.r, CHILD_BOX(1), s.t, d1) && c1 != kEmpty;
-  bool h2 = box_test_nf(s.r, CHILD_BOX(2), s.t, d2) && c2 != kEmpty;
-  bool h3 = box_test_nf(s.r, CHILD_BOX(3), s.t, d3) && c3 != kEmpty;
+  bool h0 = box_hit(CHILD_BOX(0), s.t, d0) && c0 != kEmpty;
+  bool h1 = box_hit(CHILD_BOX(1), s.t, d1) && c1 != kEmpty;
+  bool h2 = box_hit(CHILD_BOX(2), s.t, d2) && c2 != kEmpty;
+  bool h3 = box_hit(CHILD_BOX(3), s.t, d3) && c3 != kEmpty;
+#undef QB
 #undef CHILD_BOX
   // leaf children hit: one loop over the lane's own leaves, so the wave runs
   // as many triangle tests as its busiest lane rather than one per slot
@@ -761,11 +770,11 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
   }
 }
 
-// Register-limited variants: the default lets the compiler choose (about 6
-// waves per SIMD); O8 caps registers for 8 waves per SIMD at the price of a
+// Register-limited variants: the default caps registers for 6 waves per SIMD
+// (80 VGPRs, no spills); O8 caps them for 8 waves per SIMD at the price of a
 // few spilled, rarely used values.  The autotuner picks by measurement.
 template <bool MULTI>
-__global__ __launch_bounds__(256) void k_traverse(TraverseArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_traverse(TraverseArgs a) {
   traverse_body<MULTI>(a);
 }
 

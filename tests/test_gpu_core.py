@@ -198,19 +198,27 @@ def test_bvh_single_and_empty(ctx):
 
 # ---------------------------------------------------------------- first hit
 
-def _first_hit_parity(ctx, torch, oracle_lib, mesh, rays64, min_agree):
+def _first_hit_parity(ctx, torch, oracle_lib, mesh, rays64, min_agree, max_t=None):
+    """GPU first hits against the oracle's.  With max_t, rays whose oracle
+    path is longer (many periodic wraps, where the FP32 sum of segment
+    lengths drifts) are only checked for the GPU finding nothing earlier."""
     rays32 = rays64.astype(np.float32)
     sid = ctx.load_scene(mesh)
     tri_g, t_g = ctx.first_hit(sid, torch.from_numpy(rays32).cuda())
     tri_g = tri_g.cpu().numpy()
     t_g = t_g.cpu().numpy().astype(np.float64)
     tri_o, t_o, _ = oracle_lib.first_hit(mesh, rays32.astype(np.float64))
+    if max_t is not None:
+        far = t_o > max_t
+        assert (t_g[far] >= max_t * (1 - 1e-5)).all()
+        tri_g, t_g, tri_o, t_o = tri_g[~far], t_g[~far], tri_o[~far], t_o[~far]
     agree = tri_g == tri_o
     frac = agree.mean()
     assert frac >= min_agree, (frac, np.nonzero(~agree)[0][:10])
     # Distance tolerance: 1e-5 relative, floored by the FP32 coordinate
-    # quantum of the cell (16 half-ulps of its largest extent) for short hits.
-    L = max(h - l for l, h in zip(mesh.box_lo, mesh.box_hi))
+    # quantum of the cell (16 half-ulps of its largest coordinate magnitude,
+    # the precision of the re-entry points of periodic wraps) for short hits.
+    L = max(max(abs(l), abs(h)) for l, h in zip(mesh.box_lo, mesh.box_hi))
     tol = np.maximum(1e-5 * t_o, 16 * 2.0 ** -24 * L)
     err = np.abs(t_g - t_o)
     bad = agree & (err > tol)
@@ -239,6 +247,38 @@ def test_first_hit_soup_and_plane(ctx, torch, oracle_lib):
     d /= np.linalg.norm(d, axis=1, keepdims=True)
     _first_hit_parity(ctx, torch, oracle_lib, m, np.concatenate([o, d], 1), 0.9999)
     _first_hit_parity(ctx, torch, oracle_lib, fg.trench(), fg.top_rays(fg.trench(), 4000, seed=5), 0.9999)
+
+
+def _axis_rays(mesh, n, seed):
+    """Rays along the axes, rays with one zero direction component and rays
+    starting on the lower faces of the cell, origins off the grid lines."""
+    rng = np.random.default_rng(seed)
+    lo, hi = np.array(mesh.box_lo), np.array(mesh.box_hi)
+    o = lo + rng.uniform(0.01, 0.99, size=(3 * n, 3)) * (hi - lo)
+    d = np.zeros((3 * n, 3))
+    ax = rng.integers(0, 3, n)
+    d[np.arange(n), ax] = rng.choice([-1.0, 1.0], n)
+    planar = rng.normal(size=(n, 3))
+    planar[np.arange(n), rng.integers(0, 3, n)] = 0.0
+    d[n:2 * n] = planar / np.linalg.norm(planar, axis=1, keepdims=True)
+    face = rng.integers(0, 3, n)
+    o[2 * n + np.arange(n), face] = lo[face]
+    inward = rng.normal(size=(n, 3))
+    inward[np.arange(n), face] = np.abs(inward[np.arange(n), face]) + 0.1
+    d[2 * n:] = inward / np.linalg.norm(inward, axis=1, keepdims=True)
+    return np.concatenate([o, d], 1)
+
+
+@pytest.mark.parametrize("shift", [0.0, 1000.0, -500.0])
+def test_first_hit_axis_parallel_and_face_rays(ctx, torch, oracle_lib, tiny, shift):
+    """The node slab test stays conservative where one direction component is
+    zero (reciprocal clamped), where origins lie on cell faces, and in a cell
+    far from the coordinate origin (where the slab margin, which scales with
+    the largest coordinate, is widest relative to the cell)."""
+    m = fg.Mesh(tiny.verts + np.float32(shift), tiny.tris, tuple(v + shift for v in tiny.box_lo),
+                tuple(v + shift for v in tiny.box_hi), tiny.flags, {})
+    L = max(h - l for l, h in zip(m.box_lo, m.box_hi))
+    _first_hit_parity(ctx, torch, oracle_lib, m, _axis_rays(m, 3000, seed=21), 0.999, max_t=4 * L)
 
 
 @pytest.mark.slow
