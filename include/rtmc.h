@@ -141,8 +141,8 @@ typedef struct {
   int32_t lds_stack; /* traversal stack entries per lane held in LDS, 4..64 */
   int32_t chunk;     /* primaries per chunk; sizes the daughter queues */
   int32_t refill;    /* a wave fetches new rays once this many of its 64 lanes are idle, 1..64 */
-  int32_t occupancy; /* 8: traversal kernel built for 8 waves per SIMD (registers capped); otherwise
-                        the compiler's choice */
+  int32_t occupancy; /* traversal kernel build, waves per SIMD (registers capped to fit): 6 or 8;
+                        any other value: 7 for one scene, 6 for a batch (the default) */
 } rtmc_launch_cfg;
 
 typedef struct {

@@ -309,7 +309,7 @@ class Context:
         stream too, so the caching allocator's stream matches)."""
         self._chk(self.lib.rtmc_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
 
-    def set_launch(self, block: int, wg_per_cu: int, lds_stack: int, chunk: int, refill: int = 16, occupancy: int = 0):
+    def set_launch(self, block: int, wg_per_cu: int, lds_stack: int, chunk: int, refill: int = 48, occupancy: int = 0):
         self._chk(self.lib.rtmc_set_launch(self.h, C.byref(LaunchCfg(block, wg_per_cu, lds_stack, chunk, refill,
                                                                      occupancy))))
 

@@ -69,7 +69,7 @@ struct rtmc_ctx {
   std::vector<Scene> scenes;
   std::vector<Tables> tables;
   std::vector<Surrogate> srgs;
-  rtmc_launch_cfg cfg{256, 6, 16, 1 << 24, 48, 0};
+  rtmc_launch_cfg cfg{256, 7, 16, 1 << 24, 48, 0};
   // trace work buffers, grown on demand
   DevBuf queue[2];
   DevBuf hits;  // hit records, qcap entries
@@ -1129,13 +1129,13 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
     return st;
   }
   const int blocks[] = {64, 128, 256};
-  const int wgs[] = {2, 4, 6, 8, 12, 16};
+  const int wgs[] = {2, 4, 6, 7, 8, 12, 16};
   const int stacks[] = {8, 12, 16, 24, 32};
   const int refills[] = {24, 32, 40, 48, 56, 64};
-  const int occs[] = {0, 8};
+  const int occs[] = {0, 6, 8};
   for (int pass = 0; pass < 2; ++pass) {
     for (int knob = 0; knob < 5; ++knob) {
-      const int n = knob == 0 ? 3 : (knob == 1 ? 6 : (knob == 2 ? 5 : (knob == 3 ? 6 : 2)));
+      const int n = knob == 0 ? 3 : (knob == 1 ? 7 : (knob == 2 ? 5 : (knob == 3 ? 6 : 3)));
       for (int i = 0; i < n; ++i) {
         rtmc_launch_cfg cf = cur;
         if (knob == 0) {

@@ -770,11 +770,19 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
   }
 }
 
-// Register-limited variants: the default caps registers for 6 waves per SIMD
-// (80 VGPRs, no spills); O8 caps them for 8 waves per SIMD at the price of a
-// few spilled, rarely used values.  The autotuner picks by measurement.
+// Register-limited builds: k_traverse caps registers for 7 waves per SIMD
+// (72 VGPRs; no spills for one scene, a few for the batched form); O6 caps
+// them for 6 waves (80 VGPRs, no spills in either form) and O8 for 8 waves at
+// the price of more spilled, rarely used values.  One scene runs the 7-wave
+// build unless 6 or 8 waves are asked for; a batch runs the 6-wave build
+// unless 8 are (its 7-wave form spills).  The autotuner picks by measurement.
 template <bool MULTI>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_traverse(TraverseArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(7))) void k_traverse(TraverseArgs a) {
+  traverse_body<MULTI>(a);
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_traverse_o6(TraverseArgs a) {
   traverse_body<MULTI>(a);
 }
 
@@ -1260,16 +1268,21 @@ size_t shade_lds_bytes(const DevTables& tb, int n_hist, int block, int n_jobs) {
 
 hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int grid, int block, hipStream_t s) {
   const size_t lds = traverse_lds_bytes(a.lds_stack, block);
-  if (occupancy >= 8) {
+  // waves per SIMD of the build: 8 or 6 when asked, else 7 for one scene and
+  // 6 for a batch
+  const int w = occupancy >= 8 ? 8 : (occupancy == 6 || multi ? 6 : 7);
+  if (w == 8) {
     if (multi)
       k_traverse_o8<true><<<grid, block, lds, s>>>(a);
     else
       k_traverse_o8<false><<<grid, block, lds, s>>>(a);
-  } else {
+  } else if (w == 6) {
     if (multi)
-      k_traverse<true><<<grid, block, lds, s>>>(a);
+      k_traverse_o6<true><<<grid, block, lds, s>>>(a);
     else
-      k_traverse<false><<<grid, block, lds, s>>>(a);
+      k_traverse_o6<false><<<grid, block, lds, s>>>(a);
+  } else {
+    k_traverse<false><<<grid, block, lds, s>>>(a);
   }
   return hipGetLastError();
 }

@@ -481,13 +481,13 @@ def test_irregular_spectrum_table(ctx, oracle_lib):
     assert g["e_escaped"] == pytest.approx(o["e_escaped"], rel=1e-4)
 
 
-LAUNCHES = [(256, 6, 16, 1 << 24, 48, 0), (128, 12, 8, 5000, 24, 8), (64, 24, 24, 1 << 20, 64, 0),
-            (256, 2, 4, 3000, 1, 0)]
+LAUNCHES = [(256, 7, 16, 1 << 24, 48, 0), (128, 12, 8, 5000, 24, 8), (64, 24, 24, 1 << 20, 64, 0),
+            (256, 2, 4, 3000, 1, 0), (256, 6, 16, 1 << 24, 40, 6), (256, 8, 16, 1 << 24, 48, 7)]
 
 
 def test_launch_shapes_do_not_change_results(ctx, tiny, vaughan):
     """Block size, workgroups per CU, LDS stack depth, chunking, refill threshold
-    and the register-capped kernel change only speed: every tally, the
+    and the register-capped kernel builds change only speed: every tally, the
     traversal work counters included, is identical."""
     sid = ctx.load_scene(tiny)
     tid = ctx.load_tables(vaughan)
