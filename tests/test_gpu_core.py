@@ -341,6 +341,33 @@ def test_yield_parity_tiny_foam(ctx, torch, oracle_lib, tiny, vaughan):
     assert abs(diff.mean()) <= 3 * diff.std(ddof=1) / math.sqrt(n) + 1e-12
 
 
+@pytest.mark.slow
+@pytest.mark.parametrize("grid,porosity,seed,theta,n,max_gen,k", [
+    (128, 0.6, 1, 40.0, 10_000_000, 6, 256),   # one point of the 128^3 sweep (1.91M triangles)
+    (256, 0.8, 4, -80.0, 100_000_000, 10, 64),  # the 256^3 run (11.0M triangles), random incidence
+])
+def test_full_size_point_sampled_against_oracle(ctx, torch, oracle_lib, vaughan, grid, porosity, seed, theta, n,
+                                                max_gen, k):
+    """A point of the benchmark workloads at full size (every primary, the
+    default launch shape the benchmark times): the escape counts of the first
+    k primaries against the oracle, which traces them one by one over every
+    triangle, and the conservation laws over all n primaries."""
+    m = fg.make_grf_foam(grid, porosity, 2.0, seed=seed)
+    sid = ctx.load_scene(m)
+    tid = ctx.load_tables(vaughan)
+    pp = torch.zeros(n, dtype=torch.int32, device="cuda:0")
+    g = ctx.trace(sid, tid, 250.0, theta, n, seed=2000 + seed, max_gen=max_gen, per_primary=pp)
+    o = oracle_lib.trace(m, vaughan, 250.0, theta, k, seed=2000 + seed, max_gen=max_gen, per_primary=True)
+    ppg = pp[:k].cpu().numpy().astype(np.int64)
+    same = (ppg == o["per_primary"]["escaped"].astype(np.int64)).mean()
+    assert same >= 0.97, same
+    assert int(pp.sum().item()) == g["n_escaped"]
+    assert g["e_escaped"] + g["e_deposited"] == pytest.approx(250.0 * n, rel=1e-12)
+    assert g["n_rays"] == g["n_escaped"] + g["n_absorbed"] + g["n_truncated"] + g["n_lost"] == n + g["n_spawned"]
+    assert int(g["e_hist"].sum()) == g["n_escaped"] == int(g["a_hist"].sum())
+    assert g["n_lost"] == 0
+
+
 @pytest.mark.parametrize("E,theta", [(100.0, 0.0), (800.0, 40.0), (250.0, -80.0)])
 def test_yield_parity_points(ctx, oracle_lib, tiny, vaughan, E, theta):
     sid = ctx.load_scene(tiny)
