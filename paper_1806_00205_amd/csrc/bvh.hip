@@ -10,8 +10,9 @@
 //      codes being told apart by their indices;
 //   4. bounds, bottom up: each leaf climbs towards the root and the second
 //      child to arrive at a node merges both child boxes.
-// Child boxes are stored in the parent (64-byte node record) so a traversal
-// step reads one record and tests both children.
+// Child boxes are stored in the parent (64-byte node record); k_collapse4
+// then turns every binary node into the quantized 4-wide node traversal
+// reads (up to four children per 64-byte record).
 #include "rtmc_internal.h"
 
 namespace rtmc {

@@ -4,9 +4,13 @@
 //   triangles  float4 [3 * n_tris], Morton order after the BVH build: V0, V1,
 //              V2 of one triangle in 48 consecutive bytes; V0.w holds the
 //              caller's triangle index (int32 bits).
-//   BVH nodes  float4 [4 * n_nodes]: one 64-byte record per internal node
-//              (both child boxes and both child links), read with four
-//              16-byte loads from one cache line.
+//   BVH nodes  float4 [4 * n_nodes], binary: one 64-byte record per internal
+//              node (both child boxes and both child links); kept for the
+//              download and its structure tests.
+//   4-wide     float4 [4 * n_nodes], what traversal reads: one 64-byte record
+//              per binary node (union-box origin, three power-of-two scales,
+//              four child links, the child boxes quantized to bytes), read
+//              with four 16-byte loads from one cache line.
 //   ray queue  structure of arrays, ten 32-bit streams, written and read
 //              coalesced by whole waves.
 //   hit records structure of arrays, seven 32-bit streams, one entry per ray

@@ -3,22 +3,22 @@
 // A generation of rays (the paper's tree of branches, section 2.2, handled
 // breadth-first across all primaries) is processed by two launches:
 //   k_traverse: closest front-facing triangle by BVH traversal (section 2.1):
-//     robust slab tests against both child boxes of a 64-byte node record and
-//     the watertight ray/triangle test of Woop, Benthin and Wald (JCGT 2013)
-//     with back-face culling; periodic re-entry through the x / y faces,
-//     escape through z_max, substrate plane at z_min (section 2.2).  Lanes
-//     whose ray is done fetch new rays, so waves stay full.  Output: one
-//     28-byte hit record per ray.
+//     conservative slab tests against the four byte-quantized child boxes of
+//     a 64-byte node and the watertight ray/triangle test of Woop, Benthin and
+//     Wald (JCGT 2013) with back-face culling; periodic re-entry through the
+//     x / y faces, escape through z_max, substrate plane at z_min (section
+//     2.2).  Persistent waves whose lanes refill from the generation's queue
+//     once enough of them are done.  Output: one 28-byte hit record per ray.
 //   k_shade: the local incidence angle and the flat-surface tables give the
 //     daughter count (stochastic rounding, footnote of section 2.2), energies
 //     (inverse of the tabulated CDF truncated to the energy still available)
 //     and cosine-law directions; daughters are appended to the next queue with
-//     one atomic per wave; tallies go to per-wave LDS blocks.
-// Generation 0 rays are regenerated from primary ids in both launches rather
-// than stored.  Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed
-// by the job seed, counter (primary id, 0, path code, draw); draw 0 = birth
-// of a primary, 1 = daughter count, 2 + d = daughter d; a daughter's path
-// code is parent * 8 + d + 1.
+//     one atomic per workgroup step; tallies accumulate per lane and per job.
+// Generation 0 is written to the queue from primary ids by k_primaries, so
+// both launches read it like any other generation.  Random numbers:
+// Philox4x32-10 (Salmon et al., SC'11) keyed by the job seed, counter (primary
+// id, 0, path code, draw); draw 0 = birth of a primary, 1 = daughter count,
+// 2 + d = daughter d; a daughter's path code is parent * 8 + d + 1.
 #include "rtmc_internal.h"
 
 namespace rtmc {
@@ -825,8 +825,10 @@ __global__ void k_hit_ids(const float4* __restrict__ tris, const int32_t* __rest
 // Shading of one generation (section 2.2): for every ray, its hit record
 // decides escape, absorption or emission; emitting hits draw the daughter
 // count, energies and directions and append the daughters to the next queue
-// with one atomic per wave.  Tables sit in LDS; tallies in per-wave LDS
-// blocks tagged with the job they belong to.
+// with one atomic per workgroup step.  Tables sit in LDS; counters
+// accumulate in per-lane registers for the wave's current job (flushed when
+// it changes), histograms in per-wave LDS blocks, or everything in per-job
+// LDS blocks when the chunk holds few jobs.
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void k_shade(ShadeArgs a) {
   const int wpb = blockDim.x >> 6;
   const int w = threadIdx.x >> 6;
