@@ -19,6 +19,7 @@ import hashlib
 import json
 import math
 import os
+import re
 import sys
 import time
 
@@ -51,11 +52,21 @@ CONFIGS = {
 }
 
 
-def kernel_hash() -> str:
+def source_hash(texts) -> str:
+    """sha256 (first 16 hex digits) of C++ sources with comments and blank
+    space removed, so that edits to comments keep a counter summary current."""
     h = hashlib.sha256()
-    for f in ("trace.hip", "rtmc_internal.h"):
-        h.update(open(os.path.join(ROOT, "paper_1806_00205_amd", "csrc", f), "rb").read())
+    for t in texts:
+        t = re.sub(r"/\*.*?\*/", " ", t, flags=re.S)
+        t = re.sub(r"//[^\n]*", " ", t)
+        h.update(" ".join(t.split()).encode())
     return h.hexdigest()[:16]
+
+
+def kernel_hash() -> str:
+    """Hash of the traversal kernel's sources (trace.hip and rtmc_internal.h)."""
+    return source_hash(open(os.path.join(ROOT, "paper_1806_00205_amd", "csrc", f)).read()
+                       for f in ("trace.hip", "rtmc_internal.h"))
 
 
 def load_traffic(cfg_name: str):
