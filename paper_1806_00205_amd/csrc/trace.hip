@@ -536,13 +536,22 @@ __device__ inline bool trav_step(Trav& s, const LaneScene& L, LAS uint32_t* lstk
     cswap(d0, c0, d2, c2);
     cswap(d1, c1, d3, c3);
     cswap(d1, c1, d2, c2);
-    bool ok = true;
-    if (cnt >= 4) ok = ok && push(s, lstk, gstk, sd, gd, c3);
-    if (cnt >= 3) ok = ok && push(s, lstk, gstk, sd, gd, c2);
-    ok = ok && push(s, lstk, gstk, sd, gd, c1);
-    if (!ok) {
-      ovf = true;
-      return true;
+    if (s.sp + 3 <= sd) {
+      // common case: three free LDS entries, so write all three (entries above
+      // the new top are free) and move the top once; farthest lowest
+      lstk[s.sp * 64] = cnt >= 4 ? c3 : (cnt == 3 ? c2 : c1);
+      lstk[(s.sp + 1) * 64] = cnt >= 4 ? c2 : c1;
+      lstk[(s.sp + 2) * 64] = c1;
+      s.sp += cnt - 1;
+    } else {
+      bool ok = true;
+      if (cnt >= 4) ok = ok && push(s, lstk, gstk, sd, gd, c3);
+      if (cnt >= 3) ok = ok && push(s, lstk, gstk, sd, gd, c2);
+      ok = ok && push(s, lstk, gstk, sd, gd, c1);
+      if (!ok) {
+        ovf = true;
+        return true;
+      }
     }
     s.node = c0;
     return false;
