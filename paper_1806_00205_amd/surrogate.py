@@ -237,6 +237,13 @@ def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primar
     torch.cuda.synchronize()
     t_q = time.perf_counter() - t0
     inf = bench_inference(ctx, model.id)
+    # a foam-blind predictor for comparison: the mean training yield of the 32
+    # training points nearest in (ln E, cos theta), whatever their foam
+    Et, Ft = F_train[:, -2:], F_test[:, -2:]
+    d2 = ((Ft[:, None, :] - Et[None, :, :]) ** 2).sum(axis=2)
+    nn = np.argpartition(d2, 32, axis=1)[:, :32]
+    blind = y_train[nn].mean(axis=1)
+    blind_mae = float(np.abs(blind - y_test).mean())
     # RTMC cost of one yield at the surrogate's error: primaries for sigma = MAE
     sd_pp = float(np.median(s_test * math.sqrt(judge_primaries)))
     mae = float(err.mean())
@@ -248,6 +255,7 @@ def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primar
         "foam_grids": list(sizes),
         "n_test_foams": n_test, "test_points": len(test), "judge_primaries_per_yield": judge_primaries,
         "mae": mae, "p95_abs_err": float(np.quantile(err, 0.95)), "max_abs_err": float(err.max()),
+        "foam_blind_mae": blind_mae,
         "mae_in_support": float(err[ok].mean()) if ok.any() else None, "in_support_frac": float(ok.mean()),
         "judge_sigma_median": float(np.median(s_test)),
         "train_sigma_median": float(np.median([r[4] for r in train])),

@@ -137,3 +137,20 @@ def test_fused_prediction_agrees_with_training_forward(ctx):
     y = ctx.srg_predict(s, X).cpu().numpy()
     loss, _ = ctx.srg_gradient(s, X, y)
     assert loss <= 1e-8 * float(np.mean(y.astype(np.float64) ** 2)) + 1e-12, (loss, float(np.mean(y ** 2)))
+
+
+@pytest.mark.slow
+def test_surrogate_gains_over_rtmc_on_held_out_foams(ctx):
+    """End to end at small scale: RTMC traces yields on 96 training foams, the
+    network is trained on them with the GPU kernels, and on 16 held-out foams
+    it is (a) closer to RTMC than a foam-blind predictor (the mean training
+    yield at the nearest (E, theta) points), so it has learned the foam's
+    effect, and (b) far faster than RTMC itself at the same error."""
+    from paper_1806_00205_amd.surrogate import run_experiment
+    out, _ = run_experiment(ctx, n_train=96, points_per_foam=32, n_test=16, train_primaries=20000,
+                            judge_primaries=100000, steps=2000, seed=5, log=lambda *a: None, sizes=(24, 32, 40),
+                            workers=0, batch_foams=32)
+    print(f"held-out MAE {out['mae']:.4f}, foam-blind MAE {out['foam_blind_mae']:.4f}, gain {out['gain']:.3g}")
+    assert out["mae"] < 0.05, out["mae"]
+    assert out["mae"] < 0.7 * out["foam_blind_mae"], (out["mae"], out["foam_blind_mae"])
+    assert out["gain"] > 100, out["gain"]
