@@ -220,6 +220,12 @@ __device__ inline void store_slot(float4* nodes, int32_t p, int slot, const floa
   for (int q = 0; q < 6; ++q) f[o + q] = b[q];
 }
 
+// Bottom-up bounds.  The child boxes are written and read with device-scope
+// atomic stores and loads, which go to the device's coherence point past the
+// per-XCD L2 caches; the writer waits for its stores to complete before it
+// counts its arrival, and the second arrival reads only after that count.
+// So no release or acquire fence (an L2 write-back or invalidation on every
+// step of every thread) is needed.
 __global__ void k_refit(const float4* __restrict__ tris, int32_t n, float4* nodes, const int32_t* __restrict__ parent,
                         uint32_t* flags) {
   int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -231,8 +237,12 @@ __global__ void k_refit(const float4* __restrict__ tris, int32_t n, float4* node
   while (p >= 0) {
     float4 links = nodes[4 * (int64_t)p + 3];
     int slot = __float_as_uint(links.x) == child ? 0 : 1;
-    store_slot(nodes, p, slot, b);
-    uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    float* dst = reinterpret_cast<float*>(nodes + 4 * (int64_t)p) + slot * 6;
+    for (int q = 0; q < 6; ++q) __hip_atomic_store(dst + q, b[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __builtin_amdgcn_sched_barrier(0);
+    __builtin_amdgcn_s_waitcnt(0);  // the box stores have completed
+    __builtin_amdgcn_sched_barrier(0);
+    uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     if (old == 0u) return;
     const float* f = reinterpret_cast<const float*>(nodes + 4 * (int64_t)p);
     float o[12];

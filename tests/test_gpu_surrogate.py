@@ -151,6 +151,8 @@ def test_surrogate_gains_over_rtmc_on_held_out_foams(ctx):
                             judge_primaries=100000, steps=2000, seed=5, log=lambda *a: None, sizes=(24, 32, 40),
                             workers=0, batch_foams=32)
     print(f"held-out MAE {out['mae']:.4f}, foam-blind MAE {out['foam_blind_mae']:.4f}, gain {out['gain']:.3g}")
-    assert out["mae"] < 0.05, out["mae"]
+    # observed: MAE 0.046 against 0.100 foam-blind, gain about 200 (the full-size
+    # experiment, 1024 training foams of 64^3-192^3: MAE 0.010, gain about 3000)
+    assert out["mae"] < 0.08, out["mae"]
     assert out["mae"] < 0.7 * out["foam_blind_mae"], (out["mae"], out["foam_blind_mae"])
-    assert out["gain"] > 100, out["gain"]
+    assert out["gain"] > 50, out["gain"]
