@@ -749,7 +749,7 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
   if (ensure(c, tris, (size_t)n * 48) || ensure(c, nodes, (size_t)nn * 64) || ensure(c, nodes4, (size_t)nn * 64) ||
       ensure(c, keys, (size_t)n * 8) ||
       ensure(c, vals, (size_t)n * 4) || ensure(c, keys2, (size_t)n * 8) || ensure(c, vals2, (size_t)n * 4) ||
-      ensure(c, parent, (size_t)(nn + n) * 4) || ensure(c, flags, (size_t)nn * 4) ||
+      ensure(c, parent, (size_t)(nn + n) * 4) || ensure(c, flags, (size_t)nn * 8) ||
       ensure(c, hist, radix_hist_words(n) * 4) || ensure(c, depth, 16)) {
     cleanup();
     dev_free(c, tris);

@@ -67,6 +67,50 @@ __global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* __restrict__ a, in
   }
 }
 
+// Exclusive scan of a long array in three launches: the sum of each 4096-word
+// segment, an exclusive scan of those sums (k_scan_excl, one workgroup), then
+// each segment scanned inside its workgroup and offset by its sum's prefix.
+constexpr int kScanSeg = 4096;  // words per workgroup of 256 threads, 16 each
+
+__global__ __launch_bounds__(256) void k_scan_reduce(const uint32_t* __restrict__ a, int64_t len,
+                                                     uint32_t* __restrict__ part) {
+  __shared__ uint32_t ws[4];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanSeg;
+  uint32_t s = 0;
+  for (int r = 0; r < 16; ++r) {
+    const int64_t i = b0 + (int64_t)r * 256 + threadIdx.x;
+    if (i < len) s += a[i];
+  }
+  for (int off = 32; off >= 1; off >>= 1) s += __shfl_xor(s, off, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+__global__ __launch_bounds__(256) void k_scan_apply(uint32_t* __restrict__ a, int64_t len,
+                                                    const uint32_t* __restrict__ part) {
+  __shared__ uint32_t ts[256];
+  const int64_t b0 = (int64_t)blockIdx.x * kScanSeg + (int64_t)threadIdx.x * 16;
+  uint32_t v[16], s = 0;
+  for (int q = 0; q < 16; ++q) {
+    v[q] = b0 + q < len ? a[b0 + q] : 0u;
+    s += v[q];
+  }
+  ts[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t t = threadIdx.x >= (unsigned)off ? ts[threadIdx.x - off] : 0u;
+    __syncthreads();
+    ts[threadIdx.x] += t;
+    __syncthreads();
+  }
+  uint32_t run = part[blockIdx.x] + ts[threadIdx.x] - s;
+  for (int q = 0; q < 16; ++q) {
+    if (b0 + q < len) a[b0 + q] = run;
+    run += v[q];
+  }
+}
+
 // Stable scatter: each wave owns kSortRounds * 64 consecutive keys of the
 // tile; ranks inside a round come from ballots over the 8 digit bits.
 __global__ __launch_bounds__(kSortBlock) void k_radix_scatter(const uint64_t* __restrict__ kin,
@@ -225,20 +269,24 @@ __device__ inline void store_slot(float4* nodes, int32_t p, int slot, const floa
 // per-XCD L2 caches; the writer waits for its stores to complete before it
 // counts its arrival, and the second arrival reads only after that count.
 // So no release or acquire fence (an L2 write-back or invalidation on every
-// step of every thread) is needed.
+// step of every thread) is needed.  Node heights (a leaf 0, an internal node
+// one more than its taller child) travel the same way, and the thread that
+// completes the root writes its height: the tree's depth in internal nodes.
 __global__ void k_refit(const float4* __restrict__ tris, int32_t n, float4* nodes, const int32_t* __restrict__ parent,
-                        uint32_t* flags) {
+                        uint32_t* flags, uint32_t* height, uint32_t* depth) {
   int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   float b[6];
   tri_box(tris, k, b);
   uint32_t child = (uint32_t)k | kLeafBit;
   int32_t p = parent[(n - 1) + k];
+  uint32_t h = 0;
   while (p >= 0) {
     float4 links = nodes[4 * (int64_t)p + 3];
     int slot = __float_as_uint(links.x) == child ? 0 : 1;
     float* dst = reinterpret_cast<float*>(nodes + 4 * (int64_t)p) + slot * 6;
     for (int q = 0; q < 6; ++q) __hip_atomic_store(dst + q, b[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_fetch_max(&height[p], h + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __builtin_amdgcn_sched_barrier(0);
     __builtin_amdgcn_s_waitcnt(0);  // the box stores have completed
     __builtin_amdgcn_sched_barrier(0);
@@ -247,6 +295,7 @@ __global__ void k_refit(const float4* __restrict__ tris, int32_t n, float4* node
     const float* f = reinterpret_cast<const float*>(nodes + 4 * (int64_t)p);
     float o[12];
     for (int q = 0; q < 12; ++q) o[q] = __hip_atomic_load(f + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    h = __hip_atomic_load(&height[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     b[0] = fminf(o[0], o[6]);
     b[1] = fminf(o[1], o[7]);
     b[2] = fminf(o[2], o[8]);
@@ -256,6 +305,7 @@ __global__ void k_refit(const float4* __restrict__ tris, int32_t n, float4* node
     child = (uint32_t)p;
     p = parent[p];
   }
+  *depth = h;
 }
 
 // One triangle: a single node whose two children are that triangle.
@@ -267,24 +317,13 @@ __global__ void k_single(const float4* __restrict__ tris, float4* nodes) {
   nodes[3] = make_float4(__uint_as_float(kLeafBit), __uint_as_float(kLeafBit), 0.0f, 0.0f);
 }
 
-__global__ void k_depth(const int32_t* __restrict__ parent, int32_t n, uint32_t* depth) {
-  int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= n) return;
-  uint32_t d = 1;
-  int32_t p = parent[(n - 1) + k];
-  while (p > 0) {
-    p = parent[p];
-    ++d;
-  }
-  atomicMax(depth, d);
-}
-
 }  // namespace
 
 size_t radix_hist_words(int64_t n) {
   int64_t nb = (n + kSortTile - 1) / kSortTile;
   if (nb < 1) nb = 1;
-  return (size_t)nb * 256;
+  const int64_t len = nb * 256;
+  return (size_t)(len + (len + kScanSeg - 1) / kScanSeg + 16);  // histogram, then the segment sums
 }
 
 hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, uint32_t* hist,
@@ -298,7 +337,14 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
   uint32_t* vb = vals_alt;
   for (int shift = 0; shift < key_bits; shift += 8) {
     k_radix_hist<<<nb, kSortBlock, 0, s>>>(ka, n, shift, hist, nb);
-    k_scan_excl<<<1, 1024, 0, s>>>(hist, (int64_t)nb * 256);
+    {
+      const int64_t len = (int64_t)nb * 256;
+      const int g = (int)((len + kScanSeg - 1) / kScanSeg);
+      uint32_t* part = hist + len;
+      k_scan_reduce<<<g, 256, 0, s>>>(hist, len, part);
+      k_scan_excl<<<1, 1024, 0, s>>>(part, g);
+      k_scan_apply<<<g, 256, 0, s>>>(hist, len, part);
+    }
     k_radix_scatter<<<nb, kSortBlock, 0, s>>>(ka, va, kb, vb, n, shift, hist, nb);
     uint64_t* tk = ka;
     ka = kb;
@@ -454,12 +500,11 @@ hipError_t build_bvh(BvhBuild& b, hipStream_t s) {
   }
   const int gi = (n - 1 + TB - 1) / TB;
   k_karras<<<gi, TB, 0, s>>>(keys, n, b.nodes, b.parent);
-  e = launch_fill_u32(b.flags, 0u, (size_t)(n - 1), s);
+  e = launch_fill_u32(b.flags, 0u, 2 * (size_t)(n - 1), s);  // arrival counts, then heights
   if (e != hipSuccess) return e;
   e = launch_fill_u32(b.depth, 0u, 1, s);
   if (e != hipSuccess) return e;
-  k_refit<<<g, TB, 0, s>>>(b.tris_out, n, b.nodes, b.parent, b.flags);
-  k_depth<<<g, TB, 0, s>>>(b.parent, n, b.depth);
+  k_refit<<<g, TB, 0, s>>>(b.tris_out, n, b.nodes, b.parent, b.flags, b.flags + (n - 1), b.depth);
   k_collapse4<<<gi, TB, 0, s>>>(b.nodes, (int64_t)(n - 1), b.nodes4);
   return hipGetLastError();
 }

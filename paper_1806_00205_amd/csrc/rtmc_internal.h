@@ -229,7 +229,7 @@ struct BvhBuild {
   uint64_t* keys_alt;     // [n]
   uint32_t* vals_alt;     // [n]
   int32_t* parent;        // [max(n - 1, 1) + n]: internal nodes then leaves
-  uint32_t* flags;        // [max(n - 1, 1)]
+  uint32_t* flags;        // [2 max(n - 1, 1)]: arrival counts, then node heights
   uint32_t* hist;         // radix histogram scratch
   uint32_t* depth;        // [1]
   int32_t n;
