@@ -76,6 +76,10 @@ struct rtmc_ctx {
   uint32_t qcap = 0;
   DevBuf gstack;
   DevBuf counters, ppc, err_word, jobs, tally;
+  // pinned host copy of the error word and the tallies: read back with
+  // asynchronous copies queued behind the kernels, one synchronization per trace
+  void* pin = nullptr;
+  size_t pin_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> kev;  // per-launch timing events (eager traces)
   // last instantiated batch graph and the signature it was captured for
@@ -133,6 +137,24 @@ rtmc_status check_scene(rtmc_ctx* c, int32_t id, bool need_bvh) {
   if (id < 0 || id >= (int32_t)c->scenes.size()) return fail(c, RTMC_EINVAL, "unknown scene id %d", id);
   if (need_bvh && !c->scenes[id].built) return fail(c, RTMC_ESTATE, "scene %d has no BVH: call rtmc_build_bvh", id);
   return RTMC_OK;
+}
+
+// Queue the copies of the error word and n_words tally words into the pinned
+// host buffer (grown when needed; no copy is in flight when this is called).
+hipError_t queue_readback(rtmc_ctx* c, size_t n_words, hipStream_t s) {
+  const size_t need = 16 + n_words * 8;
+  if (c->pin_bytes < need) {
+    if (c->pin) (void)hipHostFree(c->pin);
+    c->pin = nullptr;
+    c->pin_bytes = 0;
+    hipError_t e = hipHostMalloc(&c->pin, need, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    c->pin_bytes = need;
+  }
+  hipError_t e = hipMemcpyAsync(c->pin, c->err_word.p, 4, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess && n_words)
+    e = hipMemcpyAsync(static_cast<char*>(c->pin) + 16, c->tally.p, n_words * 8, hipMemcpyDeviceToHost, s);
+  return e;
 }
 
 DevScene dev_scene(const Scene& s) {
@@ -349,15 +371,15 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
       sa.count_in = cnt + g;
       sa.count_out = cnt + g + 1;
       if (timed) {
-        const size_t k = 4 * (size_t)(*n_launch);
-        hipEvent_t e0 = ev(k), e1 = ev(k + 1), e2 = ev(k + 2), e3 = ev(k + 3);
-        if (!e0 || !e1 || !e2 || !e3) return fail(c, RTMC_EDEVICE, "event creation failed");
+        // three events per generation: before traversal, between the launches, after shading
+        const size_t k = 3 * (size_t)(*n_launch);
+        hipEvent_t e0 = ev(k), e1 = ev(k + 1), e2 = ev(k + 2);
+        if (!e0 || !e1 || !e2) return fail(c, RTMC_EDEVICE, "event creation failed");
         HIPCHK(c, hipEventRecord(e0, s));
         HIPCHK(c, launch_traverse(ta, multi, cfg.occupancy, grid, block, s));
         HIPCHK(c, hipEventRecord(e1, s));
-        HIPCHK(c, hipEventRecord(e2, s));
         HIPCHK(c, launch_shade(sa, c->n_cu, kShadeBlock, s));
-        HIPCHK(c, hipEventRecord(e3, s));
+        HIPCHK(c, hipEventRecord(e2, s));
       } else {
         HIPCHK(c, launch_traverse(ta, multi, cfg.occupancy, grid, block, s));
         HIPCHK(c, launch_shade(sa, c->n_cu, kShadeBlock, s));
@@ -489,6 +511,7 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
       HIPCHK(c, hipEventRecord(c->ev0, s));
       hipError_t le = hipGraphLaunch(c->gexec, s);
       HIPCHK(c, hipEventRecord(c->ev1, s));
+      HIPCHK(c, queue_readback(c, tw * jobs.size(), s));
       hipError_t se = hipStreamSynchronize(s);
       HIPCHK(c, le);
       HIPCHK(c, se);
@@ -499,13 +522,14 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
                          &nl);
       if (st) return st;
       HIPCHK(c, hipEventRecord(c->ev1, s));
+      HIPCHK(c, queue_readback(c, tw * jobs.size(), s));
       HIPCHK(c, hipStreamSynchronize(s));
       double kms = 0.0, sms = 0.0;
       for (uint64_t i = 0; i < nl; ++i) {
         float e = 0.f;
-        HIPCHK(c, hipEventElapsedTime(&e, c->kev[4 * i], c->kev[4 * i + 1]));
+        HIPCHK(c, hipEventElapsedTime(&e, c->kev[3 * i], c->kev[3 * i + 1]));
         kms += e;
-        HIPCHK(c, hipEventElapsedTime(&e, c->kev[4 * i + 2], c->kev[4 * i + 3]));
+        HIPCHK(c, hipEventElapsedTime(&e, c->kev[3 * i + 1], c->kev[3 * i + 2]));
         sms += e;
       }
       out.kernel_ms = kms;
@@ -515,7 +539,7 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
     float ms = 0.f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev0, c->ev1));
     uint32_t errw = 0;
-    HIPCHK(c, hipMemcpy(&errw, c->err_word.p, 4, hipMemcpyDeviceToHost));
+    std::memcpy(&errw, c->pin, 4);
     if (errw & 2u) return fail(c, RTMC_EOVERFLOW, "traversal stack overflow (BVH deeper than the stack)");
     if (errw & 1u) {
       if (cfg.chunk <= 1)
@@ -524,7 +548,7 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
       continue;
     }
     out.tally.resize(tw * jobs.size());
-    HIPCHK(c, hipMemcpy(out.tally.data(), c->tally.p, out.tally.size() * 8, hipMemcpyDeviceToHost));
+    std::memcpy(out.tally.data(), static_cast<const char*>(c->pin) + 16, out.tally.size() * 8);
     out.ms = ms;
     out.n_chunks = (int)plan_chunks(jobs, (uint32_t)cfg.chunk).size();
     (void)attempt;
@@ -631,6 +655,7 @@ void rtmc_destroy(rtmc_ctx* c) {
   dev_free(c, c->err_word);
   dev_free(c, c->jobs);
   dev_free(c, c->tally);
+  if (c->pin) (void)hipHostFree(c->pin);
   if (c->ev0) (void)hipEventDestroy(c->ev0);
   if (c->ev1) (void)hipEventDestroy(c->ev1);
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
