@@ -31,10 +31,13 @@ Q_READ_BYTES = 24  # traversal reads origin + direction of a queued ray (6 x 32-
 HIT_BYTES = 28  # one hit record: 7 x 32-bit streams
 NODE_BYTES = 64
 # LBVH build per triangle: Morton codes (48 read + 12 written), 8 radix passes
-# (8 + 24 bytes each), triangle gather (4 + 48 + 48), hierarchy (24 key reads
-# + 16 link writes), bottom-up bounds (48 triangle read + 64 node write + 12)
-BUILD_BYTES_PER_TRI = 60 + 8 * 32 + 100 + 40 + 124
-TRI_BYTES = 48
+# (8 + 24 bytes each), triangle gather (4 + 48 read, 48 sorted + 64 rotated
+# written), hierarchy (24 key reads + 16 link writes), bottom-up bounds (48
+# triangle read + 64 node write + 12)
+BUILD_BYTES_PER_TRI = 60 + 8 * 32 + 164 + 40 + 124
+# one triangle test reads the three vertices in the ray's axis order (3 x 12 B)
+# and the caller's index (4 B) from the triangle's rotated 64-byte record
+TRI_BYTES = 40
 
 CONFIGS = {
     "c1": dict(n=128, porosity=0.6, ell=2.0, seed=1, energies=[50.0, 100.0, 250.0, 500.0, 1000.0],

@@ -30,6 +30,7 @@ struct Scene {
   uint32_t flags = 0;
   DevBuf tris_in;  // compacted, caller order (freed after the build)
   DevBuf tris;     // Morton order
+  DevBuf tris_t;   // the same as rotated 64-byte records, what traversal reads
   DevBuf nodes;    // binary LBVH (64 B per node)
   DevBuf nodes4;   // quantized 4-wide nodes collapsed from it (64 B per node), what traversal reads
   int64_t n_nodes = 0;
@@ -161,6 +162,7 @@ DevScene dev_scene(const Scene& s) {
   DevScene d;
   d.nodes = reinterpret_cast<const float4*>(s.nodes4.p);
   d.tris = reinterpret_cast<const float4*>(s.tris.p);
+  d.tris_t = reinterpret_cast<const float4*>(s.tris_t.p);
   double w = 0.0;
   for (int a = 0; a < 3; ++a) {
     d.lo[a] = (float)s.lo[a];
@@ -634,6 +636,7 @@ void rtmc_destroy(rtmc_ctx* c) {
   for (auto& s : c->scenes) {
     dev_free(c, s.tris_in);
     dev_free(c, s.tris);
+    dev_free(c, s.tris_t);
     dev_free(c, s.nodes);
     dev_free(c, s.nodes4);
   }
@@ -760,7 +763,7 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
     return RTMC_OK;
   }
   const int64_t nn = std::max<int64_t>(n - 1, 1);
-  DevBuf tris, nodes, nodes4, keys, vals, keys2, vals2, parent, flags, hist, depth;
+  DevBuf tris, tris_t, nodes, nodes4, keys, vals, keys2, vals2, parent, flags, hist, depth;
   auto cleanup = [&]() {
     dev_free(c, keys);
     dev_free(c, vals);
@@ -771,13 +774,14 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
     dev_free(c, hist);
     dev_free(c, depth);
   };
-  if (ensure(c, tris, (size_t)n * 48) || ensure(c, nodes, (size_t)nn * 64) || ensure(c, nodes4, (size_t)nn * 64) ||
+  if (ensure(c, tris, (size_t)n * 48) || ensure(c, tris_t, (size_t)n * 64) || ensure(c, nodes, (size_t)nn * 64) || ensure(c, nodes4, (size_t)nn * 64) ||
       ensure(c, keys, (size_t)n * 8) ||
       ensure(c, vals, (size_t)n * 4) || ensure(c, keys2, (size_t)n * 8) || ensure(c, vals2, (size_t)n * 4) ||
       ensure(c, parent, (size_t)(nn + n) * 4) || ensure(c, flags, (size_t)nn * 8) ||
       ensure(c, hist, radix_hist_words(n) * 4) || ensure(c, depth, 16)) {
     cleanup();
     dev_free(c, tris);
+    dev_free(c, tris_t);
     dev_free(c, nodes);
     dev_free(c, nodes4);
     return RTMC_ENOMEM;
@@ -785,6 +789,7 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
   BvhBuild b;
   b.tris_in = reinterpret_cast<const float4*>(s.tris_in.p);
   b.tris_out = reinterpret_cast<float4*>(tris.p);
+  b.tris_rot = reinterpret_cast<float4*>(tris_t.p);
   b.nodes = reinterpret_cast<float4*>(nodes.p);
   b.nodes4 = reinterpret_cast<float4*>(nodes4.p);
   b.keys = reinterpret_cast<uint64_t*>(keys.p);
@@ -811,12 +816,14 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
   cleanup();
   if (e != hipSuccess) {
     dev_free(c, tris);
+    dev_free(c, tris_t);
     dev_free(c, nodes);
     dev_free(c, nodes4);
     return fail(c, RTMC_EDEVICE, "BVH build: %s", hipGetErrorString(e));
   }
   dev_free(c, s.tris_in);
   s.tris = tris;
+  s.tris_t = tris_t;
   s.nodes = nodes;
   s.nodes4 = nodes4;
   s.n_nodes = nn;

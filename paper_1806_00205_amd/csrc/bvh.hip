@@ -191,13 +191,19 @@ __global__ void k_morton(const float4* __restrict__ tris, int32_t n, float lox, 
 }
 
 __global__ void k_gather_tris(const float4* __restrict__ in, const uint32_t* __restrict__ perm, int32_t n,
-                              float4* __restrict__ out) {
+                              float4* __restrict__ out, float4* __restrict__ rot) {
   int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   int64_t s = 3 * (int64_t)perm[i];
-  out[3 * (int64_t)i] = in[s];
-  out[3 * (int64_t)i + 1] = in[s + 1];
-  out[3 * (int64_t)i + 2] = in[s + 2];
+  const float4 a = in[s], b = in[s + 1], c = in[s + 2];
+  out[3 * (int64_t)i] = a;
+  out[3 * (int64_t)i + 1] = b;
+  out[3 * (int64_t)i + 2] = c;
+  // the traversal record: x y z x y of each vertex, then a.w (caller's index)
+  rot[4 * (int64_t)i] = make_float4(a.x, a.y, a.z, a.x);
+  rot[4 * (int64_t)i + 1] = make_float4(a.y, b.x, b.y, b.z);
+  rot[4 * (int64_t)i + 2] = make_float4(b.x, b.y, c.x, c.y);
+  rot[4 * (int64_t)i + 3] = make_float4(c.z, c.x, c.y, a.w);
 }
 
 // ---------------------------------------------------------------- Karras
@@ -492,7 +498,7 @@ hipError_t build_bvh(BvhBuild& b, hipStream_t s) {
   if (e != hipSuccess) return e;
   uint64_t* keys = alt ? b.keys_alt : b.keys;
   uint32_t* perm = alt ? b.vals_alt : b.vals;
-  k_gather_tris<<<g, TB, 0, s>>>(b.tris_in, perm, n, b.tris_out);
+  k_gather_tris<<<g, TB, 0, s>>>(b.tris_in, perm, n, b.tris_out, b.tris_rot);
   if (n == 1) {
     k_single<<<1, 1, 0, s>>>(b.tris_out, b.nodes);
     k_collapse4<<<1, 64, 0, s>>>(b.nodes, 1, b.nodes4);

@@ -4,6 +4,10 @@
 //   triangles  float4 [3 * n_tris], Morton order after the BVH build: V0, V1,
 //              V2 of one triangle in 48 consecutive bytes; V0.w holds the
 //              caller's triangle index (int32 bits).
+//   rotated    float4 [4 * n_tris], what traversal reads: one 64-byte record
+//   triangles  per sorted triangle, each vertex as five floats (x, y, z, x, y)
+//              so that every cyclic order of its coordinates is three
+//              consecutive floats, then the caller's triangle index.
 //   BVH nodes  float4 [4 * n_nodes], binary: one 64-byte record per internal
 //              node (both child boxes and both child links); kept for the
 //              download and its structure tests.
@@ -63,7 +67,8 @@ constexpr double kFixScale = 1048576.0;  // 2^20
 
 struct DevScene {
   const float4* nodes;  // quantized 4-wide nodes, 4 float4 each
-  const float4* tris;
+  const float4* tris;    // sorted triangles, 48 B each
+  const float4* tris_t;  // the same as rotated records, 64 B each (traversal)
   float lo[3], hi[3];
   float wext;  // bound on the magnitude of every coordinate of the scene and its node planes
   int32_t n_tris;
@@ -222,6 +227,7 @@ hipError_t mlp_infer(const MlpInfer& p, hipStream_t s);
 struct BvhBuild {
   const float4* tris_in;  // [3 n] unsorted, compacted
   float4* tris_out;       // [3 n] sorted
+  float4* tris_rot;       // [4 n] sorted, rotated records
   float4* nodes;          // [4 max(n - 1, 1)] binary nodes
   float4* nodes4;         // [4 max(n - 1, 1)] quantized 4-wide nodes (traversal)
   uint64_t* keys;         // [n]

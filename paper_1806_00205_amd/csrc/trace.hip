@@ -81,12 +81,16 @@ __device__ inline float u01(uint32_t u) { return (float)((u >> 8) + 1u) * 5.9604
 
 // ---------------------------------------------------------------- geometry
 
+// Per-lane ray state kept in registers while a segment is traversed (the
+// direction itself is read only when a segment begins or ends, and waits in
+// LDS meanwhile).
 struct RayP {
-  float ox, oy, oz, dx, dy, dz;
+  float ox, oy, oz;
   float ix, iy, iz;
   float w;  // slab margin of the current segment per unit of |1/d|
   float Sx, Sy, Sz;
-  uint32_t kk;  // shear axes: kx | ky << 2 | kz << 4
+  float qx, qy, qz;  // origin with its coordinates in the order kx, ky, kz
+  uint32_t kk;       // 4 kx (byte offset of a rotated vertex) | bit 31 when kx and ky are swapped
 };
 
 __device__ inline float pick(float x, float y, float z, int k) { return k == 0 ? x : (k == 1 ? y : z); }
@@ -98,27 +102,35 @@ __device__ inline float safe_inv(float d) {
 }
 
 __device__ inline void ray_setup(RayP& r, float dx, float dy, float dz) {
-  r.dx = dx;
-  r.dy = dy;
-  r.dz = dz;
   r.ix = safe_inv(dx);
   r.iy = safe_inv(dy);
   r.iz = safe_inv(dz);
   const float ax = fabsf(dx), ay = fabsf(dy), az = fabsf(dz);
-  int kz = ax > ay ? (ax > az ? 0 : 2) : (ay > az ? 1 : 2);
-  int kx = kz == 2 ? 0 : kz + 1;
-  int ky = kx == 2 ? 0 : kx + 1;
-  const float dkz = pick(dx, dy, dz, kz);
-  if (dkz < 0.0f) {
-    int t = kx;
-    kx = ky;
-    ky = t;
-  }
-  r.kk = (uint32_t)kx | ((uint32_t)ky << 2) | ((uint32_t)kz << 4);
+  // kz: the dominant axis; (kx, ky, kz) in cyclic order.  Written as selects
+  // on the comparisons (an index into the three values would go to scratch).
+  const bool z0 = ax > ay && ax > az, z1 = !z0 && ay > az;
+  const float dkz = z0 ? dx : (z1 ? dy : dz);
+  const float dkx = z0 ? dy : (z1 ? dz : dx);
+  const float dky = z0 ? dz : (z1 ? dx : dy);
+  // The watertight test keeps the sheared frame right-handed by swapping kx
+  // and ky when d[kz] < 0.  The swap maps the edge functions U, V, W to
+  // exactly -U, -V, -W (the same rounded products, subtracted the other way
+  // round) and leaves T / det and the weights unchanged, so the test below
+  // always uses the cyclic order and negates instead: the cyclic order is
+  // what a rotated vertex record holds (kx = 1, 2, 0 for kz = 0, 1, 2).
+  r.kk = (z0 ? 4u : (z1 ? 8u : 0u)) | (dkz < 0.0f ? 0x80000000u : 0u);
   // any per-ray shear is watertight as long as every triangle sees the same one
   r.Sz = __builtin_amdgcn_rcpf(dkz);
-  r.Sx = pick(dx, dy, dz, kx) * r.Sz;
-  r.Sy = pick(dx, dy, dz, ky) * r.Sz;
+  r.Sx = dkx * r.Sz;
+  r.Sy = dky * r.Sz;
+}
+
+// Origin in the shear's axis order (after every change of the origin).
+__device__ inline void rotate_origin(RayP& r) {
+  const bool x1 = (r.kk & 0xFu) == 4u, x2 = (r.kk & 0xFu) == 8u;
+  r.qx = x1 ? r.oy : (x2 ? r.oz : r.ox);
+  r.qy = x1 ? r.oz : (x2 ? r.ox : r.oy);
+  r.qz = x1 ? r.ox : (x2 ? r.oy : r.oz);
 }
 
 // Margins of the fused slab distances of one segment.  A node's child plane
@@ -147,20 +159,20 @@ __device__ inline bool box_hit(float nx, float ny, float nz, float fx, float fy,
   return t0 <= fminf(t1, tmax);
 }
 
-// Watertight ray/triangle test with back-face culling.  U, V, W are the
-// sheared edge functions (weights of V0, V1, V2); products are kept
-// unfused so that an edge shared by two triangles gets exactly opposite
+// Watertight ray/triangle test with back-face culling.  a, b, c are the
+// vertices with their coordinates already in the order kx, ky, kz (read from
+// the rotated records); U, V, W are the sheared edge functions (weights of
+// V0, V1, V2), negated when the ray's frame swaps kx and ky.  Products are
+// kept unfused so that an edge shared by two triangles gets exactly opposite
 // values, and an exactly zero edge function is recomputed in FP64.
-__device__ inline bool tri_test(const RayP& r, f4v a, f4v b, f4v c, float tbest, float& t, float& b1,
+__device__ inline bool tri_test(const RayP& r, float3 a, float3 b, float3 c, float tbest, float& t, float& b1,
                                 float& b2) {
-  const float ax = a.x - r.ox, ay = a.y - r.oy, az = a.z - r.oz;
-  const float bx = b.x - r.ox, by = b.y - r.oy, bz = b.z - r.oz;
-  const float cx = c.x - r.ox, cy = c.y - r.oy, cz = c.z - r.oz;
-  const int kx = (int)(r.kk & 3u), ky = (int)((r.kk >> 2) & 3u), kz = (int)(r.kk >> 4);
-  const float Akz = pick(ax, ay, az, kz), Bkz = pick(bx, by, bz, kz), Ckz = pick(cx, cy, cz, kz);
-  const float Ax = fmaf(-r.Sx, Akz, pick(ax, ay, az, kx)), Ay = fmaf(-r.Sy, Akz, pick(ax, ay, az, ky));
-  const float Bx = fmaf(-r.Sx, Bkz, pick(bx, by, bz, kx)), By = fmaf(-r.Sy, Bkz, pick(bx, by, bz, ky));
-  const float Cx = fmaf(-r.Sx, Ckz, pick(cx, cy, cz, kx)), Cy = fmaf(-r.Sy, Ckz, pick(cx, cy, cz, ky));
+  const float ax = a.x - r.qx, ay = a.y - r.qy, Akz = a.z - r.qz;
+  const float bx = b.x - r.qx, by = b.y - r.qy, Bkz = b.z - r.qz;
+  const float cx = c.x - r.qx, cy = c.y - r.qy, Ckz = c.z - r.qz;
+  const float Ax = fmaf(-r.Sx, Akz, ax), Ay = fmaf(-r.Sy, Akz, ay);
+  const float Bx = fmaf(-r.Sx, Bkz, bx), By = fmaf(-r.Sy, Bkz, by);
+  const float Cx = fmaf(-r.Sx, Ckz, cx), Cy = fmaf(-r.Sy, Ckz, cy);
   float U = __fsub_rn(__fmul_rn(Cx, By), __fmul_rn(Cy, Bx));
   float V = __fsub_rn(__fmul_rn(Ax, Cy), __fmul_rn(Ay, Cx));
   float W = __fsub_rn(__fmul_rn(Bx, Ay), __fmul_rn(By, Ax));
@@ -169,6 +181,10 @@ __device__ inline bool tri_test(const RayP& r, f4v a, f4v b, f4v c, float tbest,
     V = (float)((double)Ax * (double)Cy - (double)Ay * (double)Cx);
     W = (float)((double)Bx * (double)Ay - (double)By * (double)Ax);
   }
+  const uint32_t sg = r.kk & 0x80000000u;
+  U = __uint_as_float(__float_as_uint(U) ^ sg);
+  V = __uint_as_float(__float_as_uint(V) ^ sg);
+  W = __uint_as_float(__float_as_uint(W) ^ sg);
   if (U < 0.0f || V < 0.0f || W < 0.0f) return false;
   const float det = U + V + W;
   if (!(det > 0.0f)) return false;
@@ -402,20 +418,22 @@ struct Trav {
 
 // Distances from the segment origin to the x, y, z faces of the cell, with
 // the ray's reciprocal direction (recomputed where needed, not kept live).
-__device__ inline void exit_dists(const RayP& r, const DevScene& sc, float& te0, float& te1, float& te2) {
-  const float tex = r.dx > 0.0f ? (sc.hi[0] - r.ox) * r.ix : (r.dx < 0.0f ? (sc.lo[0] - r.ox) * r.ix : INFINITY);
-  const float tey = r.dy > 0.0f ? (sc.hi[1] - r.oy) * r.iy : (r.dy < 0.0f ? (sc.lo[1] - r.oy) * r.iy : INFINITY);
-  const float tez = r.dz > 0.0f ? (sc.hi[2] - r.oz) * r.iz : (r.dz < 0.0f ? (sc.lo[2] - r.oz) * r.iz : INFINITY);
+__device__ inline void exit_dists(const RayP& r, float dx, float dy, float dz, const DevScene& sc, float& te0,
+                                  float& te1, float& te2) {
+  const float tex = dx > 0.0f ? (sc.hi[0] - r.ox) * r.ix : (dx < 0.0f ? (sc.lo[0] - r.ox) * r.ix : INFINITY);
+  const float tey = dy > 0.0f ? (sc.hi[1] - r.oy) * r.iy : (dy < 0.0f ? (sc.lo[1] - r.oy) * r.iy : INFINITY);
+  const float tez = dz > 0.0f ? (sc.hi[2] - r.oz) * r.iz : (dz < 0.0f ? (sc.lo[2] - r.oz) * r.iz : INFINITY);
   te0 = fmaxf(tex, 0.0f);
   te1 = fmaxf(tey, 0.0f);
   te2 = fmaxf(tez, 0.0f);
 }
 
-__device__ inline void seg_begin(Trav& s, const DevScene& sc) {
+__device__ inline void seg_begin(Trav& s, float dx, float dy, float dz, const DevScene& sc) {
   float te0, te1, te2;
-  exit_dists(s.r, sc, te0, te1, te2);
+  exit_dists(s.r, dx, dy, dz, sc, te0, te1, te2);
   s.t = fminf(fminf(te0, te1), te2);
   slab_margins(s.r, sc.wext);
+  rotate_origin(s.r);
   s.idx = -1;
   s.oid = 0x7fffffff;
   s.node = 0;
@@ -423,12 +441,17 @@ __device__ inline void seg_begin(Trav& s, const DevScene& sc) {
 }
 
 __device__ inline void tri_candidate(Trav& s, const LaneScene& L, uint32_t k, uint32_t& tests) {
-  const GAS f4v* T = (const GAS f4v*)L.tris + 3 * (size_t)k;
-  const f4v a = T[0], b = T[1], c = T[2];
+  // rotated record: V0, V1, V2 as five floats each (x, y, z, x, y), then the
+  // caller's index; the ray's three coordinates start at byte 4 kx
+  const GAS char* R = (const GAS char*)L.tris + ((size_t)k << 6);
+  const GAS char* P = R + (s.r.kk & 0xFu);
+  const GAS float* F = (const GAS float*)P;
+  const float3 a = make_float3(F[0], F[1], F[2]), b = make_float3(F[5], F[6], F[7]),
+               c = make_float3(F[10], F[11], F[12]);
+  const int32_t oid = *(const GAS int32_t*)(R + 60);
   ++tests;
   float t, b1, b2;
   if (tri_test(s.r, a, b, c, s.t, t, b1, b2)) {
-    const int32_t oid = (int32_t)__float_as_uint(a.w);
     // closest hit; equal distances go to the lower caller index
     if (t < s.t || (t == s.t && oid < s.oid)) {
       s.t = t;
@@ -564,20 +587,21 @@ __device__ inline bool trav_step(Trav& s, const LaneScene& L, LAS uint32_t* lstk
 // through the opposite x / y face and traversal continues (section 2.2
 // boundaries: periodic in x and y, substrate or open bottom at z_min,
 // escape at z_max).
-__device__ inline int seg_end(Trav& s, const DevScene& sc, bool ovf, float& px, float& py) {
+__device__ inline int seg_end(Trav& s, float dx, float dy, float dz, const DevScene& sc, bool ovf, float& px,
+                              float& py) {
   if (s.idx >= 0) {
     s.total += s.t;
     return K_HIT;
   }
   const RayP& r = s.r;
   float te0, te1, te2;
-  exit_dists(r, sc, te0, te1, te2);
+  exit_dists(r, dx, dy, dz, sc, te0, te1, te2);
   if (te2 <= te0 && te2 <= te1) {
     s.total += te2;
-    if (r.dz > 0.0f) return K_ESCAPE;
+    if (dz > 0.0f) return K_ESCAPE;
     if (sc.flags & 2u) {
-      px = r.ox + te2 * r.dx;
-      py = r.oy + te2 * r.dy;
+      px = r.ox + te2 * dx;
+      py = r.oy + te2 * dy;
       return K_SUBSTRATE;
     }
     return K_LOST;
@@ -588,13 +612,13 @@ __device__ inline int seg_end(Trav& s, const DevScene& sc, bool ovf, float& px, 
     return K_LOST;
   }
   s.total += texit;
-  float qx = r.ox + texit * r.dx, qy = r.oy + texit * r.dy, qz = r.oz + texit * r.dz;
+  float qx = r.ox + texit * dx, qy = r.oy + texit * dy, qz = r.oz + texit * dz;
   if (te0 == texit)
-    qx = r.dx > 0.0f ? sc.lo[0] : sc.hi[0];
+    qx = dx > 0.0f ? sc.lo[0] : sc.hi[0];
   else
     qx = fminf(fmaxf(qx, sc.lo[0]), sc.hi[0]);
   if (te1 == texit)
-    qy = r.dy > 0.0f ? sc.lo[1] : sc.hi[1];
+    qy = dy > 0.0f ? sc.lo[1] : sc.hi[1];
   else
     qy = fminf(fmaxf(qy, sc.lo[1]), sc.hi[1]);
   qz = fminf(fmaxf(qz, sc.lo[2]), sc.hi[2]);
@@ -642,6 +666,7 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
   const uint32_t lane = lane_id();
   const uint64_t lt = (1ull << lane) - 1ull;
   LAS uint32_t* lstk = (LAS uint32_t*)smem + (size_t)w * a.lds_stack * 64 + lane;
+  LAS float* ldir = (LAS float*)smem + (size_t)wpb * a.lds_stack * 64 + (size_t)w * 192 + lane;  // [3][64] per wave
   GAS uint32_t* gstk = gp(a.gstack) + ((size_t)(blockIdx.x * wpb + w) * a.gstack_depth) * 64 + lane;
   const uint32_t count = (a.src == 1 && a.count_in) ? min(*gp(a.count_in), a.qcap) : a.count;
 
@@ -656,7 +681,7 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
   const uint32_t total_waves = gridDim.x * (uint32_t)wpb;
   if (!MULTI) {
     L.nodes = a.jobs[0].sc.nodes;
-    L.tris = a.jobs[0].sc.tris;
+    L.tris = a.jobs[0].sc.tris_t;
     L.n_tris = a.jobs[0].sc.n_tris;
     L.flags = a.jobs[0].sc.flags;
   }
@@ -666,9 +691,10 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
       if (st == 2) {
         float px = 0.f, py = 0.f;
         const DevScene& sc = a.jobs[job].sc;
-        const int kind = seg_end(s, sc, ovf, px, py);
+        const float dx = ldir[0], dy = ldir[64], dz = ldir[128];
+        const int kind = seg_end(s, dx, dy, dz, sc, ovf, px, py);
         if (kind < 0) {
-          seg_begin(s, sc);
+          seg_begin(s, dx, dy, dz, sc);
           st = 1;
         } else {
           int32_t code;
@@ -745,7 +771,7 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
             }
             if (MULTI) {
               L.nodes = a.jobs[job].sc.nodes;
-              L.tris = a.jobs[job].sc.tris;
+              L.tris = a.jobs[job].sc.tris_t;
               L.n_tris = a.jobs[job].sc.n_tris;
               L.flags = a.jobs[job].sc.flags;
             }
@@ -758,7 +784,10 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
             visits = 0;
             tests = 0;
             ovf = false;
-            seg_begin(s, a.jobs[job].sc);
+            ldir[0] = dx;
+            ldir[64] = dy;
+            ldir[128] = dz;
+            seg_begin(s, dx, dy, dz, a.jobs[job].sc);
             st = 1;
           }
         }
@@ -1265,7 +1294,8 @@ __global__ __launch_bounds__(256) void k_copy_probe(float4* __restrict__ dst4, c
 
 }  // namespace
 
-size_t traverse_lds_bytes(int lds_stack, int block) { return (size_t)(block / 64) * lds_stack * 64 * 4; }
+// per wave: the stacks' LDS part, then the lanes' ray directions
+size_t traverse_lds_bytes(int lds_stack, int block) { return (size_t)(block / 64) * (lds_stack + 3) * 64 * 4; }
 
 size_t shade_lds_bytes(const DevTables& tb, int n_hist, int block, int n_jobs) {
   const int wpb = block / 64;
