@@ -33,8 +33,9 @@ NODE_BYTES = 64
 # LBVH build per triangle: Morton codes (48 read + 12 written), 8 radix passes
 # (8 + 24 bytes each), triangle gather (4 + 48 read, 48 sorted + 64 rotated
 # written), hierarchy (24 key reads + 16 link writes), bottom-up bounds (48
-# triangle read + 64 node write + 12)
-BUILD_BYTES_PER_TRI = 60 + 8 * 32 + 164 + 40 + 124
+# triangle read + 64 node write + 12), 4-wide collapse (64 read + 64 written)
+# and the breadth-first copy of the reached half (32 read + 32 written)
+BUILD_BYTES_PER_TRI = 60 + 8 * 32 + 164 + 40 + 124 + 128 + 64
 # one triangle test reads the three vertices in the ray's axis order (3 x 12 B)
 # and the caller's index (4 B) from the triangle's rotated 64-byte record
 TRI_BYTES = 40

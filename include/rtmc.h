@@ -204,10 +204,12 @@ rtmc_status rtmc_get_scene_info(rtmc_ctx* ctx, int32_t scene_id, rtmc_scene_info
 rtmc_status rtmc_bvh_download(rtmc_ctx* ctx, int32_t scene_id, float* nodes, float* tris);
 
 /* Copy the 4-wide nodes that traversal reads (for inspection and tests).
- * Node i (one per binary internal node) holds the children of binary node
- * i, the inner child of largest surface area replaced by its two children
- * until four slots are filled; traversal starts at node 0 and follows the
- * links.  wide: host uint32 [n_nodes * 16]:
+ * Each node holds the children of one binary node, the inner child of
+ * largest surface area replaced by its two children until four slots are
+ * filled.  Node 0 is the root (binary node 0); the nodes reached from it
+ * follow level by level, the inner children of a node in consecutive nodes
+ * (their order within a level may differ from build to build); the rest of
+ * the n_nodes records are zero.  wide: host uint32 [n_nodes * 16]:
  *   words 0-2: float origin o (x, y, z); word 3: bytes 0-2 the biased
  *     exponents e + 127 of the per-axis scales s = 2^e;
  *   words 4-7: child links (bit 31 set: leaf, low bits: sorted triangle

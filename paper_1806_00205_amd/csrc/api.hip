@@ -763,8 +763,10 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
     return RTMC_OK;
   }
   const int64_t nn = std::max<int64_t>(n - 1, 1);
-  DevBuf tris, tris_t, nodes, nodes4, keys, vals, keys2, vals2, parent, flags, hist, depth;
+  DevBuf tris, tris_t, nodes, nodes4, nodes4b, lv, keys, vals, keys2, vals2, parent, flags, hist, depth;
   auto cleanup = [&]() {
+    dev_free(c, nodes4b);
+    dev_free(c, lv);
     dev_free(c, keys);
     dev_free(c, vals);
     dev_free(c, keys2);
@@ -778,7 +780,8 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
       ensure(c, keys, (size_t)n * 8) ||
       ensure(c, vals, (size_t)n * 4) || ensure(c, keys2, (size_t)n * 8) || ensure(c, vals2, (size_t)n * 4) ||
       ensure(c, parent, (size_t)(nn + n) * 4) || ensure(c, flags, (size_t)nn * 8) ||
-      ensure(c, hist, radix_hist_words(n) * 4) || ensure(c, depth, 16)) {
+      ensure(c, hist, radix_hist_words(n) * 4) || ensure(c, depth, 16) || ensure(c, nodes4b, (size_t)nn * 64) ||
+      ensure(c, lv, 2 * kRelayoutLevels * 4)) {
     cleanup();
     dev_free(c, tris);
     dev_free(c, tris_t);
@@ -807,10 +810,19 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
   }
   hipError_t e = hipEventRecord(c->ev0, c->stream);
   if (e == hipSuccess) e = build_bvh(b, c->stream);
-  if (e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   uint32_t d = 1;
   if (e == hipSuccess && n > 1) e = hipMemcpy(&d, depth.p, 4, hipMemcpyDeviceToHost);
+  // breadth-first copy of the reached 4-wide records (the 4-wide depth is at
+  // most the binary one); a tree too deep for the level table keeps the
+  // collapsed layout, which traversal reads just as well
+  const bool relaid = e == hipSuccess && (int64_t)d + 2 <= kRelayoutLevels;
+  if (relaid)
+    e = relayout_wide(b.nodes4, reinterpret_cast<float4*>(nodes4b.p), nn, b.vals, b.vals_alt,
+                      reinterpret_cast<uint32_t*>(lv.p), (int)d + 1, c->stream);
+  if (e == hipSuccess) e = hipEventRecord(c->ev1, c->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e == hipSuccess && relaid) std::swap(nodes4, nodes4b);
   float ms = 0.f;
   if (e == hipSuccess) e = hipEventElapsedTime(&ms, c->ev0, c->ev1);
   cleanup();

@@ -13,6 +13,8 @@
 // Child boxes are stored in the parent (64-byte node record); k_collapse4
 // then turns every binary node into the quantized 4-wide node traversal
 // reads (up to four children per 64-byte record).
+#include <algorithm>
+
 #include "rtmc_internal.h"
 
 namespace rtmc {
@@ -484,6 +486,94 @@ __global__ void k_collapse4(const float4* __restrict__ nodes, int64_t nn, float4
   out[1] = make_float4(__uint_as_float(c[0]), __uint_as_float(c[1]), __uint_as_float(c[2]), __uint_as_float(c[3]));
   out[2] = make_float4(__uint_as_float(ql[0]), __uint_as_float(ql[1]), __uint_as_float(ql[2]), __uint_as_float(qh[0]));
   out[3] = make_float4(__uint_as_float(qh[1]), __uint_as_float(qh[2]), 0.0f, 0.0f);
+}
+
+// ---------------------------------------------------------------- relayout
+
+// One level of the breadth-first relayout of the 4-wide records.  Only the
+// records reached from the root are kept (about half: the others belong to
+// binary nodes absorbed into a parent's four slots), level after level, and
+// the inner children of a record take consecutive records, so a line holds
+// records that one ray visits together.  lv[0..kLevels) counts the records
+// of each level, lv[kLevels + l] is the first record of level l; front_in
+// lists the level's records by their index in the collapsed array.  A block
+// takes one atomic for its threads' children (a scan in LDS); the order of
+// blocks within a level, hence of records within it, is not fixed.
+constexpr int kRelayoutBlock = 256;
+typedef float f4v __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(kRelayoutBlock) void k_relayout_level(const float4* __restrict__ src,
+                                                                  float4* __restrict__ dst,
+                                                                  const uint32_t* __restrict__ front_in,
+                                                                  uint32_t* __restrict__ front_out,
+                                                                  uint32_t* __restrict__ lv, int level) {
+  __shared__ uint32_t s_cnt[kRelayoutBlock];
+  __shared__ uint32_t s_base;
+  const uint32_t n_in = lv[level];
+  const uint32_t first = lv[kRelayoutLevels + level];
+  const uint32_t next_first = first + n_in;
+  if (blockIdx.x == 0 && threadIdx.x == 0) lv[kRelayoutLevels + level + 1] = next_first;
+  for (uint32_t i0 = blockIdx.x * kRelayoutBlock; i0 < n_in; i0 += gridDim.x * kRelayoutBlock) {
+    const uint32_t i = i0 + threadIdx.x;
+    f4v r0 = {0, 0, 0, 0}, r1 = r0, r2 = r0, r3 = r0;
+    uint32_t k = 0;
+    if (i < n_in) {
+      const float4* R = src + 4 * (size_t)front_in[i];
+      r0 = *(const f4v*)&R[0];
+      r1 = *(const f4v*)&R[1];
+      r2 = *(const f4v*)&R[2];
+      r3 = *(const f4v*)&R[3];
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t l = __float_as_uint(r1[j]);
+        k += (l != kEmpty && !(l & kLeafBit)) ? 1u : 0u;
+      }
+    }
+    // exclusive scan of the block's child counts
+    s_cnt[threadIdx.x] = k;
+    __syncthreads();
+    for (int off = 1; off < kRelayoutBlock; off <<= 1) {
+      const uint32_t v = threadIdx.x >= (unsigned)off ? s_cnt[threadIdx.x - off] : 0u;
+      __syncthreads();
+      s_cnt[threadIdx.x] += v;
+      __syncthreads();
+    }
+    const uint32_t incl = s_cnt[threadIdx.x];
+    if (threadIdx.x == kRelayoutBlock - 1) s_base = atomicAdd(&lv[level + 1], incl);
+    __syncthreads();
+    uint32_t pos = s_base + incl - k;
+    if (i < n_in) {
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t l = __float_as_uint(r1[j]);
+        if (l != kEmpty && !(l & kLeafBit)) {
+          front_out[pos] = l;
+          r1[j] = __uint_as_float(next_first + pos);
+          ++pos;
+        }
+      }
+      f4v* D = (f4v*)(dst + 4 * (size_t)(first + i));
+      D[0] = r0;
+      D[1] = r1;
+      D[2] = r2;
+      D[3] = r3;
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t relayout_wide(const float4* src, float4* dst, int64_t nn, uint32_t* front0, uint32_t* front1,
+                         uint32_t* lv, int levels, hipStream_t s) {
+  if (levels + 1 > kRelayoutLevels) return hipErrorInvalidValue;
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(dst), 0u, (size_t)nn * 16, s);
+  if (e == hipSuccess) e = launch_fill_u32(lv, 0u, 2 * kRelayoutLevels, s);
+  if (e == hipSuccess) e = launch_fill_u32(lv, 1u, 1, s);        // level 0: the root record
+  if (e == hipSuccess) e = launch_fill_u32(front0, 0u, 1, s);    // ... which is record 0
+  if (e != hipSuccess) return e;
+  const int grid = (int)std::min<int64_t>((nn + kRelayoutBlock - 1) / kRelayoutBlock, 2048);
+  for (int l = 0; l < levels; ++l) {
+    k_relayout_level<<<grid, kRelayoutBlock, 0, s>>>(src, dst, (l & 1) ? front1 : front0, (l & 1) ? front0 : front1,
+                                                     lv, l);
+  }
+  return hipGetLastError();
 }
 
 hipError_t build_bvh(BvhBuild& b, hipStream_t s) {

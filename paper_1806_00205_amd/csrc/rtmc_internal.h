@@ -245,5 +245,12 @@ size_t radix_hist_words(int64_t n);
 hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                             uint32_t* hist, int64_t n, int key_bits, hipStream_t s, bool* result_in_alt);
 hipError_t build_bvh(BvhBuild& b, hipStream_t s);
+// Breadth-first copy of the 4-wide records reached from the root (src, nn
+// records) into dst (nn records, the tail zero), children of a record in
+// consecutive records; levels >= the tree's 4-wide depth.  front0 / front1:
+// nn words each; lv: 2 kRelayoutLevels words.
+constexpr int kRelayoutLevels = 128;
+hipError_t relayout_wide(const float4* src, float4* dst, int64_t nn, uint32_t* front0, uint32_t* front1,
+                         uint32_t* lv, int levels, hipStream_t s);
 
 }  // namespace rtmc

@@ -128,10 +128,12 @@ def _decode(q, s, o):
 
 
 def _check_wide(wide, nodes, tris, n):
-    """Quantized 4-wide nodes against the binary tree they are collapsed from:
-    node i holds the children of binary node i, the largest inner slot
-    expanded until four; every decoded box contains its child's exact box; the
-    nodes reached from node 0 reference every triangle exactly once."""
+    """Quantized 4-wide nodes against the binary tree they are collapsed from,
+    walked from the root (node 0 = binary node 0): each node holds the children
+    of its binary node, the largest inner slot expanded until four; every
+    decoded box contains its child's exact box; the nodes reached from node 0
+    reference every triangle exactly once; they fill the first records level
+    by level, a node's inner children in consecutive records, the rest zero."""
     links = nodes[:, 12:14].view(np.uint32)
     boxes = nodes[:, :12].reshape(-1, 2, 6)
     tb = tris.reshape(-1, 3, 4)[:, :, :3]
@@ -160,21 +162,26 @@ def _check_wide(wide, nodes, tris, n):
         return out
 
     seen = np.zeros(n, dtype=np.int64)
-    stack = [0]
-    while stack:
-        i = stack.pop()
-        w = wide[i]
+    queue = [(0, 0)]  # (record, binary node), breadth first
+    level_of = {0: 0}
+    for r, i in queue:
+        w = wide[r]
         o = w[0:3].view(np.float32)
         sc = [np.float32(2.0) ** (int((w[3] >> (8 * a)) & 0xFF) - 127) for a in range(3)]
         expect = slots_of(i)
         assert 2 <= len(expect) <= 4
+        inner = []
         for j in range(4):
             link = w[4 + j]
             if j >= len(expect):
                 assert link == empty
                 continue
             el, ebox = expect[j]
-            assert link == el
+            if el & leaf_bit:
+                assert link == el
+            else:
+                assert not (link & leaf_bit) and link != empty
+                inner.append(int(link))
             q = [(w[8 + k] >> np.uint32(8 * j)) & np.uint32(0xFF) for k in range(6)]
             lo = [_decode(q[a], sc[a], o[a]) for a in range(3)]
             hi = [_decode(q[3 + a], sc[a], o[a]) for a in range(3)]
@@ -187,8 +194,17 @@ def _check_wide(wide, nodes, tris, n):
                 assert np.all(ebox[:3] <= tri_box[k, :3]) and np.all(ebox[3:] >= tri_box[k, 3:])
                 seen[k] += 1
             else:
-                stack.append(int(link))
+                queue.append((int(link), int(el)))
+                level_of[int(link)] = level_of[r] + 1
+        # inner children: consecutive records, right after everything queued before them
+        if inner:
+            assert inner == list(range(inner[0], inner[0] + len(inner))), (r, inner)
     assert np.all(seen == 1) if n > 1 else seen[0] == 2
+    recs = [r for r, _ in queue]
+    assert sorted(recs) == list(range(len(recs)))  # compact: records 0 .. reached - 1
+    lv = [level_of[r] for r in range(len(recs))]
+    assert lv == sorted(lv)  # level by level
+    assert not wide[len(recs):].any()
 
 
 @pytest.mark.parametrize("n,p,seed", [(8, 0.5, 1), (16, 0.5, 0), (24, 0.7, 2)])
