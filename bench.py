@@ -39,6 +39,7 @@ BUILD_BYTES_PER_TRI = 60 + 8 * 32 + 164 + 40 + 124 + 128 + 64
 # one triangle test reads the three vertices in the ray's axis order (3 x 12 B)
 # and the caller's index (4 B) from the triangle's rotated 64-byte record
 TRI_BYTES = 40
+SWEEP_CHUNK = 1 << 26  # primaries per chunk of the batched sweep
 
 CONFIGS = {
     "c1": dict(n=128, porosity=0.6, ell=2.0, seed=1, energies=[50.0, 100.0, 250.0, 500.0, 1000.0],
@@ -122,11 +123,15 @@ def main():
           file=sys.stderr, flush=True)
     points = [(E, th) for E in cfg["energies"] for th in cfg["thetas"]]
 
+    # the points go through the library as one batch: chunks of up to 2^26
+    # primaries span several points, so every generation's launch is large
+    # (per-point results are those of single traces, integer tallies equal)
+    lc = ctx.get_launch()
+    ctx.set_launch(lc["block"], lc["wg_per_cu"], lc["lds_stack"], SWEEP_CHUNK, lc["refill"], lc["occupancy"])
+    jobs = [(sid, E, th, npp, cfg["rng"] * 1000 + k) for k, (E, th) in enumerate(points)]
+
     def step():
-        res = []
-        for k, (E, th) in enumerate(points):
-            res.append(ctx.trace(sid, tid, E, th, npp, seed=cfg["rng"] * 1000 + k, max_gen=cfg["max_gen"]))
-        return res
+        return ctx.trace_batch(tid, jobs, max_gen=cfg["max_gen"])
 
     for w in range(args.warmup):
         step()
@@ -143,9 +148,11 @@ def main():
             tot["tests"] += r["n_tri_tests"]
             tot["visits"] += r["n_node_visits"]
             tot["spawned"] += r["n_spawned"]
-            tot["kms"] += r["kernel_ms"]
-            tot["sms"] += r["shade_ms"]
-            tot["launches"] += r["n_kernel_launches"]
+        # timing and launch counts are the whole batch's, repeated in every job's result
+        assert last[0]["kernel_ms"] > 0.0, "batch was replayed as a graph: no per-launch timing"
+        tot["kms"] += last[0]["kernel_ms"]
+        tot["sms"] += last[0]["shade_ms"]
+        tot["launches"] += last[0]["n_kernel_launches"]
         print(f"[bench] step {s + 1}/{args.steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t_start
@@ -173,7 +180,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {cfg['name']}", "n_tris": info["n_tris"],
                    "primaries_per_point": npp, "points": len(points), "bvh_depth": info["bvh_depth"],
-                   "launch": ctx.get_launch()},
+                   "call": "rtmc_trace_batch over the points", "launch": ctx.get_launch()},
         "tri_tests_per_s": tot["tests"] / wall,
         "rays_per_s": tot["rays"] / wall,
         "node_visits_per_ray": tot["visits"] / max(tot["rays"], 1),

@@ -128,7 +128,7 @@ typedef struct {
   double e_deposited;  /* energy left in the surface (same fixed point); e_escaped + e_deposited = E0 n */
   double ms;           /* elapsed device time of the whole launch sequence */
   double kernel_ms;    /* summed duration of the traversal-kernel launches (HIP events around
-                          each launch; 0 for rtmc_trace_batch, which replays a graph) */
+                          each launch; 0 when rtmc_trace_batch replays a graph) */
   double shade_ms;     /* summed duration of the shading-kernel launches (same rules) */
   uint64_t n_kernel_launches;
   int32_t n_chunks;    /* primary chunks used (grows when a queue would overflow) */
@@ -231,9 +231,15 @@ rtmc_status rtmc_load_tables(rtmc_ctx* ctx, const rtmc_tables* t, int32_t* table
 rtmc_status rtmc_trace(rtmc_ctx* ctx, int32_t scene_id, int32_t table_id, double E_eV, double theta_deg,
                        uint64_t n_primaries, uint64_t seed, const rtmc_trace_opts* opts, rtmc_result* out);
 
-/* Many (scene, E, theta) jobs through one launch sequence replayed as a HIP
- * graph; outs[i] receives job i's result.  One table set and max_gen for all
- * jobs.  Integer tallies equal those of the same jobs traced one by one. */
+/* Many (scene, E, theta) jobs through one launch sequence: chunks of the
+ * concatenated primaries (at most the launch configuration's chunk; a chunk
+ * holding a quarter of that is closed before it would span a ninth job) go
+ * through traversal and shading generation by generation; outs[i] receives job i's result.  One table set and max_gen
+ * for all jobs.  A sequence of more than 128 traversal launches (chunks x
+ * (max_gen + 1)) is replayed as a HIP graph, and kernel_ms / shade_ms are then
+ * 0; a shorter one is launched directly and timed launch by launch.  Jobs
+ * that share one scene run the single-scene traversal kernel.  Integer
+ * tallies equal those of the same jobs traced one by one. */
 rtmc_status rtmc_trace_batch(rtmc_ctx* ctx, int32_t table_id, const rtmc_job* jobs, int64_t n_jobs,
                              int32_t max_gen, rtmc_result* outs);
 

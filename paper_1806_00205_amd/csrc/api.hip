@@ -276,6 +276,15 @@ std::vector<ChunkPlan> plan_chunks(const std::vector<HostJob>& jobs, uint32_t ch
   return out;
 }
 
+// Rays of several scenes in one launch: traversal then takes each ray's scene
+// from its job (the batched kernel); jobs that share one scene use the
+// single-scene kernel.
+bool multi_scene(const std::vector<HostJob>& jobs) {
+  for (auto& j : jobs)
+    if (j.scene != jobs[0].scene) return true;
+  return false;
+}
+
 // Enqueue the launch sequence of a batch of jobs with a given chunk size:
 // per chunk and generation, traversal then shading.
 rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJob>& jobs, int max_gen,
@@ -291,9 +300,7 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   const int ncnt = 2 * (kMaxGen + 2);
   int gdepth = kGlobalStack;
   for (auto& j : jobs) gdepth = std::max(gdepth, stack_need(c->scenes[j.scene].depth));
-  bool multi = false;
-  for (auto& j : jobs) multi = multi || j.scene != jobs[0].scene;
-  multi = multi || jobs.size() > 1;
+  const bool multi = multi_scene(jobs);
 
   HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->tally.p), 0ull, tw * jobs.size(), s));
   HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->counters.p), 0u, (size_t)ncnt * n_chunks, s));
@@ -481,8 +488,7 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
       int gd = kGlobalStack;
       for (auto& j : jobs) gd = std::max(gd, stack_need(c->scenes[j.scene].depth));
       key.push_back((uint64_t)gd);
-      bool multi = jobs.size() > 1;
-      key.push_back(multi ? 1u : 0u);
+      key.push_back(multi_scene(jobs) ? 1u : 0u);
       // the per-job primary counts fix each chunk's job range, baked into the launches
       for (auto& j : jobs) key.push_back(j.n);
       uint64_t nl = 0;
@@ -596,6 +602,9 @@ void fill_result(const unsigned long long* t, const HostJob& j, int n_ebins, int
 }
 
 bool finite_f(float x) { return std::isfinite(x); }
+
+// A batch whose sequence holds more traversal launches than this is replayed as a HIP graph.
+constexpr uint64_t kGraphLaunches = 128;
 
 }  // namespace
 
@@ -1036,8 +1045,11 @@ rtmc_status rtmc_trace_batch(rtmc_ctx* c, int32_t table_id, const rtmc_job* jobs
     for (int64_t i = 0; i < n_jobs; ++i) std::memset(&outs[i], 0, sizeof(rtmc_result));
     return RTMC_OK;
   }
+  // a long sequence of launches (many small chunks) is replayed as a graph;
+  // a short one is launched directly, which also times every launch
+  const uint64_t n_launch = (uint64_t)plan_chunks(hj, (uint32_t)c->cfg.chunk).size() * (uint64_t)(max_gen + 1);
   TraceOut to;
-  rtmc_status st = run_trace(c, table_id, hj, max_gen, 256, 90, 0, true, to);
+  rtmc_status st = run_trace(c, table_id, hj, max_gen, 256, 90, 0, n_launch > kGraphLaunches, to);
   if (st) return st;
   const size_t tw = (size_t)T_NCOUNT + 256 + 90;
   for (int64_t i = 0; i < n_jobs; ++i)

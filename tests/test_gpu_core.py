@@ -394,6 +394,33 @@ def test_yield_parity_tiny_foam(ctx, torch, oracle_lib, tiny, vaughan):
 
 
 @pytest.mark.slow
+def test_full_size_sweep_batch_equals_single_traces(ctx, vaughan):
+    """The benchmark's 128^3 sweep (5 energies x 5 angles, 1e7 primaries per
+    point, max_gen 6) in the launch shape it times -- one rtmc_trace_batch with
+    2^26-primary chunks spanning several points, the single-scene kernel, a
+    directly launched sequence -- gives every point the integer tallies of its
+    own rtmc_trace (which the sampled oracle test pins at full size)."""
+    m = fg.make_grf_foam(128, 0.6, 2.0, seed=1)
+    sid = ctx.load_scene(m)
+    tid = ctx.load_tables(vaughan)
+    pts = [(E, th) for E in (50.0, 100.0, 250.0, 500.0, 1000.0) for th in (0.0, 20.0, 40.0, 60.0, 80.0)]
+    jobs = [(sid, E, th, 10_000_000, 2000 + k) for k, (E, th) in enumerate(pts)]
+    cfg = ctx.get_launch()
+    ctx.set_launch(cfg["block"], cfg["wg_per_cu"], cfg["lds_stack"], 1 << 26, cfg["refill"], cfg["occupancy"])
+    try:
+        outs = ctx.trace_batch(tid, jobs, max_gen=6)
+    finally:
+        ctx.set_launch(**cfg)
+    assert outs[0]["n_chunks"] == 4 and outs[0]["kernel_ms"] > 0.0
+    for (s, E, th, n, sd), b in zip(jobs, outs):
+        r = ctx.trace(s, tid, E, th, n, seed=sd, max_gen=6)
+        for key in ("n_rays", "n_escaped", "n_absorbed", "n_truncated", "n_lost", "n_substrate", "n_tri_tests",
+                    "n_node_visits", "n_wraps", "n_spawned", "e_escaped", "e_deposited"):
+            assert b[key] == r[key], (E, th, key, b[key], r[key])
+        assert b["yield_sigma"] == pytest.approx(r["yield_sigma"], rel=1e-12)
+
+
+@pytest.mark.slow
 @pytest.mark.parametrize("grid,porosity,seed,theta,n,max_gen,k", [
     (128, 0.6, 1, 40.0, 10_000_000, 6, 256),   # one point of the 128^3 sweep (1.91M triangles)
     (256, 0.8, 4, -80.0, 100_000_000, 10, 64),  # the 256^3 run (11.0M triangles), random incidence
@@ -511,24 +538,50 @@ def test_errors_are_reported(ctx, vaughan):
 
 
 def test_batch_graph_replays_match_eager(ctx, tiny, vaughan):
-    """rtmc_trace_batch records its launch sequence once as a HIP graph and
-    replays it for later calls of the same shape: replay it several times,
-    with eager traces (other kernels, synchronisations) in between, and check
-    every replay against the eager single-job results."""
+    """rtmc_trace_batch records a long launch sequence (here 128-primary
+    chunks: over 128 traversal launches) once as a HIP graph and replays it
+    for later calls of the same shape: replay it several times, with eager
+    traces (other kernels, synchronisations) in between, and check every
+    replay against the eager single-job results."""
     s1 = ctx.load_scene(tiny)
     s2 = ctx.load_scene(fg.make_grf_foam(12, 0.7, 2.0, seed=5))
     tid = ctx.load_tables(vaughan)
     keys = ("n_rays", "n_escaped", "n_absorbed", "n_truncated", "n_lost", "n_tri_tests", "n_node_visits",
             "e_escaped", "e_deposited")
+    cfg = ctx.get_launch()
     for rep in range(4):
         seeds = (11 + rep, 12 + rep, 13 + rep)
         jobs = [(s1, 500.0, 0.0, 3000, seeds[0]), (s2, 150.0, 30.0, 2000, seeds[1]),
                 (s1, 900.0, -80.0, 2500, seeds[2])]
-        outs = ctx.trace_batch(tid, jobs, max_gen=6)
+        ctx.set_launch(cfg["block"], cfg["wg_per_cu"], cfg["lds_stack"], 128)
+        try:
+            outs = ctx.trace_batch(tid, jobs, max_gen=6)
+        finally:
+            ctx.set_launch(**cfg)
+        assert outs[0]["n_kernel_launches"] > 128 and outs[0]["kernel_ms"] == 0.0  # replayed graph
         eager = [ctx.trace(s, tid, E, th, n, seed=sd, max_gen=6) for s, E, th, n, sd in jobs]
         for b, r in zip(outs, eager):
             for k in keys:
                 assert b[k] == r[k], (rep, k, b[k], r[k])
+
+
+def test_same_scene_batch_runs_directly(ctx, tiny, vaughan):
+    """A sweep of (E, theta) points on one scene as one batch: a short launch
+    sequence runs directly (every launch timed) with the single-scene
+    traversal kernel, chunks spanning several points; integer tallies equal
+    the points traced one by one."""
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    jobs = [(sid, E, th, 4000 + 500 * k, 30 + k) for k, (E, th) in
+            enumerate([(50.0, 0.0), (250.0, 40.0), (1000.0, 80.0), (500.0, -60.0), (100.0, 20.0)])]
+    outs = ctx.trace_batch(tid, jobs, max_gen=6)
+    assert outs[0]["n_chunks"] == 1 and outs[0]["n_kernel_launches"] == 7
+    for (s, E, th, n, sd), b in zip(jobs, outs):
+        assert b["kernel_ms"] > 0.0 and b["shade_ms"] > 0.0
+        r = ctx.trace(s, tid, E, th, n, seed=sd, max_gen=6)
+        for k in ("n_rays", "n_escaped", "n_absorbed", "n_truncated", "n_lost", "n_tri_tests", "n_node_visits",
+                  "n_wraps", "e_escaped", "e_deposited"):
+            assert b[k] == r[k], (E, th, k, b[k], r[k])
 
 
 def test_irregular_spectrum_table(ctx, oracle_lib):
