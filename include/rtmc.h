@@ -210,13 +210,13 @@ rtmc_status rtmc_bvh_download(rtmc_ctx* ctx, int32_t scene_id, float* nodes, flo
  * follow level by level, the inner children of a node in consecutive nodes
  * (their order within a level may differ from build to build); the rest of
  * the n_nodes records are zero.  wide: host uint32 [n_nodes * 16]:
- *   words 0-2: float origin o (x, y, z); word 3: bytes 0-2 the biased
- *     exponents e + 127 of the per-axis scales s = 2^e;
+ *   words 0-2: float origin o (x, y, z); words 3, 14, 15: the per-axis
+ *     scales s_x, s_y, s_z as floats, each a power of two;
  *   words 4-7: child links (bit 31 set: leaf, low bits: sorted triangle
  *     index; else a node index; 0xFFFFFFFF: unused slot);
  *   words 8-13: lo_x, lo_y, lo_z, hi_x, hi_y, hi_z, each four bytes q (byte j
  *     for child j); a bound decodes as fmaf(q, s, o) and contains the exact
- *     child box; words 14-15 zero. */
+ *     child box. */
 rtmc_status rtmc_bvh_download_wide(rtmc_ctx* ctx, int32_t scene_id, uint32_t* wide);
 
 /* Upload flat-surface tables; returns the table id in *table_id. */

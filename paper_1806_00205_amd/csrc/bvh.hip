@@ -481,11 +481,12 @@ __global__ void k_collapse4(const float4* __restrict__ nodes, int64_t nn, float4
       qh[a] |= q_hi(b[j][3 + a], o[a], sc[a]) << (8 * j);
     }
   float4* out = nodes4 + 4 * i;
-  const uint32_t ex = (uint32_t)(e[0] + 127) | ((uint32_t)(e[1] + 127) << 8) | ((uint32_t)(e[2] + 127) << 16);
-  out[0] = make_float4(o[0], o[1], o[2], __uint_as_float(ex));
+  // the scales 2^e themselves (x in word 3, y and z in words 14 and 15), so
+  // that traversal takes a plane's step as one product
+  out[0] = make_float4(o[0], o[1], o[2], sc[0]);
   out[1] = make_float4(__uint_as_float(c[0]), __uint_as_float(c[1]), __uint_as_float(c[2]), __uint_as_float(c[3]));
   out[2] = make_float4(__uint_as_float(ql[0]), __uint_as_float(ql[1]), __uint_as_float(ql[2]), __uint_as_float(qh[0]));
-  out[3] = make_float4(__uint_as_float(qh[1]), __uint_as_float(qh[2]), 0.0f, 0.0f);
+  out[3] = make_float4(__uint_as_float(qh[1]), __uint_as_float(qh[2]), sc[1], sc[2]);
 }
 
 // ---------------------------------------------------------------- relayout

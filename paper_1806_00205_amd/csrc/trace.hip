@@ -499,9 +499,7 @@ __device__ inline bool trav_step(Trav& s, const LaneScene& L, LAS uint32_t* lstk
   const RayP& r = s.r;
   // per axis: distance per code step (exact, the scale being a power of
   // two) and the near and far distances of the node origin with the margin
-  const uint32_t ex = __float_as_uint(q0.w);
-  const float ax = __uint_as_float((ex & 0xFFu) << 23) * r.ix, ay = __uint_as_float(((ex >> 8) & 0xFFu) << 23) * r.iy,
-              az = __uint_as_float(((ex >> 16) & 0xFFu) << 23) * r.iz;
+  const float ax = q0.w * r.ix, ay = q3.z * r.iy, az = q3.w * r.iz;
   const float bx = q0.x - r.ox, by = q0.y - r.oy, bz = q0.z - r.oz;
   const float mx = r.w * fabsf(r.ix), my = r.w * fabsf(r.iy), mz = r.w * fabsf(r.iz);
   const float nbx = fmaf(bx, r.ix, -mx), nby = fmaf(by, r.iy, -my), nbz = fmaf(bz, r.iz, -mz);

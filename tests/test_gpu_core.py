@@ -167,7 +167,9 @@ def _check_wide(wide, nodes, tris, n):
     for r, i in queue:
         w = wide[r]
         o = w[0:3].view(np.float32)
-        sc = [np.float32(2.0) ** (int((w[3] >> (8 * a)) & 0xFF) - 127) for a in range(3)]
+        sc = [w[k:k + 1].view(np.float32)[0] for k in (3, 14, 15)]
+        for a in range(3):  # powers of two
+            assert sc[a] > 0 and np.frexp(sc[a])[0] == 0.5
         expect = slots_of(i)
         assert 2 <= len(expect) <= 4
         inner = []
