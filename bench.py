@@ -39,7 +39,7 @@ BUILD_BYTES_PER_TRI = 60 + 8 * 32 + 164 + 40 + 124 + 128 + 64
 # one triangle test reads the three vertices in the ray's axis order (3 x 12 B)
 # and the caller's index (4 B) from the triangle's rotated 64-byte record
 TRI_BYTES = 40
-SWEEP_CHUNK = 1 << 27  # primaries per chunk of the batched sweep
+SWEEP_CHUNK = 1 << 28  # primaries per chunk of the batched sweep
 
 CONFIGS = {
     "c1": dict(n=128, porosity=0.6, ell=2.0, seed=1, energies=[50.0, 100.0, 250.0, 500.0, 1000.0],
@@ -123,7 +123,7 @@ def main():
           file=sys.stderr, flush=True)
     points = [(E, th) for E in cfg["energies"] for th in cfg["thetas"]]
 
-    # the points go through the library as one batch: chunks of up to 2^27
+    # the points go through the library as one batch: chunks of up to 2^28
     # primaries span several points, so every generation's launch is large
     # (per-point results are those of single traces, integer tallies equal)
     lc = ctx.get_launch()

@@ -233,7 +233,7 @@ rtmc_status rtmc_trace(rtmc_ctx* ctx, int32_t scene_id, int32_t table_id, double
 
 /* Many (scene, E, theta) jobs through one launch sequence: chunks of the
  * concatenated primaries (at most the launch configuration's chunk; a chunk
- * holding a quarter of that is closed before it would span a 17th job) go
+ * holding a quarter of that is closed before it would span a 33rd job) go
  * through traversal and shading generation by generation; outs[i] receives job i's result.  One table set and max_gen
  * for all jobs.  A sequence of more than 128 traversal launches (chunks x
  * (max_gen + 1)) is replayed as a HIP graph, and kernel_ms / shade_ms are then

@@ -427,7 +427,10 @@ rtmc_status prepare_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   if (st) return st;
   HIPCHK(c, hipMemcpyAsync(c->jobs.p, dj.data(), sizeof(DevJob) * dj.size(), hipMemcpyHostToDevice, c->stream));
   const uint32_t chunk = (uint32_t)cfg.chunk;
-  const uint64_t need_q = (uint64_t)chunk * tb.max_d;
+  // queues sized for the largest chunk this trace plans (at most `chunk` primaries)
+  uint64_t max_chunk = 1;
+  for (const ChunkPlan& p : plan_chunks(jobs, chunk)) max_chunk = std::max<uint64_t>(max_chunk, p.n);
+  const uint64_t need_q = max_chunk * tb.max_d;
   // the 32-bit work counters may run past the queue length by one block claim per wave
   const uint64_t claim_slack = (uint64_t)grid_of(c, cfg) * (cfg.block / 64) * kClaimMax;
   if (need_q + claim_slack > 0xFFFFFFF0ull) return fail(c, RTMC_EINVAL, "chunk too large for the queue index range");
@@ -465,7 +468,10 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
     rtmc_status st = prepare_trace(c, tb, jobs, n_ebins, n_abins, n_zbins, cfg, &total);
     if (st) return st;
     const size_t lds_t = traverse_lds_bytes(cfg.lds_stack, cfg.block);
-    const size_t lds_s = shade_lds_bytes(dev_tables(tb), n_ebins + n_abins + n_zbins, kShadeBlock, kShadeJobs);
+    // shading keeps per-job tallies in LDS for chunks of at most kShadeJobs jobs
+    int max_jobs = 1;
+    for (const ChunkPlan& p : plan_chunks(jobs, (uint32_t)cfg.chunk)) max_jobs = std::max(max_jobs, p.j_hi - p.j_lo + 1);
+    const size_t lds_s = shade_lds_bytes(dev_tables(tb), n_ebins + n_abins + n_zbins, kShadeBlock, max_jobs);
     if (lds_t > c->lds_per_block || lds_s > c->lds_per_block)
       return fail(c, RTMC_EINVAL, "launch needs %zu / %zu bytes of LDS per workgroup (device limit %zu)", lds_t,
                   lds_s, c->lds_per_block);

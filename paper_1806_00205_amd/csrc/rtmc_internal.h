@@ -40,7 +40,7 @@ constexpr int kMaxCdf = 1024;
 constexpr int kGuide = 1024;  // entries of each CDF guide table
 constexpr int kGlobalStack = 64;  // minimum traversal stack entries per lane beyond the LDS part
 constexpr int kClaimMax = 2048;   // largest block of rays one traversal wave claims at once
-constexpr int kShadeJobs = 16;    // chunks with at most this many jobs tally per workgroup in LDS
+constexpr int kShadeJobs = 32;    // chunks with at most this many jobs tally per workgroup in LDS
 
 // tally counter slots (u64 each), followed by the energy and angle histograms
 enum TallySlot {
