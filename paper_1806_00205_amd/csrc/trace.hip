@@ -732,7 +732,7 @@ __device__ inline void traverse_body(const TraverseArgs& a) {
           claim = claim > (uint32_t)kClaimMax ? (uint32_t)kClaimMax : claim;
           claim = claim < want ? want : claim;
           if (lane == 0) base = __hip_atomic_fetch_add(gp(a.work), claim, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          base = __shfl(base, 0, 64);
+          base = __builtin_amdgcn_readlane(base, 0);  // lane 0's claim, wave-uniform (scalar registers)
           seen = base + claim;
           if (base + claim >= count) exhausted = true;
           new_hi = base >= count ? base : min(base + claim, count);
@@ -953,7 +953,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     (void)ox;
     (void)oy;
     (void)oz;
-    const int j0 = __shfl(job, 0, 64);
+    const int j0 = __builtin_amdgcn_readlane(job, 0);
     if (base < wg1 && j0 != tag) {  // lane 0 active: the wave has rays this step
       if (tag >= 0) {
         if (shared)
@@ -1074,10 +1074,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
     if (w == 0) {
       const uint32_t v = lane < (uint32_t)wpb ? s_wtot[lane] : 0u;
       const uint32_t inc2 = wave_incl_scan(v, lane);
-      const uint32_t T = __shfl(inc2, 63, 64);
+      const uint32_t T = __builtin_amdgcn_readlane(inc2, 63);
       uint32_t b = 0;
       if (lane == 0 && T) b = __hip_atomic_fetch_add(gp(a.count_out), T, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      b = __shfl(b, 0, 64);
+      b = __builtin_amdgcn_readlane(b, 0);
       if (lane < (uint32_t)wpb) s_wbase[lane] = b + inc2 - v;
     }
     __syncthreads();
