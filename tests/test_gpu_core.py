@@ -519,6 +519,26 @@ def test_batch_equals_single_jobs(ctx, tiny, vaughan):
             assert b[key] == r[key], (key, b[key], r[key])
 
 
+def test_batch_of_many_small_jobs(ctx, tiny, vaughan):
+    """40 small jobs on two scenes fit one chunk that spans more jobs than
+    shading keeps tallies for in LDS: the per-wave tallies and their flushes
+    to each job's global block on every change of job must still give every
+    job the integer tallies of its own trace."""
+    s1 = ctx.load_scene(tiny)
+    s2 = ctx.load_scene(fg.make_grf_foam(12, 0.7, 2.0, seed=5))
+    tid = ctx.load_tables(vaughan)
+    rng = np.random.default_rng(17)
+    jobs = [((s1, s2)[k % 3 == 0], float(rng.uniform(30.0, 1500.0)), float(rng.uniform(-85.0, 85.0)),
+             int(rng.integers(1, 400)), 500 + k) for k in range(40)]
+    outs = ctx.trace_batch(tid, jobs, max_gen=6)
+    assert outs[0]["n_chunks"] == 1
+    for (s, E, th, n, sd), b in zip(jobs, outs):
+        r = ctx.trace(s, tid, E, th, n, seed=sd, max_gen=6)
+        for k in ("n_primaries", "n_rays", "n_escaped", "n_absorbed", "n_truncated", "n_lost", "n_tri_tests",
+                  "n_node_visits", "n_spawned", "e_escaped", "e_deposited"):
+            assert b[k] == r[k], (E, th, n, k, b[k], r[k])
+
+
 def test_errors_are_reported(ctx, vaughan):
     import paper_1806_00205_amd as rt
     m = fg.flat_plane()
