@@ -6,7 +6,7 @@ of the void chord length, ln E and cos(theta) -- to the secondary electron
 yield.  Its training targets are yields traced by the library itself
 (rtmc_trace_batch); its forward and backward passes and AdamW updates run in
 the library's BF16 matrix-core kernels (rtmc_srg_*).  Plain RTMC stays the
-reference: it judges the surrogate on held-out foams and is the fallback for
+reference: it evaluates the surrogate on held-out foams and is the fallback for
 inputs outside the training support.
 
 Command line: ``python -m paper_1806_00205_amd.surrogate --out results.json``.
@@ -178,9 +178,9 @@ def _traced_batches(device, tab, specs, points, batch_foams, pool, max_gen, log,
 
 
 def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primaries=20000,
-                   judge_primaries=100000, steps=4000, seed=0, log=print, sizes=(40, 48, 56), workers=0,
+                   eval_primaries=100000, steps=4000, seed=0, log=print, sizes=(40, 48, 56), workers=0,
                    batch_foams=64, max_gen=6):
-    """Train on RTMC yields of n_train foams, judge on n_test held-out foams."""
+    """Train on RTMC yields of n_train foams, evaluate on n_test held-out foams."""
     rng = np.random.default_rng(seed)
     tab = fg.make_tables("vaughan")
     pool = None
@@ -198,13 +198,13 @@ def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primar
             th = rng.uniform(0.0, 80.0, size=points_per_foam)
             tp.append([(e, t, train_primaries, int(rng.integers(1, 2 ** 62))) for e, t in zip(E, th)])
         # held-out foams: the 5 x 5 grid
-        jp = [[(e, t, judge_primaries, int(rng.integers(1, 2 ** 62))) for e in GRID_E for t in GRID_THETA]
+        jp = [[(e, t, eval_primaries, int(rng.integers(1, 2 ** 62))) for e in GRID_E for t in GRID_THETA]
               for _ in range(n_test)]
         train, t_rtmc, t_gen, prim = _traced_batches(ctx.device, tab, train_specs, lambda i: tp[i], batch_foams,
                                                      pool, max_gen, log, "training foams")
         log(f"[srg] {len(train)} training yields traced in {t_rtmc:.2f} s ({prim / t_rtmc:.3g} primaries/s); "
             f"foams generated in {t_gen:.1f} s")
-        test, t_judge, t_gen2, prim_t = _traced_batches(ctx.device, tab, test_specs, lambda i: jp[i], batch_foams,
+        test, t_eval, t_gen2, prim_t = _traced_batches(ctx.device, tab, test_specs, lambda i: jp[i], batch_foams,
                                                         pool, max_gen, log, "held-out foams")
     finally:
         if pool is not None:
@@ -245,24 +245,24 @@ def run_experiment(ctx, n_train=256, points_per_foam=64, n_test=64, train_primar
     blind = y_train[nn].mean(axis=1)
     blind_mae = float(np.abs(blind - y_test).mean())
     # RTMC cost of one yield at the surrogate's error: primaries for sigma = MAE
-    sd_pp = float(np.median(s_test * math.sqrt(judge_primaries)))
+    sd_pp = float(np.median(s_test * math.sqrt(eval_primaries)))
     mae = float(err.mean())
     n_matched = (sd_pp / mae) ** 2
-    rtmc_rate = prim_t / t_judge
+    rtmc_rate = prim_t / t_eval
     rtmc_yield_s = rtmc_rate / n_matched
     out = {
         "n_train_foams": n_train, "train_yields": len(train), "train_primaries_per_yield": train_primaries,
         "foam_grids": list(sizes),
-        "n_test_foams": n_test, "test_points": len(test), "judge_primaries_per_yield": judge_primaries,
+        "n_test_foams": n_test, "test_points": len(test), "eval_primaries_per_yield": eval_primaries,
         "mae": mae, "p95_abs_err": float(np.quantile(err, 0.95)), "max_abs_err": float(err.max()),
         "foam_blind_mae": blind_mae,
         "mae_in_support": float(err[ok].mean()) if ok.any() else None, "in_support_frac": float(ok.mean()),
-        "judge_sigma_median": float(np.median(s_test)),
+        "eval_sigma_median": float(np.median(s_test)),
         "train_sigma_median": float(np.median([r[4] for r in train])),
         "mae_by_grid": {str(n): float(err[np.repeat(np.array(test_grid) == n, 25)].mean())
                         for n in sorted(set(test_grid))},
         "final_loss": losses[-1][1], "train_seconds": t_train, "gen_seconds": t_gen + t_gen2,
-        "rtmc_train_seconds": t_rtmc, "rtmc_judge_seconds": t_judge,
+        "rtmc_train_seconds": t_rtmc, "rtmc_eval_seconds": t_eval,
         "surrogate_queries_per_s": 1e6 / t_q, "rtmc_primaries_per_s": rtmc_rate,
         "rtmc_primaries_for_matched_error": n_matched, "rtmc_yields_per_s_matched_error": rtmc_yield_s,
         "gain": (1e6 / t_q) / rtmc_yield_s,
@@ -280,7 +280,7 @@ def main():
     ap.add_argument("--test-foams", type=int, default=64)
     ap.add_argument("--steps", type=int, default=4000)
     ap.add_argument("--train-primaries", type=int, default=100000)
-    ap.add_argument("--judge-primaries", type=int, default=1000000)
+    ap.add_argument("--eval-primaries", type=int, default=1000000)
     ap.add_argument("--sizes", default="64,96,128,192", help="foam grids (voxels per side)")
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--batch-foams", type=int, default=32)
@@ -289,7 +289,7 @@ def main():
 
     ctx = rt.Context(0)
     res, _ = run_experiment(ctx, n_train=args.train_foams, points_per_foam=args.points, n_test=args.test_foams,
-                            train_primaries=args.train_primaries, judge_primaries=args.judge_primaries,
+                            train_primaries=args.train_primaries, eval_primaries=args.eval_primaries,
                             steps=args.steps, sizes=tuple(int(x) for x in args.sizes.split(",")),
                             workers=args.workers, batch_foams=args.batch_foams,
                             log=lambda m: print(m, flush=True))

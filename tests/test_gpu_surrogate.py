@@ -148,7 +148,7 @@ def test_surrogate_gains_over_rtmc_on_held_out_foams(ctx):
     effect, and (b) far faster than RTMC itself at the same error."""
     from paper_1806_00205_amd.surrogate import run_experiment
     out, _ = run_experiment(ctx, n_train=96, points_per_foam=32, n_test=16, train_primaries=20000,
-                            judge_primaries=100000, steps=2000, seed=5, log=lambda *a: None, sizes=(24, 32, 40),
+                            eval_primaries=100000, steps=2000, seed=5, log=lambda *a: None, sizes=(24, 32, 40),
                             workers=0, batch_foams=32)
     print(f"held-out MAE {out['mae']:.4f}, foam-blind MAE {out['foam_blind_mae']:.4f}, gain {out['gain']:.3g}")
     # observed: MAE 0.046 against 0.100 foam-blind, gain about 200 (the full-size

@@ -1,7 +1,7 @@
 """The learned surrogate, trained on RTMC yields, against RTMC on held-out foams.
 
 Reduced scale (the full experiment -- 1024 training foams, 256 held-out foams
-judged at 1e5 primaries per point -- is `python -m paper_1806_00205_amd.surrogate`).
+evaluated at 1e5 primaries per point -- is `python -m paper_1806_00205_amd.surrogate`).
 """
 import math
 
@@ -22,7 +22,7 @@ def ctx():
 def test_surrogate_beats_rtmc_at_matched_error(ctx):
     from paper_1806_00205_amd.surrogate import run_experiment
     res, model = run_experiment(ctx, n_train=160, points_per_foam=64, n_test=24, train_primaries=20000,
-                                judge_primaries=50000, steps=3000, seed=1, log=lambda s: None)
+                                eval_primaries=50000, steps=3000, seed=1, log=lambda s: None)
     # held-out foams never seen in training: absolute yield error
     assert res["mae"] <= 0.03, res
     # what the network gains over tracing at the same error
