@@ -49,3 +49,15 @@ def test_product_does_not_import_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "import oracle" not in text and "from oracle" not in text, f
                 assert "rtmc_oracle" not in text and "liboracle" not in text, f
+
+
+def test_committed_traffic_counters_match_the_kernel_sources():
+    """The traffic figure bench.py reports comes from a committed counter
+    summary keyed by a hash of the traversal kernel's sources: it must belong
+    to the kernel as it stands (else the figure would be reported as null)."""
+    import sys
+    sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+    import bench
+    t = bench.load_traffic("c1")
+    assert t is not None, "profiles/k_traverse_c1_traffic.json was measured on other kernel sources"
+    assert t["kernel"] == "k_traverse" and 0.0 < t["fetch_plus_write_bytes_per_alg_byte"] < 2.0
