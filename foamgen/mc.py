@@ -162,6 +162,9 @@ def _build_table():
 CASE_TRIS, CASE_COUNT = _build_table()
 
 
+_T_EDGE = 2.0 ** -12  # smallest distance of a vertex from the ends of its edge, in voxels
+
+
 def marching_cubes_periodic(field: np.ndarray, tau: float):
     """Extract the surface ``field == tau`` (solid where ``field >= tau``).
 
@@ -216,7 +219,11 @@ def marching_cubes_periodic(field: np.ndarray, tau: float):
     z1 = uz + step[:, 2]
     f1 = f[x1 % nx, y1 % ny, z1]
     t = (tau - f0) / (f1 - f0)
-    t = np.clip(t, 0.0, 1.0)
+    # keep every vertex strictly inside its edge after rounding to float32
+    # (exact for lattice coordinates below 2048): a crossing that rounded onto
+    # a lattice corner could put a triangle into the plane of a cube face,
+    # and on the periodic boundary that plane is a face of the cell
+    t = np.clip(t, _T_EDGE, 1.0 - _T_EDGE)
     pos = np.stack([uxx, uy, uz], axis=1).astype(np.float64) + step * t[:, None]
     verts = pos.astype(np.float32)
     canon = (((uxx % nx) * ny + (uy % ny)) * nz + uz) * 3 + uax

@@ -53,7 +53,7 @@
  *   - a ray of generation max_gen that hits is absorbed without emission.
  *   - primaries start at a uniform point of the top face z_max; azimuth
  *     uniform; theta fixed, or uniform in [0, |theta|] when theta < 0.
- *   - absorption depth (section 3.3, penetration profile): every ray of
+ *   - absorption depth (section 3.2, Fig. pen, penetration profile): every ray of
  *     any generation that ends on a surface (triangle or substrate) is one
  *     absorption event at depth (z_max - z) / (z_max - z_min) in [0, 1].
  *   - random numbers: Philox4x32-10 (Salmon et al., SC'11), key = seed,
@@ -160,7 +160,8 @@ static double norm3(const double a[3]) { return sqrt(dot3(a, a)); }
 
 /* Promote the float mesh to FP64 and drop triangles whose normal s is exactly
  * zero (no intersection test can accept them).  Returns ORC_EINVAL on bad
- * indices, non-finite coordinates or vertices outside the box. */
+ * indices, non-finite coordinates, vertices outside the box or a triangle
+ * lying in a face of the cell. */
 static int mesh_build(omesh* m, const float* verts, int64_t nv, const int32_t* tris, int64_t nt,
                       const double lo[3], const double hi[3], uint32_t flags) {
   memset(m, 0, sizeof(*m));
@@ -199,6 +200,18 @@ static int mesh_build(omesh* m, const float* verts, int64_t nv, const int32_t* t
     if (s[0] == 0.0 && s[1] == 0.0 && s[2] == 0.0) {
       m->dropped++;
       continue;
+    }
+    /* a surface lying in a face of the cell would be met exactly where the
+       ray leaves the cell (periodic re-entry, the substrate plane, escape),
+       and which of the two comes first is a matter of rounding: rejected */
+    for (int a = 0; a < 3; ++a) {
+      const int on_lo = T.v0[a] == lo[a] && T.v1[a] == lo[a] && T.v2[a] == lo[a];
+      const int on_hi = T.v0[a] == hi[a] && T.v1[a] == hi[a] && T.v2[a] == hi[a];
+      if (on_lo || on_hi) {
+        free(m->t);
+        m->t = NULL;
+        return ORC_EINVAL;
+      }
     }
     T.id = (int32_t)j;
     m->t[m->n++] = T;
@@ -596,7 +609,7 @@ int orc_trace(const orc_mesh_in* mi, const orc_tables_in* ti, const orc_job* job
         if (p.kind == OUT_SUBSTRATE) l_sub++;
         if (NZ) {
           /* the ray ends on a surface: its depth below the top of the cell,
-             as a fraction of the cell height (section 3.3, penetration) */
+             as a fraction of the cell height (section 3.2, Fig. pen, penetration) */
           int zb = (int)floor((m.hi[2] - p.P[2]) / (m.hi[2] - m.lo[2]) * NZ);
           if (zb < 0) zb = 0;
           if (zb > NZ - 1) zb = NZ - 1;

@@ -127,6 +127,43 @@ def pin_paper_slot(o):
     return abs(est - p2) <= 4.0 * math.sqrt(p2 * (1 - p2) / n)
 
 
+def pin_cutoff(o):
+    from tests.test_oracle_pins import _cutoff_slot, _slot_one_bounce
+    for E0 in (5.0, 10.0):
+        r = o.trace(fg.flat_plane(), fg.make_tables("constant", const=1.0, Ec=10.0), E0, 0.0, 500, seed=3)
+        if r["n_escaped"] != 0:
+            return False
+    n = 40000
+    p = _slot_one_bounce()
+    return abs(_cutoff_slot(o, n, max_gen=6)["yield"] - p) <= 3.0 * math.sqrt(p * (1 - p) / n)
+
+
+def pin_sigma(o):
+    tab = fg.make_tables("vaughan")
+    n = 40000
+    for E, th in ((500.0, 0.0), (60.0, 80.0)):
+        r = o.trace(fg.flat_plane(), tab, E, th, n, seed=11, max_gen=6)
+        ref = float(fg.bilinear_reference(tab, E, th))
+        f = ref - math.floor(ref)
+        exact = math.sqrt(f * (1 - f) / n)
+        if abs(r["yield_sigma"] - exact) > 0.03 * exact:
+            return False
+    return True
+
+
+def pin_substrate(o):
+    from tests.test_oracle_pins import _empty_substrate_cell
+    tab = fg.make_tables("vaughan")
+    n = 20000
+    for E, th in ((500.0, 0.0), (100.0, 50.0)):
+        r = o.trace(_empty_substrate_cell(), tab, E, th, n, seed=13, max_gen=6)
+        ref = float(fg.bilinear_reference(tab, E, th))
+        f = ref - math.floor(ref)
+        if abs(r["yield"] - ref) > 3.0 * math.sqrt(f * (1 - f) / n):
+            return False
+    return True
+
+
 MUTANTS = [
     ("cull the wrong side",
      "if (det <= DET_EPS * norm3(L1) * norm3(L2) * dn) continue;",
@@ -164,6 +201,17 @@ MUTANTS = [
      "s2 = 1.0 - xi_pair;", "s2 = xi_pair;", pin_paper_slot),
     ("paper rule: lone daughter's energy from the spectrum",
      "Ed = es;\n", "Ed = tab_cdf_inv(&T, u[0] * tab_cdf(&T, Eav));\n", pin_paper_lone),
+    ("emission cut-off ignored",
+     "if (ray.E <= T.Ec) {", "if (ray.E <= 0.0) {", pin_cutoff),
+    ("emission cut-off exclusive (a ray at E_c still emits)",
+     "if (ray.E <= T.Ec) {", "if (ray.E < T.Ec) {", pin_cutoff),
+    ("standard error without the 1 / N",
+     "res->yield_sigma = sqrt(var / N);", "res->yield_sigma = sqrt(var);", pin_sigma),
+    ("variance without the squared mean",
+     "double var = N > 1 ? (g_c2 - N * mean * mean) / (N - 1.0) : 0.0;",
+     "double var = N > 1 ? g_c2 / (N - 1.0) : 0.0;", pin_sigma),
+    ("substrate normal pointing down",
+     "        r->n[2] = 1.0;\n", "        r->n[2] = -1.0;\n", pin_substrate),
 ]
 
 

@@ -302,3 +302,105 @@ def test_absorption_depth_in_a_slot(oracle_lib):
     z = r["z_hist"]
     assert z.sum() == n and z[2] + z[5] == n
     assert abs(z[2] / n - 1 / 3) <= 4 * math.sqrt(2 / 9 / n)
+
+
+# --------------------------------------------------------------- emission cut-off, standard error, substrate
+
+def test_no_emission_at_or_below_the_cutoff(oracle_lib):
+    """A ray whose energy is at or below E_c emits nothing when it hits
+    (section 2.2).  On a flat plane with a yield of 1 everywhere, primaries at
+    and below E_c are absorbed and leave their whole energy; just above E_c
+    every primary emits its one daughter, which escapes."""
+    n = 2000
+    for E0 in (5.0, 10.0):
+        tab = fg.make_tables("constant", const=1.0, Ec=10.0)
+        r = oracle_lib.trace(fg.flat_plane(), tab, E0, 0.0, n, seed=3, per_primary=True)
+        assert r["n_escaped"] == 0 and r["yield"] == 0.0
+        assert r["n_rays"] == r["n_absorbed"] == n
+        assert np.all(r["per_primary"]["e_dep"] == E0)
+    r = oracle_lib.trace(fg.flat_plane(), fg.make_tables("constant", const=1.0, Ec=10.0), 10.5, 0.0, n, seed=3)
+    assert r["n_escaped"] == n
+
+
+def _cutoff_slot(o, n, max_gen, seed=23):
+    # one daughter of 100 eV per emitting hit (the paper's rule with a
+    # constant E_SEE), E_c = 200 eV: only the 500 eV primaries can emit
+    tab = fg.make_tables("constant", const=1.0, emission="paper", esee_const=100.0, Ec=200.0)
+    return o.trace(fg.trench(w=2.0, h=3.0, tw=1.0), tab, 500.0, 0.0, n, seed=seed, max_gen=max_gen)
+
+
+def _slot_one_bounce(w=2.0, h=3.0, tw=1.0):
+    # primaries at normal incidence land on a wall top (fraction tw / (w + tw),
+    # its daughter escapes) or on the floor (its daughter escapes with the
+    # crossed-string view factor of the opening)
+    F = math.sqrt(1 + (h / w) ** 2) - h / w
+    return tw / (w + tw) + w / (w + tw) * F
+
+
+def test_daughters_below_the_cutoff_do_not_reemit(oracle_lib):
+    """In a slot, daughters below E_c that hit a wall are absorbed however
+    deep the cascade may go: the yield is the one-bounce closed form."""
+    n = 40000
+    p = _slot_one_bounce()
+    r = _cutoff_slot(oracle_lib, n, max_gen=6)
+    assert abs(r["yield"] - p) <= 3.0 * math.sqrt(p * (1 - p) / n), (r["yield"], p)
+    assert r["n_truncated"] == 0
+
+
+@pytest.mark.parametrize("E,theta", FLAT_CASES)
+def test_yield_sigma_is_the_standard_error(oracle_lib, E, theta):
+    """On a flat plane every daughter escapes, so a primary's escape count is
+    floor(delta), or floor(delta) + 1 with probability f = frac(delta): the
+    standard error of the yield over n primaries is sqrt(f (1 - f) / n)."""
+    tab = fg.make_tables("vaughan")
+    n = 40000
+    r = oracle_lib.trace(fg.flat_plane(), tab, E, theta, n, seed=11, max_gen=6)
+    ref = float(fg.bilinear_reference(tab, E, theta))
+    f = ref - math.floor(ref)
+    exact = math.sqrt(f * (1 - f) / n)
+    # the sample standard deviation of n = 40000 two-valued counts is within
+    # 0.5 % (one standard deviation) of the exact one at these f
+    assert abs(r["yield_sigma"] - exact) <= 0.03 * exact, (r["yield_sigma"], exact)
+
+
+def _empty_substrate_cell(L=4.0, H=4.0):
+    return fg.Mesh(np.zeros((0, 3), np.float32), np.zeros((0, 3), np.int32), (0.0, 0.0, 0.0), (L, L, H),
+                   fg.PERIODIC_XY | fg.SUBSTRATE, dict(kind="substrate only"))
+
+
+@pytest.mark.parametrize("E,theta", [(500.0, 0.0), (100.0, 50.0)])
+def test_substrate_plane_is_a_flat_surface(oracle_lib, E, theta):
+    """The substrate (section 2.2) is an emitting plane at z_min with normal
+    +z: alone in a periodic cell it is a flat surface, so the yield is the
+    table value at the primary's angle and the escape angles follow the
+    cosine law."""
+    tab = fg.make_tables("vaughan")
+    n = 40000
+    r = oracle_lib.trace(_empty_substrate_cell(), tab, E, theta, n, seed=13, max_gen=6, n_abins=90)
+    ref = float(fg.bilinear_reference(tab, E, theta))
+    f = ref - math.floor(ref)
+    assert abs(r["yield"] - ref) <= 3.0 * math.sqrt(f * (1 - f) / n), (r["yield"], ref)
+    assert r["n_substrate"] == n and r["n_lost"] == 0
+    b = np.deg2rad(np.linspace(0, 90, 91))
+    m = r["n_escaped"]
+    emp = np.concatenate([[0], np.cumsum(r["a_hist"])]) / m
+    assert np.max(np.abs(emp - np.sin(b) ** 2)) < 1.63 / math.sqrt(m)
+
+
+def test_surfaces_in_a_cell_face_are_rejected(oracle_lib):
+    """A triangle lying in a face of the cell would meet the ray exactly where
+    it leaves the cell; such meshes are refused.  A triangle touching a face
+    along an edge is fine."""
+    with pytest.raises(ValueError):
+        oracle_lib.mesh_dropped(fg.flat_plane(z0=0.0))  # in the bottom face
+    v = np.array([[0, 0, 1], [0, 2, 1], [0, 0, 3], [2, 2, 4], [3, 2, 4], [2, 3, 4]], dtype=np.float32)
+    box = ((0.0, 0.0, 0.0), (4.0, 4.0, 4.0))
+    for tri in ([0, 1, 2], [3, 4, 5]):  # in the x = 0 face; in the top face
+        m = fg.Mesh(v, np.array([tri], dtype=np.int32), *box, fg.PERIODIC_XY, {})
+        with pytest.raises(ValueError):
+            oracle_lib.mesh_dropped(m)
+        with pytest.raises(ValueError):
+            oracle_lib.first_hit(m, np.array([[1.0, 1.0, 3.5, 0.0, 0.0, -1.0]]))
+    edge = fg.Mesh(np.array([[0, 0, 1], [0, 2, 1], [1, 0, 3]], dtype=np.float32), np.array([[0, 1, 2]], np.int32),
+                   *box, fg.PERIODIC_XY, {})
+    assert oracle_lib.mesh_dropped(edge) == 0
