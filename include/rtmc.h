@@ -113,7 +113,7 @@ typedef struct {
   uint64_t* e_hist;      /* host, n_ebins counts, may be NULL */
   uint64_t* a_hist;      /* host, n_abins counts, may be NULL */
   uint32_t* pp_escaped;  /* device, n_primaries escape counts indexed by primary id - pid0, may be NULL */
-  int32_t n_zbins;       /* absorption-depth histogram (section 3.3): every ray of any generation that
+  int32_t n_zbins;       /* absorption-depth histogram (section 3.2, Fig. pen): every ray of any generation that
                             ends on a surface counts once at depth (z_max - z) / (z_max - z_min), in
                             n_zbins bins over [0, 1]; 0 means none; <= 256 */
   uint64_t* z_hist;      /* host, n_zbins counts, may be NULL */
@@ -153,13 +153,16 @@ typedef struct {
   double build_ms;
 } rtmc_scene_info;
 
-/* One (scene, energy, angle) point of a batched trace. */
+/* One (scene, energy, angle) point of a batched trace.  Its primaries have
+ * ids 0 .. n_primaries - 1 and the random numbers of rtmc_trace with the same
+ * seed, so a job reproduces the single trace of the same point. */
 typedef struct {
   int32_t scene_id;
   double E_eV;
   double theta_deg;     /* >= 0 fixed incidence; < 0 uniform in [0, -theta_deg] */
   uint64_t n_primaries; /* < 2^32 */
   uint64_t seed;
+  uint32_t* pp_escaped; /* device, n_primaries escape counts indexed by primary id, may be NULL */
 } rtmc_job;
 
 /* Create a context on HIP device `device`.  alloc may be NULL (hipMalloc);
@@ -182,7 +185,11 @@ rtmc_status rtmc_set_stream(rtmc_ctx* ctx, void* hip_stream);
  *   primaries start on z = box_hi[2]; box_lo[2] is the substrate plane.
  *   Every vertex must lie inside the box and be finite; every index in
  *   [0, n_verts).  Triangles whose normal is exactly zero are dropped and
- *   counted.  Returns the new scene id in *scene_id. */
+ *   counted.  A triangle lying in a face of the box (all three vertices on
+ *   box_lo[a], or all on box_hi[a], for some axis a) is refused with
+ *   RTMC_EINVAL: a ray would meet it exactly where it leaves the cell, and
+ *   which of the two comes first would be decided by rounding.  Returns the
+ *   new scene id in *scene_id. */
 rtmc_status rtmc_load_mesh(rtmc_ctx* ctx, const float* verts, int64_t n_verts, const int32_t* tris,
                            int64_t n_tris, const double box_lo[3], const double box_hi[3], uint32_t flags,
                            int32_t* scene_id);
@@ -243,7 +250,9 @@ rtmc_status rtmc_trace(rtmc_ctx* ctx, int32_t scene_id, int32_t table_id, double
 rtmc_status rtmc_trace_batch(rtmc_ctx* ctx, int32_t table_id, const rtmc_job* jobs, int64_t n_jobs,
                              int32_t max_gen, rtmc_result* outs);
 
-/* First surface reached by each ray, following periodic re-entry.
+/* First surface reached by each ray, following periodic re-entry: the
+ * closest front-facing element along the ray (the intersection checks of
+ * section 2.1), or the substrate, or escape (section 2.2).
  *   rays: device float [n * 6] (origin xyz, unit direction xyz);
  *   tri_out: device int32 [n], the caller's triangle index or an RTMC_HIT_ code;
  *   t_out: device float [n], path length over all periodic segments.

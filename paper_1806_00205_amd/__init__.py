@@ -85,7 +85,7 @@ class SceneInfo(C.Structure):
 
 class Job(C.Structure):
     _fields_ = [("scene_id", C.c_int32), ("E_eV", C.c_double), ("theta_deg", C.c_double),
-                ("n_primaries", C.c_uint64), ("seed", C.c_uint64)]
+                ("n_primaries", C.c_uint64), ("seed", C.c_uint64), ("pp_escaped", C.c_void_p)]
 
 
 _lib = None
@@ -277,10 +277,20 @@ class Context:
             d["z_hist"] = zh
         return d
 
-    def trace_batch(self, table: int, jobs, max_gen: int = 6) -> list:
-        """jobs: iterable of (scene, E, theta, n_primaries, seed)."""
+    def trace_batch(self, table: int, jobs, max_gen: int = 6, per_primary=None) -> list:
+        """jobs: iterable of (scene, E, theta, n_primaries, seed).  per_primary,
+        if given, is a list with one entry per job: None or a uint32/int32
+        torch tensor of n_primaries on the GPU for that job's escape counts."""
         jl = list(jobs)
-        arr = (Job * len(jl))(*[Job(int(s), float(E), float(th), int(n), int(sd)) for s, E, th, n, sd in jl])
+        pps = list(per_primary) if per_primary is not None else [None] * len(jl)
+        if len(pps) != len(jl):
+            raise ValueError("per_primary needs one entry per job")
+        for (s, E, th, n, sd), p in zip(jl, pps):
+            if p is not None:
+                assert p.is_cuda and p.is_contiguous() and p.numel() >= int(n) and p.element_size() == 4
+        arr = (Job * len(jl))(*[Job(int(s), float(E), float(th), int(n), int(sd),
+                                    p.data_ptr() if p is not None else None)
+                                for (s, E, th, n, sd), p in zip(jl, pps)])
         outs = (Result * len(jl))()
         self._chk(self.lib.rtmc_trace_batch(self.h, table, arr, len(jl), int(max_gen), outs))
         return [o.to_dict() for o in outs]

@@ -306,7 +306,11 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->counters.p), 0u, (size_t)ncnt * n_chunks, s));
   HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->err_word.p), 0u, 1, s));
 
-  const uint32_t qcap = (uint32_t)std::min<uint64_t>((uint64_t)chunk * tb.max_d, c->qcap);
+  // the whole allocated queue is the limit: after an overflow the chunk is
+  // halved while the queue keeps its length, so every retry doubles the
+  // room per primary
+  const uint32_t qcap = c->qcap;
+  (void)chunk;
   RayQueue q[2];
   for (int i = 0; i < 2; ++i) {
     float* f = reinterpret_cast<float*>(c->queue[i].p);
@@ -556,9 +560,13 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
     std::memcpy(&errw, c->pin, 4);
     if (errw & 2u) return fail(c, RTMC_EOVERFLOW, "traversal stack overflow (BVH deeper than the stack)");
     if (errw & 1u) {
-      if (cfg.chunk <= 1)
+      // a generation outgrew the queue: trace again with chunks half the size
+      // of the largest one just planned (the queue keeps its length)
+      uint32_t largest = 1;
+      for (const ChunkPlan& p : plan_chunks(jobs, (uint32_t)cfg.chunk)) largest = std::max(largest, p.n);
+      if (largest <= 1)
         return fail(c, RTMC_EOVERFLOW, "one primary's ray tree does not fit the daughter queue");
-      cfg.chunk = std::max(1, cfg.chunk / 2);
+      cfg.chunk = (int32_t)(largest / 2);
       continue;
     }
     out.tally.resize(tw * jobs.size());
@@ -733,6 +741,16 @@ rtmc_status rtmc_load_mesh(rtmc_ctx* c, const float* verts, int64_t n_verts, con
     if (nx == 0.0 && ny == 0.0 && nz == 0.0) {
       s.dropped++;
       continue;
+    }
+    // a surface in a face of the cell would be met exactly where a ray leaves
+    // the cell (re-entry, substrate, escape), and which comes first would be
+    // decided by rounding
+    for (int a = 0; a < 3; ++a) {
+      const bool on_lo = v[0][a] == box_lo[a] && v[1][a] == box_lo[a] && v[2][a] == box_lo[a];
+      const bool on_hi = v[0][a] == box_hi[a] && v[1][a] == box_hi[a] && v[2][a] == box_hi[a];
+      if (on_lo || on_hi)
+        return fail(c, RTMC_EINVAL, "triangle %lld lies in the %s face of the cell on axis %d", (long long)j,
+                    on_lo ? "lower" : "upper", a);
     }
     for (int k = 0; k < 3; ++k) {
       packed.push_back((float)v[k][0]);
@@ -1043,7 +1061,7 @@ rtmc_status rtmc_trace_batch(rtmc_ctx* c, int32_t table_id, const rtmc_job* jobs
     if (!(j.E_eV > 0.0) || !std::isfinite(j.E_eV) || !(std::fabs(j.theta_deg) <= 90.0) ||
         j.n_primaries > 0xFFFFFFFFull)
       return fail(c, RTMC_EINVAL, "job %lld: bad energy, angle or size", (long long)i);
-    hj.push_back({j.scene_id, j.E_eV, j.theta_deg, j.n_primaries, j.seed, 0, nullptr});
+    hj.push_back({j.scene_id, j.E_eV, j.theta_deg, j.n_primaries, j.seed, 0, j.pp_escaped});
     total += j.n_primaries;
   }
   HIPCHK(c, hipSetDevice(c->device));

@@ -371,11 +371,11 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
 // binary node gets its 4-wide node (one thread per node), so a slot may link
 // to a node of any depth; traversal reaches only the ones it links to.
 //
-// A node is 64 bytes (four float4): the origin o of the union box and three
-// power-of-two scales s = 2^e (e biased by 127 in bytes 0..2 of word 3);
-// the four child links (kEmpty: unused slot); the child boxes quantized to
-// bytes, lo_x[4] lo_y[4] lo_z[4] hi_x[4] in float4 2 and hi_y[4] hi_z[4] in
-// float4 3.  A child's box decodes as fmaf(q, s, o) per bound, and the
+// A node is 64 bytes (four float4): the origin o of the union box in words
+// 0-2 and the three per-axis power-of-two scales s as floats in words 3, 14
+// and 15; the four child links in words 4-7 (kEmpty: unused slot); the child
+// boxes quantized to bytes, lo_x[4] lo_y[4] lo_z[4] hi_x[4] in words 8-11
+// and hi_y[4] hi_z[4] in words 12-13.  A child's box decodes as fmaf(q, s, o) per bound, and the
 // builder moves each code outwards until that decoded box contains the exact
 // one; traversal's slab distances to the decoded planes carry a margin that
 // covers their own rounding, so traversal stays conservative.

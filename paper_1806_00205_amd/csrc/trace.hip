@@ -1036,7 +1036,7 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
         }
         if (a.n_zbins > 0) {
           // the ray ends on a surface: its depth below the top of the cell, as
-          // a fraction of the cell height (section 3.3, penetration profile)
+          // a fraction of the cell height (section 3.2, Fig. pen, penetration profile)
           int zb = (int)floorf((J.sc.hi[2] - pz) / (J.sc.hi[2] - J.sc.lo[2]) * (float)a.n_zbins);
           zb = min(max(zb, 0), a.n_zbins - 1);
           if (shared)

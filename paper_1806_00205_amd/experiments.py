@@ -5,7 +5,7 @@
   0.15, 0.20, 0.25 (the paper's v_f = 1, 2.25, 4, 6.25 % as (t/l)^2), with
   the paper's tungsten fits and emission rule.
 * ``penetration``: the absorption-depth profile of a 4 % volume-fraction foam
-  at 100 eV for normal and random incidence (section 3.3, Fig. pen): every
+  at 100 eV for normal and random incidence (section 3.2, Fig. pen): every
   ray of any generation that ends on a surface counts at its depth below the
   top of the cell.
 

@@ -155,7 +155,7 @@ def test_cage_parity(ctx, torch, oracle_lib, a, kind):
 
 def test_absorption_depth_flat_and_slot(ctx):
     """Depth histogram: the flat plane's single depth, and the slot's wall-top /
-    floor split at normal incidence (section 3.3)."""
+    floor split at normal incidence (section 3.2, Fig. pen)."""
     n = 3000
     sid = ctx.load_scene(fg.flat_plane(L=4.0, z0=1.0, height=4.0))
     for const in (0.0, 2.0):
