@@ -260,6 +260,26 @@ rtmc_status rtmc_trace_batch(rtmc_ctx* ctx, int32_t table_id, const rtmc_job* jo
 rtmc_status rtmc_first_hit(rtmc_ctx* ctx, int32_t scene_id, const float* rays, int64_t n, int32_t* tri_out,
                            float* t_out);
 
+/* rtmc_first_hit for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, hosts that forbid allocation): the
+ * same kernels and results as rtmc_first_hit, with every scratch buffer in a
+ * fixed 32 MiB array that the library's code object holds on each GPU it
+ * runs on, from the first rtmc_create on that GPU until the process ends.
+ * The call allocates nothing and does not synchronise: it returns once its
+ * kernels are enqueued on the context stream.
+ *   rays, tri_out, t_out: as for rtmc_first_hit (device memory, caller-owned).
+ *   n: at most 524288 (2^19) rays per call, else RTMC_EINVAL; larger sets
+ *      are traced in several calls.
+ *   The BVH's global traversal stack lives in the same array, so fewer
+ *   persistent workgroups may be launched than the launch shape asks for;
+ *   a tree too deep for it is refused with RTMC_EINVAL.
+ *   Every call on one GPU uses that GPU's one array: calls whose work
+ *   overlaps on the device (other streams, other contexts, other host
+ *   threads) race and give wrong results; calls on one stream are ordered
+ *   and safe. */
+rtmc_status rtmc_first_hit_noalloc(rtmc_ctx* ctx, int32_t scene_id, const float* rays, int64_t n,
+                                   int32_t* tri_out, float* t_out);
+
 /* In-place ascending sort of (key, value) pairs by the low key_bits bits of
  * the keys (device radix sort used by the BVH builder; stable).
  *   keys: device uint64 [n]; vals: device uint32 [n]; 1 <= key_bits <= 64.

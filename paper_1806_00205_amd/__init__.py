@@ -30,7 +30,7 @@ _STATUS = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ESTATE", -5:
 EXPORTS = [
     "rtmc_create", "rtmc_destroy", "rtmc_last_error", "rtmc_set_stream", "rtmc_load_mesh", "rtmc_build_bvh",
     "rtmc_get_scene_info", "rtmc_bvh_download", "rtmc_bvh_download_wide", "rtmc_load_tables", "rtmc_trace", "rtmc_trace_batch",
-    "rtmc_first_hit", "rtmc_sort_pairs_u64", "rtmc_set_launch", "rtmc_get_launch", "rtmc_autotune",
+    "rtmc_first_hit", "rtmc_first_hit_noalloc", "rtmc_sort_pairs_u64", "rtmc_set_launch", "rtmc_get_launch", "rtmc_autotune",
     "rtmc_copy_probe", "rtmc_srg_create", "rtmc_srg_param_count", "rtmc_srg_get_params", "rtmc_srg_set_params",
     "rtmc_srg_gradient", "rtmc_srg_train_step", "rtmc_srg_predict",
 ]
@@ -123,6 +123,7 @@ def load_library(path: str = LIB_PATH):
         "rtmc_trace": ([P, i32, i32, dbl, dbl, u64, u64, C.POINTER(TraceOpts), C.POINTER(Result)], C.c_int),
         "rtmc_trace_batch": ([P, i32, C.POINTER(Job), i64, i32, C.POINTER(Result)], C.c_int),
         "rtmc_first_hit": ([P, i32, P, i64, P, P], C.c_int),
+        "rtmc_first_hit_noalloc": ([P, i32, P, i64, P, P], C.c_int),
         "rtmc_sort_pairs_u64": ([P, P, P, i64, i32], C.c_int),
         "rtmc_set_launch": ([P, C.POINTER(LaunchCfg)], C.c_int),
         "rtmc_get_launch": ([P, C.POINTER(LaunchCfg)], C.c_int),
@@ -305,6 +306,16 @@ class Context:
         self._chk(self.lib.rtmc_first_hit(self.h, scene, C.c_void_p(rays.data_ptr()), n, C.c_void_p(tri.data_ptr()),
                                           C.c_void_p(t.data_ptr())))
         return tri, t
+
+    def first_hit_noalloc(self, scene: int, rays, tri, t):
+        """rtmc_first_hit_noalloc into caller tensors tri (int32) and t
+        (float32) of at least rays.shape[0] entries; asynchronous."""
+        torch = self.torch
+        assert rays.is_cuda and rays.dtype == torch.float32 and rays.is_contiguous() and rays.shape[-1] == 6
+        n = rays.shape[0]
+        assert tri.dtype == torch.int32 and t.dtype == torch.float32 and tri.numel() >= n and t.numel() >= n
+        self._chk(self.lib.rtmc_first_hit_noalloc(self.h, scene, C.c_void_p(rays.data_ptr()), n,
+                                                  C.c_void_p(tri.data_ptr()), C.c_void_p(t.data_ptr())))
 
     def sort_pairs(self, keys, vals, key_bits: int = 64):
         """In-place device radix sort of int64 keys (as uint64 bits) with int32 values."""

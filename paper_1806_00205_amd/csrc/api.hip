@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -58,8 +59,54 @@ struct Tables {
 
 }  // namespace
 
+// ---- scratch memory of the entry points that allocate nothing
+//
+// One array per GPU, in the library's code object: rtmc_first_hit_noalloc
+// keeps its traversal scratch (work counter, error word, job record, hit
+// record streams, global traversal stack) here instead of allocating it.
+// In host code `scratch` only names the symbol; its device address on each
+// GPU is looked up once (rtmc_create) and kept in scratch_dev[].
+namespace {
+constexpr size_t kScratchBytes = (size_t)32 << 20;
+constexpr int64_t kNoAllocMaxRays = (int64_t)1 << 19;
+constexpr size_t kScratchHead = 4096;  // work counter, error word, job record (at byte 256)
+constexpr size_t kScratchStack = kScratchBytes - kScratchHead - 20 * (size_t)kNoAllocMaxRays;
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void* scratch_dev[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static_assert(256 + sizeof(rtmc::DevJob) <= kScratchHead, "job record must fit the scratch head");
+
+// One job record written by the device, so that no host staging buffer is needed.
+__global__ void k_store_job(rtmc::DevJob* dst, rtmc::DevJob v) { *dst = v; }
+
+namespace {
+hipError_t launch_store_job(rtmc::DevJob* dst, const rtmc::DevJob& v, hipStream_t s) {
+  k_store_job<<<1, 1, 0, s>>>(dst, v);
+  return hipGetLastError();
+}
+
+// Device address of this GPU's scratch array (the device must be current).
+hipError_t resolve_scratch(int device, void** out) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(scratch_mu);
+  if (!scratch_dev[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    scratch_dev[device] = p;
+  }
+  *out = scratch_dev[device];
+  return hipSuccess;
+}
+}  // namespace
+
 struct rtmc_ctx {
   int device = 0;
+  void* scratch = nullptr;  // this device's scratch array (rtmc_first_hit_noalloc)
   hipStream_t stream = nullptr;
   hipStream_t gstream = nullptr;  // graph capture / replay
   rtmc_allocator alloc{};
@@ -647,6 +694,10 @@ rtmc_status rtmc_create(rtmc_ctx** out, int device, const rtmc_allocator* alloc,
   }
   c->n_cu = prop.multiProcessorCount;
   c->lds_per_block = prop.sharedMemPerBlock;
+  if (resolve_scratch(device, &c->scratch) != hipSuccess) {
+    rtmc_destroy(c);
+    return RTMC_EDEVICE;
+  }
   *out = c;
   return RTMC_OK;
 }
@@ -1135,6 +1186,62 @@ rtmc_status rtmc_first_hit(rtmc_ctx* c, int32_t scene_id, const float* rays, int
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   dev_free(c, scratch);
   if (e != hipSuccess) return fail(c, RTMC_EDEVICE, "first hit: %s", hipGetErrorString(e));
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_first_hit_noalloc(rtmc_ctx* c, int32_t scene_id, const float* rays, int64_t n, int32_t* tri_out,
+                                   float* t_out) {
+  rtmc_status st = check_scene(c, scene_id, true);
+  if (st) return st;
+  c->err.clear();
+  if (n < 0 || (n > 0 && (!rays || !tri_out || !t_out))) return fail(c, RTMC_EINVAL, "bad ray arrays");
+  if (n > kNoAllocMaxRays)
+    return fail(c, RTMC_EINVAL, "%lld rays exceed the %lld one call without allocation takes", (long long)n,
+                (long long)kNoAllocMaxRays);
+  if (!c->scratch) return fail(c, RTMC_ESTATE, "no scratch memory on device %d", c->device);
+  if (n == 0) return RTMC_OK;
+  HIPCHK(c, hipSetDevice(c->device));
+  const Scene& s = c->scenes[scene_id];
+  const rtmc_launch_cfg& cfg = c->cfg;
+  if (traverse_lds_bytes(cfg.lds_stack, cfg.block) > c->lds_per_block)
+    return fail(c, RTMC_EINVAL, "launch shape needs more LDS than a workgroup has");
+  // global stack entries beyond the LDS part: exactly what the tree can need
+  const int gdepth = std::max(8, stack_need(s.depth) - cfg.lds_stack);
+  const int wpb = cfg.block / 64;
+  const size_t wave_bytes = (size_t)gdepth * 64 * 4;
+  // as many persistent workgroups as the launch shape asks for and the stack region holds
+  const int grid = (int)std::min<size_t>((size_t)grid_of(c, cfg), kScratchStack / (wave_bytes * wpb));
+  if (grid < 1) return fail(c, RTMC_EINVAL, "BVH of depth %d too deep for the scratch stack", s.depth);
+  unsigned char* base = static_cast<unsigned char*>(c->scratch);
+  uint32_t* head = reinterpret_cast<uint32_t*>(base);
+  DevJob* djd = reinterpret_cast<DevJob*>(base + 256);
+  uint32_t* u = reinterpret_cast<uint32_t*>(base + kScratchHead);
+  const size_t M = (size_t)kNoAllocMaxRays;
+  DevJob dj{};
+  dj.sc = dev_scene(s);
+  TraverseArgs ta{};
+  ta.jobs = djd;
+  ta.n_jobs = 1;
+  ta.src = 2;
+  ta.rays = rays;
+  ta.count = (uint32_t)n;
+  ta.hit.code = tri_out;
+  ta.hit.t = t_out;
+  ta.hit.f0 = reinterpret_cast<float*>(u);
+  ta.hit.f1 = reinterpret_cast<float*>(u + M);
+  ta.hit.visits = u + 2 * M;
+  ta.hit.tests = u + 3 * M;
+  ta.hit.wraps = u + 4 * M;
+  ta.work = head;
+  ta.err = head + 1;
+  ta.gstack = u + 5 * M;
+  ta.lds_stack = cfg.lds_stack;
+  ta.gstack_depth = gdepth;
+  ta.refill = cfg.refill;
+  HIPCHK(c, launch_store_job(djd, dj, c->stream));
+  HIPCHK(c, launch_fill_u32(head, 0u, 2, c->stream));
+  HIPCHK(c, launch_traverse(ta, false, cfg.occupancy, grid, cfg.block, c->stream));
+  HIPCHK(c, launch_hit_ids(reinterpret_cast<const float4*>(s.tris.p), tri_out, n, tri_out, c->stream));
   return RTMC_OK;
 }
 
