@@ -117,6 +117,12 @@ typedef struct {
                             ends on a surface counts once at depth (z_max - z) / (z_max - z_min), in
                             n_zbins bins over [0, 1]; 0 means none; <= 256 */
   uint64_t* z_hist;      /* host, n_zbins counts, may be NULL */
+  float* replay;         /* device float [n_replay * 6], may be NULL: the first n_replay rays of generation
+                            replay_gen (daughters as spawned: origin, unit direction; first chunk only, in
+                            queue order, which depends on scheduling) for re-tracing elsewhere */
+  int64_t n_replay;      /* capacity of replay in rays, < 2^32 */
+  int32_t replay_gen;    /* 1 .. max_gen when replay is set */
+  int64_t* n_replay_out; /* host, may be NULL: how many rays were written to replay */
 } rtmc_trace_opts;
 
 typedef struct {
@@ -143,6 +149,8 @@ typedef struct {
   int32_t refill;    /* a wave fetches new rays once this many of its 64 lanes are idle, 1..64 */
   int32_t occupancy; /* traversal kernel build, waves per SIMD (registers capped to fit): 6 or 8;
                         any other value: 7 for one scene, 6 for a batch (the default) */
+  int32_t claim;     /* rays per wave per claim: the largest block of a generation's rays one traversal
+                        wave takes from the shared counter at once, 64..8192; 0 means 2048 */
 } rtmc_launch_cfg;
 
 typedef struct {
@@ -289,8 +297,15 @@ rtmc_status rtmc_sort_pairs_u64(rtmc_ctx* ctx, uint64_t* keys, uint32_t* vals, i
 rtmc_status rtmc_set_launch(rtmc_ctx* ctx, const rtmc_launch_cfg* cfg);
 rtmc_status rtmc_get_launch(rtmc_ctx* ctx, rtmc_launch_cfg* cfg);
 
-/* Time a few launch shapes on a short calibration trace of the scene and
- * keep the fastest (also returned in *best). */
+/* Time launch shapes on a calibration trace of the scene (n_primaries at
+ * E_eV, theta_deg) and keep the fastest, also returned in *best.  Coordinate
+ * search over block size, workgroups per compute unit, LDS stack depth,
+ * refill threshold, kernel build (waves per SIMD), rays per wave per claim
+ * and primaries per chunk (chunks of the calibration trace, at most
+ * n_primaries).  The winner is cached for the process, keyed by the GPU
+ * (architecture, compute units), the scene's size (triangles as a power of
+ * two, BVH depth), the tables' largest yield and the calibration point: a
+ * call with the same key takes the cached shape without timing. */
 rtmc_status rtmc_autotune(rtmc_ctx* ctx, int32_t scene_id, int32_t table_id, double E_eV, double theta_deg,
                           uint64_t n_primaries, rtmc_launch_cfg* best);
 
@@ -321,6 +336,19 @@ rtmc_status rtmc_srg_gradient(rtmc_ctx* ctx, int32_t srg_id, const float* X, con
 /* One AdamW step (beta 0.9 / 0.999, eps 1e-8) on a batch; *loss is the batch loss before the step. */
 rtmc_status rtmc_srg_train_step(rtmc_ctx* ctx, int32_t srg_id, const float* X, const float* y, int64_t batch,
                                 float lr, float weight_decay, float* loss);
+/* A training loop in one call: `steps` AdamW steps (as rtmc_srg_train_step),
+ * step s on a batch of `batch` rows drawn on the device from the n rows of
+ * (X, y), uniformly with replacement (Philox4x32-10, key seed, counter
+ * (row, s, 0, 0)), at learning rate lr[s] (host float [steps]).
+ * use_graph != 0: one step is captured as a HIP graph (again whenever the
+ * arrays, sizes, seed or weight decay change) and replayed `steps` times,
+ * so the loop runs without host round trips; 0: the same launches issued one
+ * by one (identical results).  losses: host float [steps] (each step's batch
+ * loss before its update), may be NULL.  X: device [n, n_in]; y: device [n];
+ * n < 2^32; batch % 32 == 0.  Synchronous. */
+rtmc_status rtmc_srg_train(rtmc_ctx* ctx, int32_t srg_id, const float* X, const float* y, int64_t n, int64_t batch,
+                           int32_t steps, const float* lr, float weight_decay, uint64_t seed, int32_t use_graph,
+                           float* losses);
 /* Predictions for n rows (any n), written to device float y[n]; asynchronous on the context stream.
  * One fused kernel per call: each workgroup runs all layers for 128 rows with
  * the activations held in LDS (BF16 between layers), so the call allocates

@@ -32,7 +32,7 @@ EXPORTS = [
     "rtmc_get_scene_info", "rtmc_bvh_download", "rtmc_bvh_download_wide", "rtmc_load_tables", "rtmc_trace", "rtmc_trace_batch",
     "rtmc_first_hit", "rtmc_first_hit_noalloc", "rtmc_sort_pairs_u64", "rtmc_set_launch", "rtmc_get_launch", "rtmc_autotune",
     "rtmc_copy_probe", "rtmc_srg_create", "rtmc_srg_param_count", "rtmc_srg_get_params", "rtmc_srg_set_params",
-    "rtmc_srg_gradient", "rtmc_srg_train_step", "rtmc_srg_predict",
+    "rtmc_srg_gradient", "rtmc_srg_train_step", "rtmc_srg_train", "rtmc_srg_predict",
 ]
 
 
@@ -56,7 +56,8 @@ class Tables(C.Structure):
 class TraceOpts(C.Structure):
     _fields_ = [("max_gen", C.c_int32), ("n_ebins", C.c_int32), ("n_abins", C.c_int32), ("pid0", C.c_uint64),
                 ("e_hist", C.c_void_p), ("a_hist", C.c_void_p), ("pp_escaped", C.c_void_p), ("n_zbins", C.c_int32),
-                ("z_hist", C.c_void_p)]
+                ("z_hist", C.c_void_p), ("replay", C.c_void_p), ("n_replay", C.c_int64), ("replay_gen", C.c_int32),
+                ("n_replay_out", C.c_void_p)]
 
 
 class Result(C.Structure):
@@ -74,7 +75,7 @@ class Result(C.Structure):
 
 class LaunchCfg(C.Structure):
     _fields_ = [("block", C.c_int32), ("wg_per_cu", C.c_int32), ("lds_stack", C.c_int32), ("chunk", C.c_int32),
-                ("refill", C.c_int32), ("occupancy", C.c_int32)]
+                ("refill", C.c_int32), ("occupancy", C.c_int32), ("claim", C.c_int32)]
 
 
 class SceneInfo(C.Structure):
@@ -135,6 +136,7 @@ def load_library(path: str = LIB_PATH):
         "rtmc_srg_set_params": ([P, i32, P, i64], C.c_int),
         "rtmc_srg_gradient": ([P, i32, P, P, i64, C.POINTER(C.c_float), P], C.c_int),
         "rtmc_srg_train_step": ([P, i32, P, P, i64, C.c_float, C.c_float, C.POINTER(C.c_float)], C.c_int),
+        "rtmc_srg_train": ([P, i32, P, P, i64, i64, i32, P, C.c_float, u64, i32, P], C.c_int),
         "rtmc_srg_predict": ([P, i32, P, i64, P], C.c_int),
     }
     for name, (args, res) in sig.items():
@@ -259,15 +261,23 @@ class Context:
 
     # ---------------------------------------------------------------- tracing
     def trace(self, scene: int, table: int, E: float, theta: float, n_primaries: int, seed: int, max_gen: int = 6,
-              n_ebins: int = 256, n_abins: int = 90, pid0: int = 0, per_primary=None, n_zbins: int = 0) -> dict:
+              n_ebins: int = 256, n_abins: int = 90, pid0: int = 0, per_primary=None, n_zbins: int = 0,
+              replay=None, replay_gen: int = 1) -> dict:
         """Full RTMC; per_primary may be a uint32/int32 torch tensor of n_primaries on the GPU;
-        n_zbins > 0 adds the absorption-depth histogram ("z_hist")."""
+        n_zbins > 0 adds the absorption-depth histogram ("z_hist"); replay may be a float32
+        [n, 6] GPU tensor that receives rays of generation replay_gen as queued ("n_replay")."""
         eh = np.zeros(n_ebins, dtype=np.uint64)
         ah = np.zeros(n_abins, dtype=np.uint64)
         zh = np.zeros(max(n_zbins, 1), dtype=np.uint64)
         pp = per_primary.data_ptr() if per_primary is not None else None
+        nrep = C.c_int64(0)
+        if replay is not None:
+            assert replay.is_cuda and replay.is_contiguous() and replay.dtype == self.torch.float32
+            assert replay.dim() == 2 and replay.shape[1] == 6
         o = TraceOpts(int(max_gen), int(n_ebins), int(n_abins), int(pid0), _ptr(eh).value, _ptr(ah).value, pp,
-                      int(n_zbins), _ptr(zh).value)
+                      int(n_zbins), _ptr(zh).value, replay.data_ptr() if replay is not None else None,
+                      int(replay.shape[0]) if replay is not None else 0, int(replay_gen),
+                      C.cast(C.pointer(nrep), C.c_void_p).value)
         r = Result()
         self._chk(self.lib.rtmc_trace(self.h, scene, table, float(E), float(theta), int(n_primaries), int(seed),
                                       C.byref(o), C.byref(r)))
@@ -276,6 +286,8 @@ class Context:
         d["a_hist"] = ah
         if n_zbins:
             d["z_hist"] = zh
+        if replay is not None:
+            d["n_replay"] = int(nrep.value)
         return d
 
     def trace_batch(self, table: int, jobs, max_gen: int = 6, per_primary=None) -> list:
@@ -330,9 +342,10 @@ class Context:
         stream too, so the caching allocator's stream matches)."""
         self._chk(self.lib.rtmc_set_stream(self.h, C.c_void_p(stream.cuda_stream)))
 
-    def set_launch(self, block: int, wg_per_cu: int, lds_stack: int, chunk: int, refill: int = 48, occupancy: int = 0):
+    def set_launch(self, block: int, wg_per_cu: int, lds_stack: int, chunk: int, refill: int = 48, occupancy: int = 0,
+                   claim: int = 0):
         self._chk(self.lib.rtmc_set_launch(self.h, C.byref(LaunchCfg(block, wg_per_cu, lds_stack, chunk, refill,
-                                                                     occupancy))))
+                                                                     occupancy, claim))))
 
     def get_launch(self) -> dict:
         c = LaunchCfg()
@@ -395,6 +408,20 @@ class Context:
         self._chk(self.lib.rtmc_srg_train_step(self.h, srg, C.c_void_p(Xd.data_ptr()), C.c_void_p(yd.data_ptr()),
                                                Xd.shape[0], float(lr), float(weight_decay), C.byref(loss)))
         return loss.value
+
+    def srg_train(self, srg: int, X, y, batch: int, lr, weight_decay: float = 0.0, seed: int = 0,
+                  use_graph: bool = True):
+        """Device training loop: len(lr) AdamW steps on batches drawn from (X, y)
+        on the GPU; returns the batch losses (numpy float32, one per step)."""
+        Xd = X if getattr(X, "is_cuda", False) else self._dev(X)
+        yd = y if getattr(y, "is_cuda", False) else self._dev(y)
+        assert Xd.is_contiguous() and yd.is_contiguous() and Xd.shape[0] == yd.shape[0]
+        lr_h = np.ascontiguousarray(lr, dtype=np.float32).reshape(-1)
+        losses = np.zeros(lr_h.size, dtype=np.float32)
+        self._chk(self.lib.rtmc_srg_train(self.h, srg, C.c_void_p(Xd.data_ptr()), C.c_void_p(yd.data_ptr()),
+                                          Xd.shape[0], int(batch), lr_h.size, _ptr(lr_h), float(weight_decay),
+                                          int(seed), int(bool(use_graph)), _ptr(losses)))
+        return losses
 
     def srg_predict(self, srg: int, X):
         """Returns a float32 GPU tensor of predictions."""

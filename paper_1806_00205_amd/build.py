@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "librtmc.so")
-SOURCES = ["api.hip", "bvh.hip", "trace.hip", "mlp.hip"]
+SOURCES = ["api.hip", "bvh.hip", "traverse.hip", "shade.hip", "mlp.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

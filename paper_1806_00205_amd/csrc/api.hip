@@ -14,7 +14,10 @@
 #include <vector>
 
 #include "../../include/rtmc.h"
+#include "bvh_build.h"
+#include "mlp_kernels.h"
 #include "rtmc_internal.h"
+#include "shade_kernels.h"
 
 using namespace rtmc;
 
@@ -47,6 +50,10 @@ struct Surrogate {
   DevBuf ws;                        // batch workspace
   int64_t ws_rows = 0;
   int64_t step = 0;
+  // device training loop: state words, learning rates, losses, the sampled batch
+  DevBuf tbuf;
+  hipGraphExec_t tgexec = nullptr;  // one loop step, captured
+  std::vector<uint64_t> tkey;       // what that capture depends on
 };
 
 struct Tables {
@@ -117,7 +124,7 @@ struct rtmc_ctx {
   std::vector<Scene> scenes;
   std::vector<Tables> tables;
   std::vector<Surrogate> srgs;
-  rtmc_launch_cfg cfg{256, 7, 16, 1 << 24, 48, 0};
+  rtmc_launch_cfg cfg{256, 7, 16, 1 << 24, 48, 0, kClaimDefault};
   // trace work buffers, grown on demand
   DevBuf queue[2];
   DevBuf hits;  // hit records, qcap entries
@@ -130,6 +137,10 @@ struct rtmc_ctx {
   size_t pin_bytes = 0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   std::vector<hipEvent_t> kev;  // per-launch timing events (eager traces)
+  // replay output requested by the current rtmc_trace (queued rays of one generation)
+  float* replay = nullptr;
+  uint32_t n_replay = 0;
+  int32_t replay_gen = 0;
   // last instantiated batch graph and the signature it was captured for
   hipGraphExec_t gexec = nullptr;
   std::vector<uint64_t> gkey;
@@ -199,7 +210,7 @@ hipError_t queue_readback(rtmc_ctx* c, size_t n_words, hipStream_t s) {
     if (e != hipSuccess) return e;
     c->pin_bytes = need;
   }
-  hipError_t e = hipMemcpyAsync(c->pin, c->err_word.p, 4, hipMemcpyDeviceToHost, s);
+  hipError_t e = hipMemcpyAsync(c->pin, c->err_word.p, 8, hipMemcpyDeviceToHost, s);
   if (e == hipSuccess && n_words)
     e = hipMemcpyAsync(static_cast<char*>(c->pin) + 16, c->tally.p, n_words * 8, hipMemcpyDeviceToHost, s);
   return e;
@@ -351,7 +362,7 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
 
   HIPCHK(c, launch_fill_u64(reinterpret_cast<unsigned long long*>(c->tally.p), 0ull, tw * jobs.size(), s));
   HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->counters.p), 0u, (size_t)ncnt * n_chunks, s));
-  HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->err_word.p), 0u, 1, s));
+  HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(c->err_word.p), 0u, 2, s));
 
   // the whole allocated queue is the limit: after an overflow the chunk is
   // halved while the queue keeps its length, so every retry doubles the
@@ -385,6 +396,7 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   ta.lds_stack = cfg.lds_stack;
   ta.gstack_depth = gdepth;
   ta.refill = cfg.refill;
+  ta.claim_max = (uint32_t)cfg.claim;
   ta.err = errw;
 
   ShadeArgs sa{};
@@ -445,6 +457,8 @@ rtmc_status enqueue_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
         HIPCHK(c, launch_shade(sa, c->n_cu, kShadeBlock, s));
       }
       ++*n_launch;
+      if (ch == 0 && c->replay && g + 1 == c->replay_gen)
+        HIPCHK(c, launch_copy_rays(q[(g + 1) & 1], cnt + g + 1, qcap, c->replay, c->n_replay, errw + 1, s));
     }
     HIPCHK(c, launch_chunk_reduce(ta.jobs, j_lo, j_hi, sa.ppc, n_here, lo, s));
   }
@@ -483,7 +497,7 @@ rtmc_status prepare_trace(rtmc_ctx* c, const Tables& tb, const std::vector<HostJ
   for (const ChunkPlan& p : plan_chunks(jobs, chunk)) max_chunk = std::max<uint64_t>(max_chunk, p.n);
   const uint64_t need_q = max_chunk * tb.max_d;
   // the 32-bit work counters may run past the queue length by one block claim per wave
-  const uint64_t claim_slack = (uint64_t)grid_of(c, cfg) * (cfg.block / 64) * kClaimMax;
+  const uint64_t claim_slack = (uint64_t)grid_of(c, cfg) * (cfg.block / 64) * (uint64_t)cfg.claim;
   if (need_q + claim_slack > 0xFFFFFFF0ull) return fail(c, RTMC_EINVAL, "chunk too large for the queue index range");
   if (c->qcap < need_q || !c->queue[0].p) {
     for (int i = 0; i < 2; ++i) {
@@ -667,6 +681,27 @@ bool finite_f(float x) { return std::isfinite(x); }
 // A batch whose sequence holds more traversal launches than this is replayed as a HIP graph.
 constexpr uint64_t kGraphLaunches = 128;
 
+// Launch shapes chosen by rtmc_autotune, for the process: the GPU, the
+// scene's size class, the tables' largest yield and the calibration point.
+using TuneKey = std::vector<uint64_t>;
+std::mutex tune_mu;
+std::vector<std::pair<TuneKey, rtmc_launch_cfg>> tune_cache;
+
+TuneKey tune_key(const rtmc_ctx* c, int32_t scene_id, int32_t table_id, double E, double theta, uint64_t n) {
+  const Scene& s = c->scenes[scene_id];
+  hipDeviceProp_t prop;
+  uint64_t arch = 0;
+  if (hipGetDeviceProperties(&prop, c->device) == hipSuccess)
+    for (const char* p = prop.gcnArchName; *p; ++p) arch = arch * 131 + (unsigned char)*p;
+  uint64_t tri_bucket = 0;
+  while ((1ull << tri_bucket) < (uint64_t)std::max<int64_t>(s.n_tris, 1)) ++tri_bucket;
+  uint64_t eb, tb;
+  std::memcpy(&eb, &E, 8);
+  std::memcpy(&tb, &theta, 8);
+  return {arch, (uint64_t)c->n_cu, tri_bucket, (uint64_t)s.depth, (uint64_t)c->tables[table_id].max_d,
+          (uint64_t)s.flags, eb, tb, n};
+}
+
 }  // namespace
 
 extern "C" {
@@ -716,6 +751,8 @@ void rtmc_destroy(rtmc_ctx* c) {
   }
   for (auto& t : c->tables) dev_free(c, t.buf);
   for (auto& g : c->srgs) {
+    if (g.tgexec) (void)hipGraphExecDestroy(g.tgexec);
+    dev_free(c, g.tbuf);
     dev_free(c, g.master);
     dev_free(c, g.mom1);
     dev_free(c, g.mom2);
@@ -1067,7 +1104,7 @@ rtmc_status rtmc_trace(rtmc_ctx* c, int32_t scene_id, int32_t table_id, double E
   c->err.clear();
   if (table_id < 0 || table_id >= (int32_t)c->tables.size()) return fail(c, RTMC_EINVAL, "unknown table id %d", table_id);
   if (!out) return fail(c, RTMC_EINVAL, "null result");
-  rtmc_trace_opts o{6, 256, 90, 0, nullptr, nullptr, nullptr, 0, nullptr};
+  rtmc_trace_opts o{6, 256, 90, 0, nullptr, nullptr, nullptr, 0, nullptr, nullptr, 0, 0, nullptr};
   if (opts) {
     o = *opts;
     if (o.n_ebins == 0) o.n_ebins = 256;
@@ -1080,6 +1117,9 @@ rtmc_status rtmc_trace(rtmc_ctx* c, int32_t scene_id, int32_t table_id, double E
   if (!(E_eV > 0.0) || !std::isfinite(E_eV) || !std::isfinite(theta_deg) || theta_deg > 90.0 || theta_deg < -90.0)
     return fail(c, RTMC_EINVAL, "bad energy or angle");
   if (o.pid0 + n_primaries > 0xFFFFFFFFull) return fail(c, RTMC_EINVAL, "pid0 + n_primaries must stay below 2^32");
+  if (o.replay && (o.n_replay < 0 || o.n_replay > 0xFFFFFFFFll || o.replay_gen < 1 || o.replay_gen > o.max_gen))
+    return fail(c, RTMC_EINVAL, "replay needs 0 <= n_replay < 2^32 and 1 <= replay_gen <= max_gen");
+  if (o.n_replay_out) *o.n_replay_out = 0;
   HIPCHK(c, hipSetDevice(c->device));
   std::vector<HostJob> jobs{{scene_id, E_eV, theta_deg, n_primaries, seed, o.pid0, o.pp_escaped}};
   if (n_primaries == 0) {
@@ -1090,8 +1130,18 @@ rtmc_status rtmc_trace(rtmc_ctx* c, int32_t scene_id, int32_t table_id, double E
     return RTMC_OK;
   }
   TraceOut to;
+  c->replay = o.replay && o.n_replay > 0 ? o.replay : nullptr;
+  c->n_replay = (uint32_t)o.n_replay;
+  c->replay_gen = o.replay_gen;
   st = run_trace(c, table_id, jobs, o.max_gen, o.n_ebins, o.n_abins, o.n_zbins, false, to);
+  const bool replayed = c->replay != nullptr;
+  c->replay = nullptr;
   if (st) return st;
+  if (replayed && o.n_replay_out) {
+    uint32_t nr = 0;
+    std::memcpy(&nr, static_cast<const char*>(c->pin) + 4, 4);
+    *o.n_replay_out = nr;
+  }
   fill_result(to.tally.data(), jobs[0], o.n_ebins, o.n_abins, o.n_zbins, o.e_hist, o.a_hist, o.z_hist, to, out);
   return RTMC_OK;
 }
@@ -1147,7 +1197,7 @@ rtmc_status rtmc_first_hit(rtmc_ctx* c, int32_t scene_id, const float* rays, int
   const int grid = grid_of(c, c->cfg);
   const size_t waves = (size_t)grid * (block / 64);
   // the 32-bit work counter may run past n by one block claim per wave
-  if ((uint64_t)n + (uint64_t)waves * kClaimMax > 0xFFFFFFF0ull) return fail(c, RTMC_EINVAL, "too many rays");
+  if ((uint64_t)n + (uint64_t)waves * (uint64_t)c->cfg.claim > 0xFFFFFFF0ull) return fail(c, RTMC_EINVAL, "too many rays");
   st = ensure(c, c->gstack, waves * gdepth * 64 * 4);
   if (st) return st;
   // job 0 carries the scene; hit records go to scratch except code and t
@@ -1178,6 +1228,7 @@ rtmc_status rtmc_first_hit(rtmc_ctx* c, int32_t scene_id, const float* rays, int
   ta.lds_stack = c->cfg.lds_stack;
   ta.gstack_depth = gdepth;
   ta.refill = c->cfg.refill;
+  ta.claim_max = (uint32_t)c->cfg.claim;
   if (e == hipSuccess) e = launch_fill_u32(ta.work, 0u, 2, c->stream);
   if (e == hipSuccess) e = launch_traverse(ta, false, c->cfg.occupancy, grid, block, c->stream);
   if (e == hipSuccess)
@@ -1238,6 +1289,7 @@ rtmc_status rtmc_first_hit_noalloc(rtmc_ctx* c, int32_t scene_id, const float* r
   ta.lds_stack = cfg.lds_stack;
   ta.gstack_depth = gdepth;
   ta.refill = cfg.refill;
+  ta.claim_max = (uint32_t)cfg.claim;
   HIPCHK(c, launch_store_job(djd, dj, c->stream));
   HIPCHK(c, launch_fill_u32(head, 0u, 2, c->stream));
   HIPCHK(c, launch_traverse(ta, false, cfg.occupancy, grid, cfg.block, c->stream));
@@ -1278,9 +1330,11 @@ rtmc_status rtmc_sort_pairs_u64(rtmc_ctx* c, uint64_t* keys, uint32_t* vals, int
 rtmc_status rtmc_set_launch(rtmc_ctx* c, const rtmc_launch_cfg* cfg) {
   if (!c) return RTMC_EINVAL;
   if (!cfg || cfg->block < 64 || cfg->block > 256 || cfg->block % 64 || cfg->wg_per_cu < 1 || cfg->wg_per_cu > 64 ||
-      cfg->lds_stack < 4 || cfg->lds_stack > 64 || cfg->chunk < 1 || cfg->refill < 1 || cfg->refill > 64)
+      cfg->lds_stack < 4 || cfg->lds_stack > 64 || cfg->chunk < 1 || cfg->refill < 1 || cfg->refill > 64 ||
+      cfg->claim < 0 || cfg->claim > kClaimLimit || (cfg->claim > 0 && cfg->claim < 64))
     return fail(c, RTMC_EINVAL, "bad launch shape");
   c->cfg = *cfg;
+  if (c->cfg.claim == 0) c->cfg.claim = kClaimDefault;
   return RTMC_OK;
 }
 
@@ -1295,6 +1349,17 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
   rtmc_status st = check_scene(c, scene_id, true);
   if (st) return st;
   if (table_id < 0 || table_id >= (int32_t)c->tables.size()) return fail(c, RTMC_EINVAL, "unknown table id %d", table_id);
+  if (n_primaries == 0 || n_primaries > 0xFFFFFFFFull) return fail(c, RTMC_EINVAL, "bad calibration size");
+  const TuneKey key = tune_key(c, scene_id, table_id, E_eV, theta_deg, n_primaries);
+  {
+    std::lock_guard<std::mutex> lock(tune_mu);
+    for (const auto& e : tune_cache)
+      if (e.first == key) {
+        c->cfg = e.second;
+        if (best) *best = e.second;
+        return RTMC_OK;
+      }
+  }
   const rtmc_launch_cfg keep = c->cfg;
   // coordinate search: one knob at a time, starting from the current shape
   rtmc_launch_cfg cur = keep;
@@ -1306,7 +1371,7 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
     c->cfg = cf;
     rtmc_result r;
     rtmc_status s2 = rtmc_trace(c, scene_id, table_id, E_eV, theta_deg, n_primaries, 12345, nullptr, &r);
-    *ms = s2 ? 1e30 : r.kernel_ms + r.shade_ms;
+    *ms = s2 ? 1e30 : r.ms;
     return s2;
   };
   double best_ms = 1e30;
@@ -1315,25 +1380,36 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
     c->cfg = keep;
     return st;
   }
-  const int blocks[] = {64, 128, 256};
-  const int wgs[] = {2, 4, 6, 7, 8, 12, 16};
-  const int stacks[] = {8, 12, 16, 24, 32};
-  const int refills[] = {24, 32, 40, 48, 56, 64};
-  const int occs[] = {0, 6, 8};
+  // chunk candidates: the whole calibration trace, and halves, quarters, eighths of it
+  std::vector<int32_t> chunks;
+  for (int k = 0; k < 4; ++k) {
+    const uint64_t ch = std::max<uint64_t>(1, n_primaries >> k);
+    if (ch >= 4096 || k == 0) chunks.push_back((int32_t)std::min<uint64_t>(ch, 1u << 30));
+  }
+  const std::vector<std::vector<int32_t>> knobs = {
+      {64, 128, 256},                    // block
+      {2, 4, 6, 7, 8, 12, 16},           // workgroups per CU (of 256 threads)
+      {8, 12, 16, 24, 32},               // LDS stack entries
+      {24, 32, 40, 48, 56, 64},          // refill threshold
+      {0, 6, 8},                         // kernel build
+      {512, 1024, 2048, 4096, 8192},     // rays per wave per claim
+      chunks};                           // primaries per chunk
   for (int pass = 0; pass < 2; ++pass) {
-    for (int knob = 0; knob < 5; ++knob) {
-      const int n = knob == 0 ? 3 : (knob == 1 ? 7 : (knob == 2 ? 5 : (knob == 3 ? 6 : 3)));
-      for (int i = 0; i < n; ++i) {
+    for (size_t knob = 0; knob < knobs.size(); ++knob) {
+      for (const int32_t v : knobs[knob]) {
         rtmc_launch_cfg cf = cur;
         if (knob == 0) {
-          cf.block = blocks[i];
-          cf.wg_per_cu = std::max(1, cur.wg_per_cu * cur.block / blocks[i]);
+          cf.block = v;
+          cf.wg_per_cu = std::max(1, cur.wg_per_cu * cur.block / v);
         }
-        if (knob == 1) cf.wg_per_cu = wgs[i] * 256 / cf.block;
-        if (knob == 2) cf.lds_stack = stacks[i];
-        if (knob == 3) cf.refill = refills[i];
-        if (knob == 4) cf.occupancy = occs[i];
+        if (knob == 1) cf.wg_per_cu = v * 256 / cf.block;
+        if (knob == 2) cf.lds_stack = v;
+        if (knob == 3) cf.refill = v;
+        if (knob == 4) cf.occupancy = v;
+        if (knob == 5) cf.claim = v;
+        if (knob == 6) cf.chunk = v;
         if (cf.wg_per_cu < 1 || cf.wg_per_cu > 64) continue;
+        if (std::memcmp(&cf, &cur, sizeof(cf)) == 0) continue;
         double ms;
         st = time_cfg(cf, &ms);
         if (st) {
@@ -1348,6 +1424,10 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
     }
   }
   c->cfg = cur;
+  {
+    std::lock_guard<std::mutex> lock(tune_mu);
+    tune_cache.emplace_back(key, cur);
+  }
   if (best) *best = cur;
   return RTMC_OK;
 }
@@ -1745,6 +1825,102 @@ rtmc_status rtmc_srg_train_step(rtmc_ctx* c, int32_t id, const float* X, const f
     HIPCHK(c, hipStreamSynchronize(c->stream));
     *loss = acc[0];
   }
+  return RTMC_OK;
+}
+
+rtmc_status rtmc_srg_train(rtmc_ctx* c, int32_t id, const float* X, const float* y, int64_t n, int64_t batch,
+                           int32_t steps, const float* lr, float weight_decay, uint64_t seed, int32_t use_graph,
+                           float* losses) {
+  rtmc_status st = srg_check(c, id);
+  if (st) return st;
+  Surrogate& g = c->srgs[id];
+  if (!X || !y || !lr || n < 1 || n > 0xFFFFFFFFll) return fail(c, RTMC_EINVAL, "bad training arrays");
+  if (batch < 32 || batch % 32 || batch > (1 << 22)) return fail(c, RTMC_EINVAL, "batch must be a positive multiple of 32");
+  if (steps < 1 || steps > (1 << 24)) return fail(c, RTMC_EINVAL, "steps must be in [1, 2^24]");
+  if (!(weight_decay >= 0.0f)) return fail(c, RTMC_EINVAL, "bad weight decay");
+  for (int32_t s = 0; s < steps; ++s)
+    if (!(lr[s] > 0.0f) || !std::isfinite(lr[s])) return fail(c, RTMC_EINVAL, "learning rate %d not positive", s);
+  HIPCHK(c, hipSetDevice(c->device));
+  st = srg_ensure_ws(c, g, batch);
+  if (st) return st;
+  // loop buffer: 2 state words (padded to 256 B), lr[steps], losses[steps], Xb [batch, n_in], yb [batch]
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t o_lr = 256, o_loss = o_lr + up((size_t)steps * 4), o_xb = o_loss + up((size_t)steps * 4);
+  const size_t o_yb = o_xb + up((size_t)batch * g.n_in * 4), total = o_yb + up((size_t)batch * 4);
+  st = ensure(c, g.tbuf, total);
+  if (st) return st;
+  char* base = static_cast<char*>(g.tbuf.p);
+  uint32_t* state = reinterpret_cast<uint32_t*>(base);
+  float* lr_d = reinterpret_cast<float*>(base + o_lr);
+  float* loss_d = reinterpret_cast<float*>(base + o_loss);
+  float* Xb = reinterpret_cast<float*>(base + o_xb);
+  float* yb = reinterpret_cast<float*>(base + o_yb);
+  HIPCHK(c, hipMemcpyAsync(lr_d, lr, (size_t)steps * 4, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, launch_fill_u32(state, (uint32_t)g.step, 2, c->stream));
+  const SrgLayout L = srg_layout(g);
+  const SrgWs w = srg_ws(g, batch);
+  // one step: batch on the device, forward, backward, AdamW, BF16 weights, loss out
+  auto one_step = [&]() -> rtmc_status {
+    HIPCHK(c, mlp_sample_batch(X, y, (uint32_t)n, g.n_in, (int)batch, seed, state, Xb, yb, c->stream));
+    rtmc_status s2 = srg_forward(c, g, Xb, batch, true, w, w.y);
+    if (s2) return s2;
+    s2 = srg_backward(c, g, yb, batch, w);
+    if (s2) return s2;
+    HIPCHK(c, mlp_adamw_loop(reinterpret_cast<float*>(g.master.p), reinterpret_cast<float*>(g.mom1.p),
+                             reinterpret_cast<float*>(g.mom2.p), reinterpret_cast<const float*>(g.grad.p), L.total,
+                             lr_d, state, 0.9f, 0.999f, 1e-8f, weight_decay, c->stream));
+    s2 = srg_refresh_bf16(c, g);
+    if (s2) return s2;
+    HIPCHK(c, mlp_step_done(state, w.acc, loss_d, c->stream));
+    return RTMC_OK;
+  };
+  if (!use_graph) {
+    for (int32_t s = 0; s < steps; ++s) {
+      st = one_step();
+      if (st) return st;
+    }
+  } else {
+    uint32_t wd_bits;
+    std::memcpy(&wd_bits, &weight_decay, 4);
+    const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)X, (uint64_t)(uintptr_t)y, (uint64_t)n, (uint64_t)batch,
+                                       seed, (uint64_t)(uintptr_t)g.tbuf.p, (uint64_t)(uintptr_t)g.ws.p,
+                                       (uint64_t)(uintptr_t)g.master.p, (uint64_t)steps, wd_bits};
+    // the step runs on the context's own capture stream, ordered after the work above
+    HIPCHK(c, hipEventRecord(c->ev0, c->stream));
+    HIPCHK(c, hipStreamWaitEvent(c->gstream, c->ev0, 0));
+    if (!g.tgexec || key != g.tkey) {
+      if (g.tgexec) {
+        (void)hipGraphExecDestroy(g.tgexec);
+        g.tgexec = nullptr;
+      }
+      hipStream_t saved = c->stream;
+      c->stream = c->gstream;
+      hipGraph_t graph = nullptr;
+      hipError_t e = hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal);
+      if (e != hipSuccess) {
+        c->stream = saved;
+        return fail(c, RTMC_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+      }
+      st = one_step();
+      e = hipStreamEndCapture(c->gstream, &graph);
+      c->stream = saved;
+      if (st) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+      }
+      HIPCHK(c, e);
+      e = hipGraphInstantiate(&g.tgexec, graph, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(graph);
+      HIPCHK(c, e);
+      g.tkey = key;
+    }
+    for (int32_t s = 0; s < steps; ++s) HIPCHK(c, hipGraphLaunch(g.tgexec, c->gstream));
+    HIPCHK(c, hipEventRecord(c->ev1, c->gstream));
+    HIPCHK(c, hipStreamWaitEvent(c->stream, c->ev1, 0));
+  }
+  g.step += steps;
+  if (losses) HIPCHK(c, hipMemcpyAsync(losses, loss_d, (size_t)steps * 4, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   return RTMC_OK;
 }
 

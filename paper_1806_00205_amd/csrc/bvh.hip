@@ -15,7 +15,7 @@
 // reads (up to four children per 64-byte record).
 #include <algorithm>
 
-#include "rtmc_internal.h"
+#include "bvh_build.h"
 
 namespace rtmc {
 

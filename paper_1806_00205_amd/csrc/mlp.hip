@@ -13,17 +13,14 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "rtmc_internal.h"
+#include "device_util.h"
+#include "mlp_kernels.h"
 
 namespace rtmc {
 namespace {
 
-#define GAS __attribute__((address_space(1)))
-
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
-
-__device__ inline uint32_t lane_id() { return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u)); }
 
 // erf by Abramowitz and Stegun 7.1.26 (absolute error <= 1.5e-7): branch
 // free, one reciprocal and one exponential, far below the BF16 rounding the
@@ -123,18 +120,20 @@ __global__ void k_out_fwd(const __bf16* __restrict__ H, int B, int width, const 
   y[b] = s;
 }
 
-// Mean squared error: dy = 2 (y - t) / B; acc[0] += mean (y - t)^2, acc[1] +=
-// sum dy (the output bias gradient).
+// Loss and output gradient of a batch: dy[b] = 2 (y[b] - t[b]) / B, and
+// acc = (mean squared error, sum of dy = the output bias gradient).  One workgroup, each thread summing
+// a fixed stride of rows, then a fixed tree: the sums do not depend on
+// scheduling, so training is reproducible bit for bit.
 __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, int B, float* __restrict__ dy,
                       float* __restrict__ acc) {
   __shared__ float part[2][256];
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
   float e = 0.f, g = 0.f;
-  if (b < B) {
+  for (int b = threadIdx.x; b < B; b += blockDim.x) {
     const float d = y[b] - t[b];
-    g = 2.0f * d / (float)B;
-    dy[b] = g;
-    e = d * d / (float)B;
+    const float gb = 2.0f * d / (float)B;
+    dy[b] = gb;
+    g += gb;
+    e += d * d / (float)B;
   }
   part[0][threadIdx.x] = e;
   part[1][threadIdx.x] = g;
@@ -147,8 +146,8 @@ __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, 
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    atomicAdd(acc, part[0][0]);
-    atomicAdd(acc + 1, part[1][0]);
+    acc[0] = part[0][0];
+    acc[1] = part[1][0];
   }
 }
 
@@ -196,6 +195,49 @@ __global__ void k_adamw(float* __restrict__ p, float* __restrict__ m, float* __r
     v[i] = vi;
     p[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i]);
   }
+}
+
+// ---- a training loop on the device (one step is replayed as a graph).
+// state[0] counts the AdamW steps taken so far, state[1] is its value when
+// the loop began, so state[0] - state[1] is the loop's current step s.
+
+// Batch of step s drawn on the device: row r takes row floor(u n / 2^32) of
+// (X, y), u the first word of Philox4x32-10 under key seed at counter
+// (r, s, 0, 0): uniform sampling with replacement.
+__global__ void k_sample_batch(const float* __restrict__ X, const float* __restrict__ y, uint32_t n, int n_in,
+                               int batch, uint64_t seed, const uint32_t* __restrict__ state, float* __restrict__ Xb,
+                               float* __restrict__ yb) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= batch) return;
+  const uint32_t s = state[0] - state[1];
+  const U4 u = philox(seed, (uint32_t)r, s, 0u, 0u);
+  const uint32_t i = __umulhi(u.x, n);
+  for (int k = 0; k < n_in; ++k) Xb[(size_t)r * n_in + k] = X[(size_t)i * n_in + k];
+  yb[r] = y[i];
+}
+
+// AdamW at the loop step's learning rate, bias corrections of step t = state[0] + 1.
+__global__ void k_adamw_loop(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
+                             const float* __restrict__ g, int64_t n, const float* __restrict__ lr_sched,
+                             const uint32_t* __restrict__ state, float b1, float b2, float eps, float wd) {
+  const uint32_t t = state[0] + 1u;
+  const float lr = lr_sched[state[0] - state[1]];
+  const float c1 = (float)(1.0 - pow((double)b1, (double)t)), c2 = (float)(1.0 - pow((double)b2, (double)t));
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i]);
+  }
+}
+
+// End of a loop step: its batch loss (before the update) to losses[s]; one step more.
+__global__ void k_step_done(uint32_t* state, const float* acc, float* losses) {
+  const uint32_t s = state[0] - state[1];
+  losses[s] = acc[0];
+  state[0] = state[0] + 1u;
 }
 
 __global__ void k_to_bf16(const float* __restrict__ W, int rows, int cols, __bf16* __restrict__ Wb,
@@ -352,7 +394,7 @@ hipError_t mlp_out_fwd(const __bf16* H, int B, int width, const float* w, const 
 }
 
 hipError_t mlp_mse(const float* y, const float* t, int B, float* dy, float* loss_acc, hipStream_t s) {
-  k_mse<<<(B + 255) / 256, 256, 0, s>>>(y, t, B, dy, loss_acc);
+  k_mse<<<1, 256, 0, s>>>(y, t, B, dy, loss_acc);
   return hipGetLastError();
 }
 
@@ -373,6 +415,25 @@ hipError_t mlp_adamw(float* p, float* m, float* v, const float* g, int64_t n, fl
   int grid = (int)((n + 255) / 256);
   if (grid > 4096) grid = 4096;
   k_adamw<<<grid, 256, 0, s>>>(p, m, v, g, n, lr, b1, b2, eps, wd, c1, c2);
+  return hipGetLastError();
+}
+
+hipError_t mlp_sample_batch(const float* X, const float* y, uint32_t n, int n_in, int batch, uint64_t seed,
+                            const uint32_t* state, float* Xb, float* yb, hipStream_t s) {
+  k_sample_batch<<<(batch + 255) / 256, 256, 0, s>>>(X, y, n, n_in, batch, seed, state, Xb, yb);
+  return hipGetLastError();
+}
+
+hipError_t mlp_adamw_loop(float* p, float* m, float* v, const float* g, int64_t n, const float* lr_sched,
+                          const uint32_t* state, float b1, float b2, float eps, float wd, hipStream_t s) {
+  int grid = (int)((n + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  k_adamw_loop<<<grid, 256, 0, s>>>(p, m, v, g, n, lr_sched, state, b1, b2, eps, wd);
+  return hipGetLastError();
+}
+
+hipError_t mlp_step_done(uint32_t* state, const float* acc, float* losses, hipStream_t s) {
+  k_step_done<<<1, 1, 0, s>>>(state, acc, losses);
   return hipGetLastError();
 }
 

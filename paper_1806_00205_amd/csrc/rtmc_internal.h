@@ -28,7 +28,6 @@ namespace rtmc {
 
 constexpr uint32_t kLeafBit = 0x80000000u;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;  // unused child slot of a 4-wide node
-constexpr int32_t kEmitPaper = 1;         // DevTables::emission of the paper's one/two-daughter rule
 constexpr int kMaxGen = 10;
 constexpr int kWrapMax = 10000;
 constexpr float kSpawnEps = 1e-4f;
@@ -37,10 +36,9 @@ constexpr int kMaxAbins = 360;
 constexpr int kMaxZbins = 256;
 constexpr int kMaxYield = 8192;
 constexpr int kMaxCdf = 1024;
-constexpr int kGuide = 1024;  // entries of each CDF guide table
 constexpr int kGlobalStack = 64;  // minimum traversal stack entries per lane beyond the LDS part
-constexpr int kClaimMax = 2048;   // largest block of rays one traversal wave claims at once
-constexpr int kShadeJobs = 32;    // chunks with at most this many jobs tally per workgroup in LDS
+constexpr int kClaimDefault = 2048;  // largest block of rays one traversal wave claims at once (default)
+constexpr int kClaimLimit = 8192;    // upper bound of that launch knob
 
 // tally counter slots (u64 each), followed by the energy and angle histograms
 enum TallySlot {
@@ -73,22 +71,6 @@ struct DevScene {
   float wext;  // bound on the magnitude of every coordinate of the scene and its node planes
   int32_t n_tris;
   uint32_t flags;
-};
-
-struct DevTables {
-  const float* yld;
-  const float* cdfE;
-  const float* cdfF;
-  const float* esee;  // E_SEE on the yield grid (paper emission), else null
-  // guide tables of the CDF look-ups (kGuide entries each): gF[b] = first
-  // segment whose upper CDF value reaches b / kGuide; gE[b] = last node at or
-  // below the energy with bit pattern e1bits + (b << eshift), e1bits = cdfE[1]
-  const uint16_t* gF;
-  const uint16_t* gE;
-  uint32_t e1bits, eshift;
-  int32_t nE, nth, ncdf;
-  int32_t emission;   // RTMC_EMIT_SPECTRUM or RTMC_EMIT_PAPER
-  float logEmin, invdlogE, thscale, Ec;
 };
 
 // One job: a scene traced at one (E, theta) point.
@@ -138,119 +120,21 @@ struct TraverseArgs {
   int32_t lds_stack;
   int32_t gstack_depth;
   int32_t refill;  // refill a wave once this many lanes are idle
+  uint32_t claim_max;  // largest block of rays a wave claims at once
   uint32_t* err;   // bit 1: stack overflow
 };
 
-struct ShadeArgs {
-  const DevJob* jobs;
-  int32_t n_jobs;
-  DevTables tb;
-  RayQueue qin, qout;
-  uint32_t qcap;
-  const uint32_t* count_in;
-  uint32_t n_gen0;
-  uint64_t chunk_lo;
-  uint32_t* count_out;
-  uint32_t* ppc;  // per-primary escape counts of the chunk
-  int32_t gen, max_gen;
-  int32_t n_ebins, n_abins, n_zbins;  // histogram bins: escaped energy, escape angle, absorption depth
-  int32_t j_lo, j_hi;  // jobs overlapping the chunk
-  HitRecs hit;
-  uint32_t* err;  // bit 0: queue overflow
-};
-
-// host-side launchers (defined in the .hip files)
+// host-side launchers (traverse.hip; the fills and copies in shade.hip)
 size_t traverse_lds_bytes(int lds_stack, int block);
-// LDS of a shading workgroup; n_jobs = jobs of the chunk (tallied in LDS when <= kShadeJobs)
-size_t shade_lds_bytes(const DevTables& tb, int n_hist, int block, int n_jobs);  // n_hist: all histogram bins
 hipError_t launch_traverse(const TraverseArgs& a, bool multi, int occupancy, int grid, int block, hipStream_t s);
-hipError_t launch_shade(const ShadeArgs& a, int n_cu, int block, hipStream_t s);  // grid = n_cu x occupancy
 hipError_t launch_primaries(const DevJob* jobs, int32_t j_lo, int32_t j_hi, uint64_t chunk_lo, uint32_t n,
                             const RayQueue& q, hipStream_t s);
 hipError_t launch_hit_ids(const float4* tris, const int32_t* code, int64_t n, int32_t* out, hipStream_t s);
-hipError_t launch_chunk_reduce(const DevJob* jobs, int32_t j_lo, int32_t j_hi, const uint32_t* ppc, uint32_t n,
-                               uint64_t chunk_lo, hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, size_t n, hipStream_t s);
+// The first min(*count, qcap, n_max) rays of a queue as [n][6] (origin, direction); the number to *n_out.
+hipError_t launch_copy_rays(const RayQueue& q, const uint32_t* count, uint32_t qcap, float* out, uint32_t n_max,
+                            uint32_t* n_out, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, size_t n, hipStream_t s);
 hipError_t launch_copy_probe(float4* dst, const float4* src, size_t n16, int grid, hipStream_t s);
-
-// Surrogate MLP pieces (mlp.hip)
-enum MlpEpi { MLP_EPI_F32 = 0, MLP_EPI_FWD_GELU = 1, MLP_EPI_BWD_GELU = 2 };
-
-// C = A B^T, A [M, K] and B [N, K] bf16 row-major, K % 32 == 0, FP32 accumulation.
-//   MLP_EPI_F32:      C[m, n] (float, ldc)
-//   MLP_EPI_FWD_GELU: z = acc + bias[n]; Z[m, n] = z (if Z); H[m, n] = GELU(z) (bf16); Ht[n, m] likewise (if Ht)
-//   MLP_EPI_BWD_GELU: d = acc * GELU'(Zs[m, n]); H[m, n] = d (bf16); Ht[n, m] likewise (if Ht)
-struct MlpGemm {
-  const __bf16* A;
-  const __bf16* B;
-  int M, N, K, lda, ldb;
-  int epi;
-  const float* bias;
-  float* Z;
-  int ldz;
-  __bf16* H;
-  int ldh;
-  __bf16* Ht;
-  int ldht;
-  float* C;
-  int ldc;
-  const float* Zs;
-};
-hipError_t mlp_gemm(const MlpGemm& g, hipStream_t s);
-hipError_t mlp_pack_input(const float* x, int B, int n_in, __bf16* X, __bf16* Xt, hipStream_t s);
-hipError_t mlp_out_fwd(const __bf16* H, int B, int width, const float* w, const float* c, float* y, hipStream_t s);
-hipError_t mlp_mse(const float* y, const float* t, int B, float* dy, float* acc, hipStream_t s);
-hipError_t mlp_out_bwd_hidden(const float* dy, const float* w, const float* Z, int B, int width, __bf16* G,
-                              __bf16* Gt, hipStream_t s);
-hipError_t mlp_rowsum(const __bf16* Mt, int R, int B, const float* scale, float* out, hipStream_t s);
-hipError_t mlp_adamw(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
-                     float wd, float c1, float c2, hipStream_t s);
-hipError_t mlp_to_bf16(const float* W, int rows, int cols, __bf16* Wb, __bf16* Wtb, hipStream_t s);
-
-// Fused inference of the 4 x 256 GELU network: y[r] = wout . H4(x[r]) + bout
-// for r < n.  Hidden weights are the bf16 copies in [256, kin] layout
-// (kin = 32 for layer 1, columns >= n_in zero); n_in <= 32.
-struct MlpInfer {
-  const float* x;  // [n, n_in]
-  int64_t n;
-  int n_in;
-  const __bf16* W[4];
-  const float* bias[4];
-  const float* wout;  // [256]
-  const float* bout;  // [1]
-  float* y;           // [n]
-};
-hipError_t mlp_infer(const MlpInfer& p, hipStream_t s);
-
-// BVH builder pieces
-struct BvhBuild {
-  const float4* tris_in;  // [3 n] unsorted, compacted
-  float4* tris_out;       // [3 n] sorted
-  float4* tris_rot;       // [4 n] sorted, rotated records
-  float4* nodes;          // [4 max(n - 1, 1)] binary nodes
-  float4* nodes4;         // [4 max(n - 1, 1)] quantized 4-wide nodes (traversal)
-  uint64_t* keys;         // [n]
-  uint32_t* vals;         // [n]
-  uint64_t* keys_alt;     // [n]
-  uint32_t* vals_alt;     // [n]
-  int32_t* parent;        // [max(n - 1, 1) + n]: internal nodes then leaves
-  uint32_t* flags;        // [2 max(n - 1, 1)]: arrival counts, then node heights
-  uint32_t* hist;         // radix histogram scratch
-  uint32_t* depth;        // [1]
-  int32_t n;
-  float lo[3], hi[3];
-};
-size_t radix_hist_words(int64_t n);
-hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                            uint32_t* hist, int64_t n, int key_bits, hipStream_t s, bool* result_in_alt);
-hipError_t build_bvh(BvhBuild& b, hipStream_t s);
-// Breadth-first copy of the 4-wide records reached from the root (src, nn
-// records) into dst (nn records, the tail zero), children of a record in
-// consecutive records; levels >= the tree's 4-wide depth.  front0 / front1:
-// nn words each; lv: 2 kRelayoutLevels words.
-constexpr int kRelayoutLevels = 128;
-hipError_t relayout_wide(const float4* src, float4* dst, int64_t nn, uint32_t* front0, uint32_t* front1,
-                         uint32_t* lv, int levels, hipStream_t s);
 
 }  // namespace rtmc

@@ -81,19 +81,14 @@ class Surrogate:
         self.hi = F.max(axis=0)
         Xd = torch.tensor(self._norm(F), device=f"cuda:{self.ctx.device}")
         yd = torch.tensor(np.asarray(y, dtype=np.float32), device=Xd.device)
-        g = torch.Generator(device=Xd.device).manual_seed(seed)
-        n = Xd.shape[0]
-        losses = []
-        for it in range(steps):
-            frac = it / max(steps - 1, 1)
-            lr_it = lr * (0.02 + 0.49 * (1.0 + math.cos(math.pi * frac)))  # cosine decay to 2 %
-            idx = torch.randint(0, n, (batch,), device=Xd.device, generator=g)
-            loss = self.ctx.srg_train_step(self.id, Xd[idx].contiguous(), yd[idx].contiguous(), lr=lr_it,
-                                           weight_decay=weight_decay)
-            if it % 200 == 0 or it == steps - 1:
-                losses.append((it, loss))
-                if log:
-                    log(f"step {it}: loss {loss:.3e}")
+        # cosine decay to 2 % of lr; the library draws the batches and replays one step as a graph
+        frac = np.arange(steps) / max(steps - 1, 1)
+        lr_s = lr * (0.02 + 0.49 * (1.0 + np.cos(np.pi * frac)))
+        step_losses = self.ctx.srg_train(self.id, Xd, yd, batch, lr_s, weight_decay=weight_decay, seed=seed)
+        losses = [(it, float(step_losses[it])) for it in range(steps) if it % 200 == 0 or it == steps - 1]
+        if log:
+            for it, loss in losses:
+                log(f"step {it}: loss {loss:.3e}")
         return losses
 
     def predict(self, F):

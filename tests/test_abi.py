@@ -58,6 +58,8 @@ def test_committed_traffic_counters_match_the_kernel_sources():
     import sys
     sys.path.insert(0, os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
     import bench
-    t = bench.load_traffic("c1")
-    assert t is not None, "profiles/k_traverse_c1_traffic.json was measured on other kernel sources"
-    assert t["kernel"] == "k_traverse" and 0.0 < t["fetch_plus_write_bytes_per_alg_byte"] < 2.0
+    for cfg in ("c3", "c1"):
+        t = bench.load_traffic(cfg)
+        assert t is not None, f"profiles/k_traverse_{cfg}_traffic.json was measured on other kernel sources"
+        assert t["kernel"] == "k_traverse" and 0.0 < t["fetch_plus_write_bytes_per_alg_byte"] < 2.0
+        assert t["bound"] in ("hbm", "alu")

@@ -635,14 +635,14 @@ def test_irregular_spectrum_table(ctx, oracle_lib):
     assert g["e_escaped"] == pytest.approx(o["e_escaped"], rel=1e-4)
 
 
-LAUNCHES = [(256, 7, 16, 1 << 24, 48, 0), (128, 12, 8, 5000, 24, 8), (64, 24, 24, 1 << 20, 64, 0),
-            (256, 2, 4, 3000, 1, 0), (256, 6, 16, 1 << 24, 40, 6), (256, 8, 16, 1 << 24, 48, 7)]
+LAUNCHES = [(256, 7, 16, 1 << 24, 48, 0, 0), (128, 12, 8, 5000, 24, 8, 8192), (64, 24, 24, 1 << 20, 64, 0, 64),
+            (256, 2, 4, 3000, 1, 0, 512), (256, 6, 16, 1 << 24, 40, 6, 4096), (256, 8, 16, 1 << 24, 48, 7, 2048)]
 
 
 def test_launch_shapes_do_not_change_results(ctx, tiny, vaughan):
-    """Block size, workgroups per CU, LDS stack depth, chunking, refill threshold
-    and the register-capped kernel builds change only speed: every tally, the
-    traversal work counters included, is identical."""
+    """Block size, workgroups per CU, LDS stack depth, chunking, refill threshold,
+    the register-capped kernel builds and the rays a wave claims at once change
+    only speed: every tally, the traversal work counters included, is identical."""
     sid = ctx.load_scene(tiny)
     tid = ctx.load_tables(vaughan)
     cfg = ctx.get_launch()
@@ -663,17 +663,31 @@ def test_launch_shapes_do_not_change_results(ctx, tiny, vaughan):
 
 
 def test_autotune_keeps_results(ctx, tiny, vaughan):
+    """The tuned launch (block, workgroups per CU, stack, refill, build, rays per
+    wave per claim, chunk) keeps every integer tally; a second call with the
+    same key takes the cached shape without timing anything."""
+    import time
     sid = ctx.load_scene(tiny)
     tid = ctx.load_tables(vaughan)
     cfg = ctx.get_launch()
     try:
         before = ctx.trace(sid, tid, 300.0, 20.0, 8000, seed=29)
+        t0 = time.perf_counter()
         best = ctx.autotune(sid, tid, 300.0, 20.0, 20000)
+        t_tune = time.perf_counter() - t0
         assert best == ctx.get_launch()
         assert best["block"] in (64, 128, 256) and best["wg_per_cu"] >= 1 and 1 <= best["refill"] <= 64
+        assert best["claim"] in (512, 1024, 2048, 4096, 8192)
+        assert best["chunk"] in (20000, 10000, 5000, cfg["chunk"])
         after = ctx.trace(sid, tid, 300.0, 20.0, 8000, seed=29)
-        for k in ("n_rays", "n_escaped", "n_node_visits", "n_tri_tests", "e_escaped"):
+        for k in ("n_rays", "n_escaped", "n_absorbed", "n_node_visits", "n_tri_tests", "e_escaped", "e_deposited"):
             assert before[k] == after[k], k
+        ctx.set_launch(**cfg)
+        t0 = time.perf_counter()
+        again = ctx.autotune(sid, tid, 300.0, 20.0, 20000)
+        t_cached = time.perf_counter() - t0
+        assert again == best and ctx.get_launch() == best
+        assert t_cached < 0.1 * t_tune, (t_cached, t_tune)
     finally:
         ctx.set_launch(**cfg)
 

@@ -267,3 +267,25 @@ def test_benchmark_sweep_paired_against_the_oracle(ctx, torch, oracle_lib, vaugh
         sig = math.sqrt(b["yield_sigma"] ** 2 + o["yield_sigma"] ** 2)
         assert abs(b["yield"] - o["yield"]) <= 3 * sig, (E, th, b["yield"], o["yield"], sig)
     assert chi2 <= stats.chi2.ppf(0.999, dof), chi2
+
+
+# ---------------------------------------------------------------- replayed daughters
+
+@pytest.mark.parametrize("gen", [1, 2])
+def test_first_hits_of_daughters_the_gpu_spawned(ctx, torch, oracle_lib, tiny, vaughan, gen):
+    """Daughter rays exactly as the GPU queued them (FP32 origin and direction,
+    read back from the queue of generation gen) re-traced by the oracle: the
+    first surface each meets agrees with the GPU's, and so does its distance."""
+    from tests.test_gpu_core import _first_hit_parity
+    sid = ctx.load_scene(tiny)
+    tid = ctx.load_tables(vaughan)
+    cap = 20000
+    rep = torch.zeros((cap, 6), dtype=torch.float32, device="cuda:0")
+    # about 1.4 daughters per primary reach generation 1, 0.045 generation 2
+    r = ctx.trace(sid, tid, 500.0, -80.0, 20000 if gen == 1 else 200000, seed=51, max_gen=6, replay=rep,
+                  replay_gen=gen)
+    n = r["n_replay"]
+    assert 2000 < n <= cap, n
+    rays = rep[:n].cpu().numpy().astype(np.float64)
+    assert np.allclose(np.linalg.norm(rays[:, 3:], axis=1), 1.0, atol=1e-5)
+    _first_hit_parity(ctx, torch, oracle_lib, tiny, rays, 0.9999)

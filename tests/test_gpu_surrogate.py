@@ -65,11 +65,12 @@ def test_gradient_matches_reference(ctx, seed):
     loss, g = ctx.srg_gradient(s, X, t)
     pv = mlp_ref.gpu_visible_params(p, N_IN)
     lr, gr = mlp_ref.loss_and_grad(pv, mlp_ref.round_bf16(X), t, N_IN)
-    assert loss == pytest.approx(lr, rel=2e-2)
+    assert loss == pytest.approx(lr, rel=1e-2)
     g = g.astype(np.float64)
     cos = g @ gr / (np.linalg.norm(g) * np.linalg.norm(gr))
     rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
-    assert cos > 0.999 and rel < 2e-2, (cos, rel)
+    # observed 5e-4 to 1e-3: the bfloat16 storage between layers (next test)
+    assert cos > 0.9999 and rel < 5e-3, (cos, rel)
     # every parameter block, separately
     n_in, W = N_IN, 256
     bounds = [0, W * n_in, W * n_in + W]
@@ -83,7 +84,112 @@ def test_gradient_matches_reference(ctx, seed):
     for a, b in zip(bounds[:-1], bounds[1:]):
         ga, gb = g[a:b], gr[a:b]
         if np.linalg.norm(gb) > 0:
-            assert np.linalg.norm(ga - gb) <= 3e-2 * np.linalg.norm(gb) + 1e-7, (a, b)
+            assert np.linalg.norm(ga - gb) <= 1e-2 * np.linalg.norm(gb) + 1e-7, (a, b)
+
+
+def _bf16_rounded_grad(p, X, t, n_in, width=256, depth=4):
+    """Gradient with the GPU's storage rounding: inputs, weights, hidden
+    activations and the hidden layers' backward signals held as bfloat16,
+    everything else (pre-activations, sums, output layer) in FP64."""
+    r = lambda a: mlp_ref.round_bf16(np.asarray(a, dtype=np.float32)).astype(np.float64)
+    Ws, bs, w_out, b_out = mlp_ref.unpack(mlp_ref.gpu_visible_params(p, n_in), n_in, width, depth)
+    h = r(X)
+    hs, zs = [h], []
+    for W, b in zip(Ws, bs):
+        z = h @ W.T + b
+        h = r(mlp_ref.gelu(z))
+        zs.append(z)
+        hs.append(h)
+    t = np.asarray(t, dtype=np.float64)
+    B = h.shape[0]
+    dy = 2.0 * (h @ w_out + b_out - t) / B
+    parts_out = [hs[-1].T @ dy, np.array([dy.sum()])]
+    G = r(np.outer(dy, w_out) * mlp_ref.gelu_d(zs[-1]))
+    gW, gb = [None] * depth, [None] * depth
+    for l in range(depth - 1, -1, -1):
+        gW[l] = G.T @ hs[l]
+        gb[l] = G.sum(axis=0)
+        if l > 0:
+            G = r((G @ Ws[l]) * mlp_ref.gelu_d(zs[l - 1]))
+    parts = []
+    for l in range(depth):
+        parts += [gW[l].ravel(), gb[l]]
+    return np.concatenate(parts + parts_out)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_gradient_deviation_is_the_bf16_storage(ctx, seed):
+    """What separates the GPU gradient from the FP64 one (about 1e-3) is the
+    bfloat16 storage of activations and backward signals between layers:
+    with that rounding reproduced on the host the agreement is about ten
+    times closer (what remains is FP32 summation order and values that round
+    to the other side of a bfloat16 step)."""
+    s = ctx.srg_create(N_IN, 256, 4, seed=10 + seed)
+    p = ctx.srg_params(s)
+    X, t = _data(20 + seed, 512)
+    _, g = ctx.srg_gradient(s, X, t)
+    g = g.astype(np.float64)
+    ge = _bf16_rounded_grad(p, mlp_ref.round_bf16(X), t, N_IN)
+    _, gr = mlp_ref.loss_and_grad(mlp_ref.gpu_visible_params(p, N_IN), mlp_ref.round_bf16(X), t, N_IN)
+    rel_e = np.linalg.norm(g - ge) / np.linalg.norm(ge)
+    rel_r = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    rel_er = np.linalg.norm(ge - gr) / np.linalg.norm(gr)
+    print(f"GPU vs bf16-rounded {rel_e:.2e}, GPU vs FP64 {rel_r:.2e}, bf16-rounded vs FP64 {rel_er:.2e}")
+    assert rel_e < 5e-4, rel_e
+    assert rel_e < 0.25 * rel_r, (rel_e, rel_r)
+
+
+def test_adamw_step_matches_numpy(ctx):
+    """Three AdamW steps (decoupled weight decay, bias-corrected moments)
+    element by element against numpy fed with the same gradients."""
+    s = ctx.srg_create(N_IN, 256, 4, seed=5)
+    X, t = _data(40, 256)
+    p = ctx.srg_params(s).astype(np.float64)
+    m = np.zeros_like(p)
+    v = np.zeros_like(p)
+    lr, wd, b1, b2, eps = 1e-3, 1e-2, 0.9, 0.999, 1e-8
+    for step in range(1, 4):
+        _, g = ctx.srg_gradient(s, X, t)  # the gradient the step will use (deterministic)
+        ctx.srg_train_step(s, X, t, lr=lr, weight_decay=wd)
+        g = g.astype(np.float64)
+        m = b1 * m + (1 - b1) * g
+        v = b2 * v + (1 - b2) * g * g
+        p = p - lr * ((m / (1 - b1 ** step)) / (np.sqrt(v / (1 - b2 ** step)) + eps) + wd * p)
+        got = ctx.srg_params(s).astype(np.float64)
+        err = np.abs(got - p)
+        assert np.max(err - 1e-6 * np.abs(p)) <= 2e-8, (step, float(np.max(err)))
+
+
+def test_training_loop_graph_replays_equal_eager(ctx):
+    """The device training loop replayed as a HIP graph gives bit for bit the
+    parameters of the same launches issued one by one: three rounds, each a
+    replayed call after an eager one on a twin network, with other GPU work
+    and synchronisation in between."""
+    import torch
+    X, t = _data(50, 4096)
+    Xd, td = torch.tensor(X, device="cuda:0"), torch.tensor(t, device="cuda:0")
+    a = ctx.srg_create(N_IN, 256, 4, seed=9)
+    b = ctx.srg_create(N_IN, 256, 4, seed=9)
+    lr = np.full(40, 1e-3, dtype=np.float32)
+    for rnd in range(3):
+        la = ctx.srg_train(a, Xd, td, 256, lr, weight_decay=1e-4, seed=77, use_graph=False)
+        lb = ctx.srg_train(b, Xd, td, 256, lr, weight_decay=1e-4, seed=77, use_graph=True)
+        assert np.array_equal(la, lb), rnd
+        assert np.array_equal(ctx.srg_params(a), ctx.srg_params(b)), rnd
+        ctx.srg_predict(a, Xd[:1000])  # other work between replays
+        torch.cuda.synchronize()
+
+
+def test_training_loop_converges(ctx):
+    import torch
+    s = ctx.srg_create(N_IN, 256, 4, seed=8)
+    X, t = _data(31, 8192)
+    Xd, td = torch.tensor(X, device="cuda:0"), torch.tensor(t, device="cuda:0")
+    losses = ctx.srg_train(s, Xd, td, 1024, np.full(400, 1e-3, dtype=np.float32), seed=3)
+    assert np.all(np.isfinite(losses)) and losses.shape == (400,)
+    y = ctx.srg_predict(s, Xd).cpu().numpy()
+    mse = float(np.mean((y - t) ** 2))
+    assert mse < float(losses[0]) / 20, (float(losses[0]), mse)
 
 
 def test_training_converges(ctx):
