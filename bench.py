@@ -82,10 +82,13 @@ def source_hash(texts) -> str:
     return h.hexdigest()[:16]
 
 
+TRAVERSAL_SOURCES = ("traverse.hip", "device_util.h", "rtmc_internal.h")
+
+
 def kernel_hash() -> str:
-    """Hash of the traversal kernel's sources (trace.hip and rtmc_internal.h)."""
+    """Hash of the traversal kernel's sources."""
     return source_hash(open(os.path.join(ROOT, "paper_1806_00205_amd", "csrc", f)).read()
-                       for f in ("trace.hip", "rtmc_internal.h"))
+                       for f in TRAVERSAL_SOURCES)
 
 
 def load_traffic(cfg_name: str):
@@ -166,7 +169,8 @@ def bench_foam(ctx, args, name, achievable):
     # primaries span several points, so every generation's launch is large
     # (per-point results are those of single traces, integer tallies equal)
     lc = ctx.get_launch()
-    ctx.set_launch(lc["block"], lc["wg_per_cu"], lc["lds_stack"], SWEEP_CHUNK, lc["refill"], lc["occupancy"])
+    ctx.set_launch(lc["block"], lc["wg_per_cu"], lc["lds_stack"], SWEEP_CHUNK, lc["refill"], lc["occupancy"],
+                   lc["claim"])
     jobs = [(sid, E, th, npp, cfg["rng"] * 1000 + k) for k, (E, th) in enumerate(points)]
 
     def step():
@@ -231,7 +235,8 @@ def bench_foam(ctx, args, name, achievable):
     ctx.set_launch(**lc)
     out["bvh_build"] = bench_build(ctx, mesh)
     if not args.no_cpu_baseline:
-        ctx.set_launch(lc["block"], lc["wg_per_cu"], lc["lds_stack"], SWEEP_CHUNK, lc["refill"], lc["occupancy"])
+        ctx.set_launch(lc["block"], lc["wg_per_cu"], lc["lds_stack"], SWEEP_CHUNK, lc["refill"], lc["occupancy"],
+                   lc["claim"])
         try:
             out["cpu_baseline"] = cpu_baseline(ctx, tid, mesh, tab, cfg, jobs, args.cpu_seconds)
         finally:
@@ -264,8 +269,13 @@ def roofline(name, achieved, per_launch, kernel_ms, tot, achievable):
         # measured memory-side rate of the same bytes per launch, next to the
         # algorithmic rate and the copy probe (from the counter summary)
         r["measured_dram_gbps"] = r["traffic"] / (kernel_ms * 1e-3) / 1e9 if kernel_ms > 0 else None
+        r["measured_dram_frac_of_copy"] = r["measured_dram_gbps"] / achievable if r["measured_dram_gbps"] else None
         r["valu_issue"] = tr.get("valu_issue")
         r["l2_hit"] = tr.get("l2_hit")
+        # the vector-ALU ceiling: one wave64 VALU instruction per CU per cycle
+        # (four SIMDs, four cycles per instruction each)
+        r["alu"] = {"achieved": tr.get("valu_issue"), "peak": 1.0, "unit": "VALU wave-instructions per CU per cycle",
+                    "frac": tr.get("valu_issue")}
         r["counters"] = f"profiles/k_traverse_{name}_traffic.json"
     return r
 
