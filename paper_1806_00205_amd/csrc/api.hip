@@ -551,7 +551,8 @@ rtmc_status run_trace(rtmc_ctx* c, int32_t table_id, std::vector<HostJob>& jobs,
                                    (uint64_t)n_abins, (uint64_t)n_zbins, (uint64_t)cfg.block,
                                    (uint64_t)cfg.wg_per_cu,
                                    (uint64_t)cfg.lds_stack, (uint64_t)cfg.chunk, (uint64_t)cfg.refill,
-                                   (uint64_t)cfg.occupancy, (uint64_t)table_id, (uint64_t)(uintptr_t)c->jobs.p,
+                                   (uint64_t)cfg.occupancy, (uint64_t)cfg.claim, (uint64_t)table_id,
+                                   (uint64_t)(uintptr_t)c->jobs.p,
                                    (uint64_t)(uintptr_t)c->tally.p, (uint64_t)(uintptr_t)c->queue[0].p,
                                    (uint64_t)(uintptr_t)c->queue[1].p, (uint64_t)(uintptr_t)c->hits.p,
                                    (uint64_t)(uintptr_t)c->counters.p, (uint64_t)(uintptr_t)c->ppc.p,
