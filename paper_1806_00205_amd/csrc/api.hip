@@ -901,9 +901,9 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
   if (ensure(c, tris, (size_t)n * 48) || ensure(c, tris_t, (size_t)n * 64) || ensure(c, nodes, (size_t)nn * 64) || ensure(c, nodes4, (size_t)nn * 64) ||
       ensure(c, keys, (size_t)n * 8) ||
       ensure(c, vals, (size_t)n * 4) || ensure(c, keys2, (size_t)n * 8) || ensure(c, vals2, (size_t)n * 4) ||
-      ensure(c, parent, (size_t)(nn + n) * 4) || ensure(c, flags, (size_t)nn * 8) ||
+      ensure(c, parent, (size_t)(nn + n) * 4) || ensure(c, flags, (size_t)nn * 4) ||
       ensure(c, hist, radix_hist_words(n) * 4) || ensure(c, depth, 16) || ensure(c, nodes4b, (size_t)nn * 64) ||
-      ensure(c, lv, 2 * kRelayoutLevels * 4)) {
+      ensure(c, lv, (size_t)std::max(2 * kRelayoutLevels, kRefitLevels) * 4)) {
     cleanup();
     dev_free(c, tris);
     dev_free(c, tris_t);
@@ -925,6 +925,7 @@ rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
   b.flags = reinterpret_cast<uint32_t*>(flags.p);
   b.hist = reinterpret_cast<uint32_t*>(hist.p);
   b.depth = reinterpret_cast<uint32_t*>(depth.p);
+  b.level_count = reinterpret_cast<uint32_t*>(lv.p);
   b.n = (int32_t)n;
   for (int a = 0; a < 3; ++a) {
     b.lo[a] = (float)s.lo[a];

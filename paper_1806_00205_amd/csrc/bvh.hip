@@ -8,8 +8,8 @@
 //   3. the hierarchy of Karras (HPG 2012): internal node i covers the sorted
 //      range decided by the longest common prefix of neighbouring codes, equal
 //      codes being told apart by their indices;
-//   4. bounds, bottom up: each leaf climbs towards the root and the second
-//      child to arrive at a node merges both child boxes.
+//   4. bounds, bottom up, one launch per node height: a node is merged from
+//      its two child boxes once the second child has arrived.
 // Child boxes are stored in the parent (64-byte node record); k_collapse4
 // then turns every binary node into the quantized 4-wide node traversal
 // reads (up to four children per 64-byte record).
@@ -272,48 +272,49 @@ __device__ inline void store_slot(float4* nodes, int32_t p, int slot, const floa
   for (int q = 0; q < 6; ++q) f[o + q] = b[q];
 }
 
-// Bottom-up bounds.  The child boxes are written and read with device-scope
-// atomic stores and loads, which go to the device's coherence point past the
-// per-XCD L2 caches; the writer waits for its stores to complete before it
-// counts its arrival, and the second arrival reads only after that count.
-// So no release or acquire fence (an L2 write-back or invalidation on every
-// step of every thread) is needed.  Node heights (a leaf 0, an internal node
-// one more than its taller child) travel the same way, and the thread that
-// completes the root writes its height: the tree's depth in internal nodes.
-__global__ void k_refit(const float4* __restrict__ tris, int32_t n, float4* nodes, const int32_t* __restrict__ parent,
-                        uint32_t* flags, uint32_t* height, uint32_t* depth) {
-  int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+// Bottom-up bounds, one launch per node height.  Launch 0 writes every leaf's
+// box into its slot of the parent record; launch L merges the two child boxes
+// of every node whose taller child has height L - 1 (the frontier of level L),
+// writes the union into the parent's slot and counts the arrival there.  The
+// second child to arrive at a node appends it to the next level's frontier.
+// A box is read only by a later launch than the one that wrote it, so the
+// order of launches on the stream is all the synchronisation the boxes need;
+// the arrival counts are relaxed atomic increments of one word each.  The
+// launch that reaches the root records its level: the tree's depth in
+// internal nodes (a leaf has height 0, a node one more than its taller child).
+__device__ inline void arrive(float4* nodes, const int32_t* parent, uint32_t* flags, uint32_t child, int32_t p,
+                              const float b[6], uint32_t* next, uint32_t* next_count) {
+  const float4 links = nodes[4 * (int64_t)p + 3];
+  store_slot(nodes, p, __float_as_uint(links.x) == child ? 0 : 1, b);
+  if (atomicAdd(&flags[p], 1u) == 1u) next[atomicAdd(next_count, 1u)] = (uint32_t)p;
+}
+
+__global__ void k_refit_leaves(const float4* __restrict__ tris, int32_t n, float4* nodes,
+                               const int32_t* __restrict__ parent, uint32_t* flags, uint32_t* next,
+                               uint32_t* next_count) {
+  const int32_t k = blockIdx.x * blockDim.x + threadIdx.x;
   if (k >= n) return;
   float b[6];
   tri_box(tris, k, b);
-  uint32_t child = (uint32_t)k | kLeafBit;
-  int32_t p = parent[(n - 1) + k];
-  uint32_t h = 0;
-  while (p >= 0) {
-    float4 links = nodes[4 * (int64_t)p + 3];
-    int slot = __float_as_uint(links.x) == child ? 0 : 1;
-    float* dst = reinterpret_cast<float*>(nodes + 4 * (int64_t)p) + slot * 6;
-    for (int q = 0; q < 6; ++q) __hip_atomic_store(dst + q, b[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_max(&height[p], h + 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __builtin_amdgcn_sched_barrier(0);
-    __builtin_amdgcn_s_waitcnt(0);  // the box stores have completed
-    __builtin_amdgcn_sched_barrier(0);
-    uint32_t old = __hip_atomic_fetch_add(&flags[p], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (old == 0u) return;
-    const float* f = reinterpret_cast<const float*>(nodes + 4 * (int64_t)p);
-    float o[12];
-    for (int q = 0; q < 12; ++q) o[q] = __hip_atomic_load(f + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    h = __hip_atomic_load(&height[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    b[0] = fminf(o[0], o[6]);
-    b[1] = fminf(o[1], o[7]);
-    b[2] = fminf(o[2], o[8]);
-    b[3] = fmaxf(o[3], o[9]);
-    b[4] = fmaxf(o[4], o[10]);
-    b[5] = fmaxf(o[5], o[11]);
-    child = (uint32_t)p;
-    p = parent[p];
+  arrive(nodes, parent, flags, (uint32_t)k | kLeafBit, parent[(n - 1) + k], b, next, next_count);
+}
+
+__global__ void k_refit_level(float4* nodes, const int32_t* __restrict__ parent, uint32_t* flags,
+                              const uint32_t* __restrict__ front, const uint32_t* count, uint32_t* next,
+                              uint32_t* next_count, uint32_t level, uint32_t* depth) {
+  const uint32_t m = *count;
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < m; i += gridDim.x * blockDim.x) {
+    const int32_t p = (int32_t)front[i];
+    const float4* r = nodes + 4 * (int64_t)p;
+    const float4 r0 = r[0], r1 = r[1], r2 = r[2];  // slot 0: r0.xyzw r1.xy; slot 1: r1.zw r2.xyzw
+    const float b[6] = {fminf(r0.x, r1.z), fminf(r0.y, r1.w), fminf(r0.z, r2.x),
+                        fmaxf(r0.w, r2.y), fmaxf(r1.x, r2.z), fmaxf(r1.y, r2.w)};
+    const int32_t q = parent[p];
+    if (q < 0)
+      *depth = level;
+    else
+      arrive(nodes, parent, flags, (uint32_t)p, q, b, next, next_count);
   }
-  *depth = h;
 }
 
 // One triangle: a single node whose two children are that triangle.
@@ -597,11 +598,30 @@ hipError_t build_bvh(BvhBuild& b, hipStream_t s) {
   }
   const int gi = (n - 1 + TB - 1) / TB;
   k_karras<<<gi, TB, 0, s>>>(keys, n, b.nodes, b.parent);
-  e = launch_fill_u32(b.flags, 0u, 2 * (size_t)(n - 1), s);  // arrival counts, then heights
+  e = launch_fill_u32(b.flags, 0u, (size_t)(n - 1), s);  // arrival counts
+  if (e == hipSuccess) e = launch_fill_u32(b.depth, 0u, 1, s);
+  if (e == hipSuccess) e = launch_fill_u32(b.level_count, 0u, kRefitLevels, s);
   if (e != hipSuccess) return e;
-  e = launch_fill_u32(b.depth, 0u, 1, s);
-  if (e != hipSuccess) return e;
-  k_refit<<<g, TB, 0, s>>>(b.tris_out, n, b.nodes, b.parent, b.flags, b.flags + (n - 1), b.depth);
+  // frontiers of even and odd levels: two n-word halves of the key buffer,
+  // free once the hierarchy is built
+  uint32_t* front[2] = {reinterpret_cast<uint32_t*>(b.keys), reinterpret_cast<uint32_t*>(b.keys) + n};
+  k_refit_leaves<<<g, TB, 0, s>>>(b.tris_out, n, b.nodes, b.parent, b.flags, front[1], b.level_count + 1);
+  // the frontier sizes are only known on the device: launch a batch of levels,
+  // then read whether the next level is empty
+  const int grid = std::min(gi, 1024);
+  const int kBatch = 16;
+  for (int level = 1;; level += kBatch) {
+    for (int l = level; l < level + kBatch; ++l) {
+      if (l + 1 >= kRefitLevels) return hipErrorInvalidValue;  // deeper than any tree of distinct 63-bit keys
+      k_refit_level<<<grid, TB, 0, s>>>(b.nodes, b.parent, b.flags, front[l & 1], b.level_count + l,
+                                        front[(l + 1) & 1], b.level_count + l + 1, (uint32_t)l, b.depth);
+    }
+    uint32_t left = 0;
+    e = hipMemcpyAsync(&left, b.level_count + level + kBatch, 4, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (left == 0) break;
+  }
   k_collapse4<<<gi, TB, 0, s>>>(b.nodes, (int64_t)(n - 1), b.nodes4);
   return hipGetLastError();
 }

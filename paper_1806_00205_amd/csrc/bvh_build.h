@@ -7,6 +7,8 @@
 namespace rtmc {
 
 // BVH builder pieces
+constexpr int kRefitLevels = 256;  // node heights the bottom-up refit can reach
+
 struct BvhBuild {
   const float4* tris_in;  // [3 n] unsorted, compacted
   float4* tris_out;       // [3 n] sorted
@@ -18,7 +20,8 @@ struct BvhBuild {
   uint64_t* keys_alt;     // [n]
   uint32_t* vals_alt;     // [n]
   int32_t* parent;        // [max(n - 1, 1) + n]: internal nodes then leaves
-  uint32_t* flags;        // [2 max(n - 1, 1)]: arrival counts, then node heights
+  uint32_t* flags;        // [max(n - 1, 1)]: arrival counts of the bottom-up refit
+  uint32_t* level_count;  // [kRefitLevels]: frontier size of each refit level
   uint32_t* hist;         // radix histogram scratch
   uint32_t* depth;        // [1]
   int32_t n;

@@ -252,34 +252,74 @@ def test_bvh_single_and_empty(ctx):
 
 # ---------------------------------------------------------------- first hit
 
-def _first_hit_parity(ctx, torch, oracle_lib, mesh, rays64, min_agree, max_t=None):
-    """GPU first hits against the oracle's.  With max_t, rays whose oracle
-    path is longer (many periodic wraps, where the FP32 sum of segment
-    lengths drifts) are only checked for the GPU finding nothing earlier."""
+def _t_tolerance(mesh, rays, tri, t):
+    """Bound on |t_GPU - t_oracle| from the FP32 arithmetic of the GPU path.
+
+    Every plane the path crosses -- each periodic wrap face, then the plane it
+    ends on (the hit triangle, the substrate or the exit face) -- is located to
+    within 16 half-ulps of the cell's largest coordinate magnitude; along the
+    ray that error grows as 1 / |cos| of the angle between ray and plane
+    normal (clamped at 1e-3).  At least 1e-5 relative."""
+    lo, hi = np.array(mesh.box_lo, np.float64), np.array(mesh.box_hi, np.float64)
+    q = 16 * 2.0 ** -24 * np.max(np.abs(np.concatenate([lo, hi])))
+    o, d = rays[:, :3], rays[:, 3:]
+    end = o + np.where(np.isfinite(t), t, 0.0)[:, None] * d
+    cos_end = np.ones(len(t))
+    hit = tri >= 0
+    V = mesh.verts[mesh.tris[tri[hit]]].astype(np.float64)
+    n = np.cross(V[:, 1] - V[:, 0], V[:, 2] - V[:, 0])
+    n /= np.linalg.norm(n, axis=1, keepdims=True)
+    cos_end[hit] = np.abs(np.sum(n * d[hit], axis=1))
+    cos_end[tri == -2] = np.abs(d[tri == -2, 2])
+    esc = tri == -1
+    periodic = bool(mesh.flags & 1)
+    if periodic:
+        cos_end[esc] = np.abs(d[esc, 2])
+    else:  # the exit face: the box face the end point lies on
+        gap = np.minimum(np.abs(end - lo), np.abs(end - hi))
+        cos_end[esc] = np.abs(d[esc, np.argmin(gap[esc], axis=1)])
+    planes = 1.0 / np.maximum(cos_end, 1e-3)
+    if periodic:
+        for a in (0, 1):
+            L = hi[a] - lo[a]
+            n_wrap = np.abs(np.floor((end[:, a] - lo[a]) / L) - np.floor((o[:, a] - lo[a]) / L))
+            planes += n_wrap / np.maximum(np.abs(d[:, a]), 1e-3)
+    return np.maximum(1e-5 * t, q * planes)
+
+
+def _first_hit_parity(ctx, torch, oracle_lib, mesh, rays64, min_agree, far_t=None):
+    """GPU first hits against the oracle's, ray by ray: the same element (or
+    a near-tie: a different element at the same distance) and the same path
+    length within `_t_tolerance`.  With far_t, a ray whose oracle path is
+    longer (tens of grazing periodic wraps, where FP32 re-entry points drift)
+    may meet the same triangle one or more cells earlier or later along the
+    periodic lattice: the difference of the two hit points must then be a
+    lattice vector (n_x L_x, n_y L_y, 0) to within the tolerance."""
     rays32 = rays64.astype(np.float32)
     sid = ctx.load_scene(mesh)
     tri_g, t_g = ctx.first_hit(sid, torch.from_numpy(rays32).cuda())
     tri_g = tri_g.cpu().numpy()
     t_g = t_g.cpu().numpy().astype(np.float64)
-    tri_o, t_o, _ = oracle_lib.first_hit(mesh, rays32.astype(np.float64))
-    if max_t is not None:
-        far = t_o > max_t
-        assert (t_g[far] >= max_t * (1 - 1e-5)).all()
-        tri_g, t_g, tri_o, t_o = tri_g[~far], t_g[~far], tri_o[~far], t_o[~far]
+    r = rays32.astype(np.float64)
+    tri_o, t_o, _ = oracle_lib.first_hit(mesh, r)
     agree = tri_g == tri_o
     frac = agree.mean()
     assert frac >= min_agree, (frac, np.nonzero(~agree)[0][:10])
-    # Distance tolerance: 1e-5 relative, floored by the FP32 coordinate
-    # quantum of the cell (16 half-ulps of its largest coordinate magnitude,
-    # the precision of the re-entry points of periodic wraps) for short hits.
-    L = max(max(abs(l), abs(h)) for l, h in zip(mesh.box_lo, mesh.box_hi))
-    tol = np.maximum(1e-5 * t_o, 16 * 2.0 ** -24 * L)
+    fin = tri_o >= -2  # a surface or the exit; lost rays carry no distance
+    tol = _t_tolerance(mesh, r, tri_o, t_o)
     err = np.abs(t_g - t_o)
-    bad = agree & (err > tol)
-    assert not bad.any(), list(zip(t_o[bad][:5], t_g[bad][:5]))
-    # disagreements must be near-ties: both found a surface at the same distance
-    dis = ~agree
-    assert not (dis & (err > tol)).any(), list(zip(tri_g[dis][:5], tri_o[dis][:5], t_g[dis][:5], t_o[dis][:5]))
+    ok = err <= tol
+    if far_t is not None:
+        lo, hi = np.array(mesh.box_lo, np.float64), np.array(mesh.box_hi, np.float64)
+        delta = np.where(fin & np.isfinite(t_g), t_g - t_o, 0.0)[:, None] * r[:, 3:]
+        per = np.array([hi[0] - lo[0], hi[1] - lo[1], np.inf])
+        lattice = np.where(np.isfinite(per), np.round(delta / per) * per, 0.0)
+        shifted = np.all(np.abs(delta - lattice) <= tol[:, None], axis=1)
+        ok |= (t_o > far_t) & agree & shifted
+    # the same element at the same distance; disagreements must be near-ties:
+    # both found a surface at the same distance
+    bad = fin & ~ok
+    assert not bad.any(), list(zip(tri_g[bad][:5], tri_o[bad][:5], t_g[bad][:5], t_o[bad][:5], tol[bad][:5]))
     return frac
 
 
@@ -332,15 +372,16 @@ def test_first_hit_axis_parallel_and_face_rays(ctx, torch, oracle_lib, tiny, shi
     m = fg.Mesh(tiny.verts + np.float32(shift), tiny.tris, tuple(v + shift for v in tiny.box_lo),
                 tuple(v + shift for v in tiny.box_hi), tiny.flags, {})
     L = max(h - l for l, h in zip(m.box_lo, m.box_hi))
-    _first_hit_parity(ctx, torch, oracle_lib, m, _axis_rays(m, 3000, seed=21), 0.999, max_t=4 * L)
+    for seed in (21, 22):
+        _first_hit_parity(ctx, torch, oracle_lib, m, _axis_rays(m, 3000, seed=seed), 0.9998, far_t=4 * L)
 
 
 @pytest.mark.slow
 def test_first_hit_sample_of_128_foam(ctx, torch, oracle_lib):
     """Subsample of rays on the 128^3, porosity 0.6 foam (about 1.9M triangles)."""
     m = fg.make_grf_foam(128, 0.6, 2.0, seed=1)
-    rays = np.concatenate([fg.top_rays(m, 1500, seed=11), fg.surface_rays(m, 1500, seed=12)])
-    _first_hit_parity(ctx, torch, oracle_lib, m, rays, 0.999)
+    rays = np.concatenate([fg.top_rays(m, 3000, seed=11), fg.surface_rays(m, 3000, seed=12)])
+    _first_hit_parity(ctx, torch, oracle_lib, m, rays, 0.9998)
 
 
 # ---------------------------------------------------------------- cascades
@@ -424,8 +465,8 @@ def test_full_size_sweep_batch_equals_single_traces(ctx, vaughan):
 
 @pytest.mark.slow
 @pytest.mark.parametrize("grid,porosity,seed,theta,n,max_gen,k", [
-    (128, 0.6, 1, 40.0, 10_000_000, 6, 256),   # one point of the 128^3 sweep (1.91M triangles)
-    (256, 0.8, 4, -80.0, 100_000_000, 10, 64),  # the 256^3 run (11.0M triangles), random incidence
+    (128, 0.6, 1, 40.0, 10_000_000, 6, 512),    # one point of the 128^3 sweep (1.91M triangles)
+    (256, 0.8, 4, -80.0, 100_000_000, 10, 192),  # the 256^3 run (11.0M triangles), random incidence
 ])
 def test_full_size_point_sampled_against_oracle(ctx, torch, oracle_lib, vaughan, grid, porosity, seed, theta, n,
                                                 max_gen, k):
@@ -441,7 +482,9 @@ def test_full_size_point_sampled_against_oracle(ctx, torch, oracle_lib, vaughan,
     o = oracle_lib.trace(m, vaughan, 250.0, theta, k, seed=2000 + seed, max_gen=max_gen, per_primary=True)
     ppg = pp[:k].cpu().numpy().astype(np.int64)
     same = (ppg == o["per_primary"]["escaped"].astype(np.int64)).mean()
-    assert same >= 0.97, same
+    # a primary's whole cascade must take the same branches on both sides; at
+    # most one cascade in a hundred may part at a near-tie (observed: none)
+    assert same >= 0.99, same
     assert int(pp.sum().item()) == g["n_escaped"]
     assert g["e_escaped"] + g["e_deposited"] == pytest.approx(250.0 * n, rel=1e-12)
     assert g["n_rays"] == g["n_escaped"] + g["n_absorbed"] + g["n_truncated"] + g["n_lost"] == n + g["n_spawned"]
