@@ -123,6 +123,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-sub", action="store_true", help="headline workload only (no c1 / surrogate records)")
+    ap.add_argument("--workers", type=int, default=0,
+                    help="foam-generation processes of the batched workload (0: up to 16, one per host core)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py: this build runs on one GPU only; the multi-GPU path (shard primary ids, one "
@@ -413,13 +415,22 @@ def bench_batched(args, cfg, npp):
     tid = ctx.load_tables(tab)
     scenes, tris = [], 0
     t0 = time.time()
+    specs = []
     for i in range(cfg["n_foams"]):
         n = int(rng.choice(cfg["sizes"]))
         p = float(rng.uniform(0.2, 0.8))
-        m = fg.make_grf_foam(n, p, 2.0, seed=1000 + i)
-        scenes.append((ctx.load_scene(m), n, p, m.n_tris))
-        tris += m.n_tris
-        log(f"foam {i + 1}/{cfg['n_foams']}: {n}^3, porosity {p:.2f}, {m.n_tris} triangles")
+        specs.append((1000 + i, n, p))
+    # the foams are CPU work: generated in worker processes, loaded as they arrive
+    import multiprocessing as mp
+
+    from foamgen.batch import grf_foam
+    workers = args.workers or max(1, min(16, len(os.sched_getaffinity(0))))
+    with mp.get_context("spawn").Pool(workers) as pool:
+        for i, m in enumerate(pool.imap(grf_foam, specs)):
+            _, n, p = specs[i]
+            scenes.append((ctx.load_scene(m), n, p, m.n_tris))
+            tris += m.n_tris
+            log(f"foam {i + 1}/{cfg['n_foams']}: {n}^3, porosity {p:.2f}, {m.n_tris} triangles")
     log(f"{len(scenes)} foams, {tris} triangles in {time.time() - t0:.0f} s")
     mid = sorted(scenes, key=lambda x: x[3])[len(scenes) // 2][0]
     tuned = ctx.autotune(mid, tid, 250.0, 40.0, 2_000_000)

@@ -13,3 +13,9 @@ def foam_with_descriptors(spec):
     field = foam_field(n, p, ell, seed=seed)
     mesh = make_grf_foam(n, p, ell, seed=seed, field=field)
     return mesh, foam_descriptors(mesh, *field)
+
+
+def grf_foam(spec):
+    """spec = (seed, n, porosity) -> the GRF foam mesh (correlation length 2 voxels)."""
+    seed, n, p = spec
+    return make_grf_foam(int(n), float(p), 2.0, seed=int(seed))

@@ -301,8 +301,10 @@ rtmc_status rtmc_get_launch(rtmc_ctx* ctx, rtmc_launch_cfg* cfg);
  * E_eV, theta_deg) and keep the fastest, also returned in *best.  Coordinate
  * search over block size, workgroups per compute unit, LDS stack depth,
  * refill threshold, kernel build (waves per SIMD), rays per wave per claim
- * and primaries per chunk (chunks of the calibration trace, at most
- * n_primaries).  The winner is cached for the process, keyed by the GPU
+ * and primaries per chunk (a half, quarter or eighth of n_primaries, else the
+ * current chunk, which the calibration trace cannot tell from any other of at
+ * least its length); a change is kept only if it is more than 2 % faster.
+ * The winner is cached for the process, keyed by the GPU
  * (architecture, compute units), the scene's size (triangles as a power of
  * two, BVH depth), the tables' largest yield and the calibration point: a
  * call with the same key takes the cached shape without timing. */

@@ -1346,6 +1346,8 @@ rtmc_status rtmc_get_launch(rtmc_ctx* c, rtmc_launch_cfg* cfg) {
   return RTMC_OK;
 }
 
+constexpr double kTuneMargin = 0.02;  // relative gain a launch-shape change must show on the probe
+
 rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, double E_eV, double theta_deg,
                           uint64_t n_primaries, rtmc_launch_cfg* best) {
   rtmc_status st = check_scene(c, scene_id, true);
@@ -1382,11 +1384,15 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
     c->cfg = keep;
     return st;
   }
-  // chunk candidates: the whole calibration trace, and halves, quarters, eighths of it
+  // chunk candidates: halves, quarters, eighths of the calibration trace.  Any
+  // chunk of at least its length traces it as one chunk, so the probe cannot
+  // tell such chunks apart: the current one (usually far larger, as a batch
+  // needs) is the baseline and is never replaced by an equivalent of the
+  // probe's own length.
   std::vector<int32_t> chunks;
-  for (int k = 0; k < 4; ++k) {
-    const uint64_t ch = std::max<uint64_t>(1, n_primaries >> k);
-    if (ch >= 4096 || k == 0) chunks.push_back((int32_t)std::min<uint64_t>(ch, 1u << 30));
+  for (int k = 1; k < 4; ++k) {
+    const uint64_t ch = n_primaries >> k;
+    if (ch >= 4096) chunks.push_back((int32_t)std::min<uint64_t>(ch, 1u << 30));
   }
   const std::vector<std::vector<int32_t>> knobs = {
       {64, 128, 256},                    // block
@@ -1418,7 +1424,8 @@ rtmc_status rtmc_autotune(rtmc_ctx* c, int32_t scene_id, int32_t table_id, doubl
           c->cfg = keep;
           return st;
         }
-        if (ms < best_ms) {
+        // a change must win by more than the probe's timing noise
+        if (ms < best_ms * (1.0 - kTuneMargin)) {
           best_ms = ms;
           cur = cf;
         }

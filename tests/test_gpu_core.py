@@ -721,7 +721,9 @@ def test_autotune_keeps_results(ctx, tiny, vaughan):
         assert best == ctx.get_launch()
         assert best["block"] in (64, 128, 256) and best["wg_per_cu"] >= 1 and 1 <= best["refill"] <= 64
         assert best["claim"] in (512, 1024, 2048, 4096, 8192)
-        assert best["chunk"] in (20000, 10000, 5000, cfg["chunk"])
+        # chunks of at least the calibration trace's length are all one chunk to
+        # it: the current chunk stays unless a real split (a half, a quarter) wins
+        assert best["chunk"] in (10000, 5000, cfg["chunk"])
         after = ctx.trace(sid, tid, 300.0, 20.0, 8000, seed=29)
         for k in ("n_rays", "n_escaped", "n_absorbed", "n_node_visits", "n_tri_tests", "e_escaped", "e_deposited"):
             assert before[k] == after[k], k
