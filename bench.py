@@ -383,10 +383,11 @@ def bench_surrogate(ctx, rtmc):
     stream), and its gain over RTMC at the held-out error of the committed
     experiment: RTMC needs (sigma_1 / MAE)^2 primaries per yield at that
     error, sigma_1 being the per-primary spread of the held-out yields."""
-    from paper_1806_00205_amd.surrogate import bench_inference
+    from paper_1806_00205_amd.surrogate import bench_inference, bench_training
 
     srg = ctx.srg_create(8, 256, 4, seed=0)
     inf = bench_inference(ctx, srg, n=1_000_000, reps=20)
+    train = bench_training(ctx)
     # held-out experiment (python -m paper_1806_00205_amd.surrogate --train-foams 1024 --points 96
     # --test-foams 256 --steps 8000): MAE 0.0100 over 256 x 25 points judged by RTMC at 1e6 primaries,
     # which need 4006 primaries per yield for sigma = MAE
@@ -398,7 +399,8 @@ def bench_surrogate(ctx, rtmc):
             "heldout_mae": mae, "heldout_source": "profiles/surrogate_vs_rtmc_heldout.md",
             "rtmc_primaries_per_yield_at_mae": prim_per_yield,
             "rtmc_yields_per_s_at_mae": rate / prim_per_yield,
-            "gain_vs_rtmc": inf["queries_per_s"] / (rate / prim_per_yield)}
+            "gain_vs_rtmc": inf["queries_per_s"] / (rate / prim_per_yield),
+            "training": train}
 
 
 def bench_batched(args, cfg, npp):

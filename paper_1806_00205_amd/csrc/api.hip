@@ -47,10 +47,11 @@ struct Surrogate {
   int64_t n_pub = 0, n_pad = 0;  // public and padded (first layer 32 wide) parameter counts
   DevBuf master, mom1, mom2, grad;  // FP32, padded layout
   DevBuf wbf;                       // BF16 weights: W_l and W_l^T per layer
-  DevBuf ws;                        // batch workspace
-  int64_t ws_rows = 0;
   int64_t step = 0;
-  // device training loop: state words, learning rates, losses, the sampled batch
+  // fused training: per-workgroup gradient slices, loss slices, pre-activations, loss word
+  DevBuf tws;
+  int tws_grid = 0;
+  // device training loop: state words, learning rates, losses
   DevBuf tbuf;
   hipGraphExec_t tgexec = nullptr;  // one loop step, captured
   std::vector<uint64_t> tkey;       // what that capture depends on
@@ -759,7 +760,7 @@ void rtmc_destroy(rtmc_ctx* c) {
     dev_free(c, g.mom2);
     dev_free(c, g.grad);
     dev_free(c, g.wbf);
-    dev_free(c, g.ws);
+    dev_free(c, g.tws);
   }
   dev_free(c, c->queue[0]);
   dev_free(c, c->queue[1]);
@@ -1499,43 +1500,6 @@ int64_t srg_wbf_off(const Surrogate& g, int l, bool transposed) {
   return o + (transposed ? (int64_t)g.width * kin : 0);
 }
 
-struct SrgWs {
-  __bf16 *X, *Xt;
-  float* Z[5];
-  __bf16 *H[5], *Ht[5];
-  __bf16 *G[2], *Gt[2];
-  float *y, *dy, *acc;
-};
-
-// workspace for `rows` rows: X, Xt, Z1..4, H1..4, Ht1..4, two G ping-pongs, y, dy, acc
-SrgWs srg_ws(Surrogate& g, int64_t rows) {
-  SrgWs w{};
-  char* p = reinterpret_cast<char*>(g.ws.p);
-  const size_t R = (size_t)rows, W = (size_t)g.width;
-  auto take = [&](size_t bytes) {
-    char* q = p;
-    p += (bytes + 255) & ~(size_t)255;
-    return q;
-  };
-  w.X = reinterpret_cast<__bf16*>(take(R * kPadIn * 2));
-  w.Xt = reinterpret_cast<__bf16*>(take(R * kPadIn * 2));
-  for (int l = 1; l <= 4; ++l) w.Z[l] = reinterpret_cast<float*>(take(R * W * 4));
-  for (int l = 1; l <= 4; ++l) w.H[l] = reinterpret_cast<__bf16*>(take(R * W * 2));
-  for (int l = 1; l <= 4; ++l) w.Ht[l] = reinterpret_cast<__bf16*>(take(R * W * 2));
-  for (int i = 0; i < 2; ++i) w.G[i] = reinterpret_cast<__bf16*>(take(R * W * 2));
-  for (int i = 0; i < 2; ++i) w.Gt[i] = reinterpret_cast<__bf16*>(take(R * W * 2));
-  w.y = reinterpret_cast<float*>(take(R * 4));
-  w.dy = reinterpret_cast<float*>(take(R * 4));
-  w.acc = reinterpret_cast<float*>(take(64));
-  return w;
-}
-
-size_t srg_ws_total(const Surrogate& g, int64_t rows) {
-  const size_t R = (size_t)rows, W = (size_t)g.width;
-  auto r = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  return 2 * r(R * kPadIn * 2) + 4 * r(R * W * 4) + 8 * r(R * W * 2) + 4 * r(R * W * 2) + 2 * r(R * 4) + r(64);
-}
-
 rtmc_status srg_check(rtmc_ctx* c, int32_t id) {
   if (!c) return RTMC_EINVAL;
   c->err.clear();
@@ -1555,98 +1519,80 @@ rtmc_status srg_refresh_bf16(rtmc_ctx* c, Surrogate& g) {
   return RTMC_OK;
 }
 
-// Forward over `rows` rows of X; training keeps Z, H^T and X^T for the backward.
-rtmc_status srg_forward(rtmc_ctx* c, Surrogate& g, const float* X, int64_t rows, bool train, const SrgWs& w,
-                        float* y_out) {
-  const SrgLayout L = srg_layout(g);
-  const float* m = reinterpret_cast<const float*>(g.master.p);
-  const __bf16* wb = reinterpret_cast<const __bf16*>(g.wbf.p);
-  const int R = (int)rows;
-  HIPCHK(c, mlp_pack_input(X, R, g.n_in, w.X, train ? w.Xt : nullptr, c->stream));
-  for (int l = 1; l <= g.depth; ++l) {
-    MlpGemm q{};
-    const int kin = l == 1 ? kPadIn : g.width;
-    q.A = l == 1 ? w.X : w.H[l - 1];
-    q.lda = kin;
-    q.B = wb + srg_wbf_off(g, l, false);
-    q.ldb = kin;
-    q.M = R;
-    q.N = g.width;
-    q.K = kin;
-    q.epi = MLP_EPI_FWD_GELU;
-    q.bias = m + L.b[l];
-    q.Z = train ? w.Z[l] : nullptr;
-    q.ldz = g.width;
-    q.H = w.H[l];
-    q.ldh = g.width;
-    q.Ht = train ? w.Ht[l] : nullptr;
-    q.ldht = R;
-    HIPCHK(c, mlp_gemm(q, c->stream));
-  }
-  HIPCHK(c, mlp_out_fwd(w.H[g.depth], R, g.width, m + L.wout, m + L.bout, y_out, c->stream));
-  return RTMC_OK;
-}
+// ---- fused training (two launches per step, mlp.hip)
+struct SrgTrainWs {
+  float *part, *loss_part, *zbuf, *acc;
+  int grid;
+};
 
-// Loss and gradients (padded layout, into g.grad) for one batch.
-rtmc_status srg_backward(rtmc_ctx* c, Surrogate& g, const float* y_true, int64_t rows, const SrgWs& w) {
-  const SrgLayout L = srg_layout(g);
-  const float* m = reinterpret_cast<const float*>(g.master.p);
-  const __bf16* wb = reinterpret_cast<const __bf16*>(g.wbf.p);
-  float* gr = reinterpret_cast<float*>(g.grad.p);
-  const int R = (int)rows, Wd = g.width;
-  HIPCHK(c, launch_fill_u32(reinterpret_cast<uint32_t*>(w.acc), 0u, 2, c->stream));
-  HIPCHK(c, mlp_mse(w.y, y_true, R, w.dy, w.acc, c->stream));
-  // output layer
-  HIPCHK(c, mlp_rowsum(w.Ht[g.depth], Wd, R, w.dy, gr + L.wout, c->stream));
-  HIPCHK(c, hipMemcpyAsync(gr + L.bout, w.acc + 1, 4, hipMemcpyDeviceToDevice, c->stream));
-  int cur = 0;
-  HIPCHK(c, mlp_out_bwd_hidden(w.dy, m + L.wout, w.Z[g.depth], R, Wd, w.G[cur], w.Gt[cur], c->stream));
-  for (int l = g.depth; l >= 1; --l) {
-    const int kin = l == 1 ? kPadIn : Wd;
-    // dW_l = G^T H_{l-1}  (FP32)
-    MlpGemm q{};
-    q.A = w.Gt[cur];
-    q.lda = R;
-    q.B = l == 1 ? w.Xt : w.Ht[l - 1];
-    q.ldb = R;
-    q.M = Wd;
-    q.N = kin;
-    q.K = R;
-    q.epi = MLP_EPI_F32;
-    q.C = gr + L.W[l];
-    q.ldc = kin;
-    HIPCHK(c, mlp_gemm(q, c->stream));
-    HIPCHK(c, mlp_rowsum(w.Gt[cur], Wd, R, nullptr, gr + L.b[l], c->stream));
-    if (l > 1) {
-      // G_{l-1} = (G W_l) * GELU'(Z_{l-1})
-      MlpGemm d{};
-      d.A = w.G[cur];
-      d.lda = Wd;
-      d.B = wb + srg_wbf_off(g, l, true);
-      d.ldb = Wd;
-      d.M = R;
-      d.N = Wd;
-      d.K = Wd;
-      d.epi = MLP_EPI_BWD_GELU;
-      d.Zs = w.Z[l - 1];
-      d.ldz = Wd;
-      d.H = w.G[cur ^ 1];
-      d.ldh = Wd;
-      d.Ht = w.Gt[cur ^ 1];
-      d.ldht = R;
-      HIPCHK(c, mlp_gemm(d, c->stream));
-      cur ^= 1;
-    }
-  }
-  return RTMC_OK;
-}
-
-rtmc_status srg_ensure_ws(rtmc_ctx* c, Surrogate& g, int64_t rows) {
-  if (g.ws.p && g.ws_rows >= rows) return RTMC_OK;
-  rtmc_status st = ensure(c, g.ws, srg_ws_total(g, rows));
+rtmc_status srg_train_ws(rtmc_ctx* c, Surrogate& g, int64_t batch, SrgTrainWs& w) {
+  if (mlp_train_lds_bytes() > c->lds_per_block)
+    return fail(c, RTMC_ENOTIMPL, "surrogate training needs %zu bytes of LDS per workgroup (device limit %zu)",
+                mlp_train_lds_bytes(), c->lds_per_block);
+  const int grid = mlp_train_grid((int)batch);
+  auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+  const size_t o_loss = up((size_t)grid * g.n_pad * 4), o_z = o_loss + up((size_t)kTrainMaxWg * 4);
+  const size_t o_acc = o_z + up((size_t)grid * 3 * kTrainRows * 256 * 4), total = o_acc + 256;
+  rtmc_status st = ensure(c, g.tws, total);
   if (st) return st;
-  g.ws_rows = rows;
+  char* b = static_cast<char*>(g.tws.p);
+  w.part = reinterpret_cast<float*>(b);
+  w.loss_part = reinterpret_cast<float*>(b + o_loss);
+  w.zbuf = reinterpret_cast<float*>(b + o_z);
+  w.acc = reinterpret_cast<float*>(b + o_acc);
+  w.grid = grid;
   return RTMC_OK;
+}
+
+MlpTrain srg_train_args(const Surrogate& g, const SrgTrainWs& w, int64_t batch) {
+  const SrgLayout L = srg_layout(g);
+  const __bf16* wb = reinterpret_cast<const __bf16*>(g.wbf.p);
+  MlpTrain t{};
+  t.master = reinterpret_cast<const float*>(g.master.p);
+  for (int l = 1; l <= 4; ++l) {
+    t.W[l - 1] = wb + srg_wbf_off(g, l, false);
+    t.Wt[l - 1] = wb + srg_wbf_off(g, l, true);
+    t.off_W[l - 1] = L.W[l];
+    t.off_b[l - 1] = L.b[l];
+  }
+  t.off_wout = L.wout;
+  t.off_bout = L.bout;
+  t.n_par = L.total;
+  t.batch = (int)batch;
+  t.n_in = g.n_in;
+  t.zbuf = w.zbuf;
+  t.part = w.part;
+  t.loss_part = w.loss_part;
+  return t;
+}
+
+// Reduction of the slices into g.grad and the loss into w.acc[0]; with an
+// update, AdamW on the masters and the BF16 weight copies.
+MlpUpdate srg_update_args(Surrogate& g, const SrgTrainWs& w, bool update) {
+  const SrgLayout L = srg_layout(g);
+  __bf16* wb = reinterpret_cast<__bf16*>(g.wbf.p);
+  MlpUpdate u{};
+  u.part = w.part;
+  u.loss_part = w.loss_part;
+  u.n_part = w.grid;
+  u.n_par = L.total;
+  u.grad = reinterpret_cast<float*>(g.grad.p);
+  u.acc = w.acc;
+  if (update) {
+    u.p = reinterpret_cast<float*>(g.master.p);
+    u.m = reinterpret_cast<float*>(g.mom1.p);
+    u.v = reinterpret_cast<float*>(g.mom2.p);
+  }
+  u.b1 = 0.9f;
+  u.b2 = 0.999f;
+  u.eps = 1e-8f;
+  for (int l = 1; l <= 4; ++l) {
+    u.Wb[l - 1] = wb + srg_wbf_off(g, l, false);
+    u.Wtb[l - 1] = wb + srg_wbf_off(g, l, true);
+    u.off_W[l - 1] = L.W[l];
+    u.kin[l - 1] = l == 1 ? kPadIn : g.width;
+  }
+  return u;
 }
 
 void pub_to_pad(const Surrogate& g, const float* pub, std::vector<float>& pad) {
@@ -1786,17 +1732,18 @@ rtmc_status rtmc_srg_gradient(rtmc_ctx* c, int32_t id, const float* X, const flo
   Surrogate& g = c->srgs[id];
   if (!X || !y || batch < 32 || batch % 32 || batch > (1 << 22)) return fail(c, RTMC_EINVAL, "batch must be a positive multiple of 32");
   HIPCHK(c, hipSetDevice(c->device));
-  st = srg_ensure_ws(c, g, batch);
+  SrgTrainWs w;
+  st = srg_train_ws(c, g, batch, w);
   if (st) return st;
-  const SrgWs w = srg_ws(g, batch);
-  st = srg_forward(c, g, X, batch, true, w, w.y);
-  if (st) return st;
-  st = srg_backward(c, g, y, batch, w);
-  if (st) return st;
-  float acc[2] = {0.f, 0.f};
+  MlpTrain t = srg_train_args(g, w, batch);
+  t.x = X;
+  t.t = y;
+  HIPCHK(c, mlp_train_rows(t, c->stream));
+  HIPCHK(c, mlp_train_update(srg_update_args(g, w, false), c->stream));
+  float acc = 0.f;
+  HIPCHK(c, hipMemcpyAsync(&acc, w.acc, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  HIPCHK(c, hipMemcpy(acc, w.acc, 8, hipMemcpyDeviceToHost));
-  if (loss) *loss = acc[0];
+  if (loss) *loss = acc;
   if (grads) {
     std::vector<float> pad((size_t)g.n_pad);
     HIPCHK(c, hipMemcpy(pad.data(), g.grad.p, pad.size() * 4, hipMemcpyDeviceToHost));
@@ -1813,26 +1760,25 @@ rtmc_status rtmc_srg_train_step(rtmc_ctx* c, int32_t id, const float* X, const f
   if (!X || !y || batch < 32 || batch % 32 || batch > (1 << 22)) return fail(c, RTMC_EINVAL, "batch must be a positive multiple of 32");
   if (!(lr > 0.0f) || !(weight_decay >= 0.0f)) return fail(c, RTMC_EINVAL, "bad learning rate or weight decay");
   HIPCHK(c, hipSetDevice(c->device));
-  st = srg_ensure_ws(c, g, batch);
+  SrgTrainWs w;
+  st = srg_train_ws(c, g, batch, w);
   if (st) return st;
-  const SrgWs w = srg_ws(g, batch);
-  st = srg_forward(c, g, X, batch, true, w, w.y);
-  if (st) return st;
-  st = srg_backward(c, g, y, batch, w);
-  if (st) return st;
+  MlpTrain t = srg_train_args(g, w, batch);
+  t.x = X;
+  t.t = y;
+  HIPCHK(c, mlp_train_rows(t, c->stream));
   g.step += 1;
-  const float b1 = 0.9f, b2 = 0.999f;
-  const float c1 = 1.0f - (float)std::pow(b1, (double)g.step), c2 = 1.0f - (float)std::pow(b2, (double)g.step);
-  HIPCHK(c, mlp_adamw(reinterpret_cast<float*>(g.master.p), reinterpret_cast<float*>(g.mom1.p),
-                      reinterpret_cast<float*>(g.mom2.p), reinterpret_cast<const float*>(g.grad.p), g.n_pad, lr, b1,
-                      b2, 1e-8f, weight_decay, c1, c2, c->stream));
-  st = srg_refresh_bf16(c, g);
-  if (st) return st;
+  MlpUpdate u = srg_update_args(g, w, true);
+  u.lr = lr;
+  u.wd = weight_decay;
+  u.c1 = 1.0f - (float)std::pow((double)u.b1, (double)g.step);
+  u.c2 = 1.0f - (float)std::pow((double)u.b2, (double)g.step);
+  HIPCHK(c, mlp_train_update(u, c->stream));
   if (loss) {
-    float acc[2] = {0.f, 0.f};
-    HIPCHK(c, hipMemcpyAsync(acc, w.acc, 8, hipMemcpyDeviceToHost, c->stream));
+    float acc = 0.f;
+    HIPCHK(c, hipMemcpyAsync(&acc, w.acc, 4, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    *loss = acc[0];
+    *loss = acc;
   }
   return RTMC_OK;
 }
@@ -1850,36 +1796,35 @@ rtmc_status rtmc_srg_train(rtmc_ctx* c, int32_t id, const float* X, const float*
   for (int32_t s = 0; s < steps; ++s)
     if (!(lr[s] > 0.0f) || !std::isfinite(lr[s])) return fail(c, RTMC_EINVAL, "learning rate %d not positive", s);
   HIPCHK(c, hipSetDevice(c->device));
-  st = srg_ensure_ws(c, g, batch);
+  SrgTrainWs w;
+  st = srg_train_ws(c, g, batch, w);
   if (st) return st;
-  // loop buffer: 2 state words (padded to 256 B), lr[steps], losses[steps], Xb [batch, n_in], yb [batch]
+  // loop buffer: 2 state words (padded to 256 B), lr[steps], losses[steps]
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t o_lr = 256, o_loss = o_lr + up((size_t)steps * 4), o_xb = o_loss + up((size_t)steps * 4);
-  const size_t o_yb = o_xb + up((size_t)batch * g.n_in * 4), total = o_yb + up((size_t)batch * 4);
+  const size_t o_lr = 256, o_loss = o_lr + up((size_t)steps * 4), total = o_loss + up((size_t)steps * 4);
   st = ensure(c, g.tbuf, total);
   if (st) return st;
   char* base = static_cast<char*>(g.tbuf.p);
   uint32_t* state = reinterpret_cast<uint32_t*>(base);
   float* lr_d = reinterpret_cast<float*>(base + o_lr);
   float* loss_d = reinterpret_cast<float*>(base + o_loss);
-  float* Xb = reinterpret_cast<float*>(base + o_xb);
-  float* yb = reinterpret_cast<float*>(base + o_yb);
   HIPCHK(c, hipMemcpyAsync(lr_d, lr, (size_t)steps * 4, hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, launch_fill_u32(state, (uint32_t)g.step, 2, c->stream));
-  const SrgLayout L = srg_layout(g);
-  const SrgWs w = srg_ws(g, batch);
-  // one step: batch on the device, forward, backward, AdamW, BF16 weights, loss out
+  MlpTrain targs = srg_train_args(g, w, batch);
+  targs.src_x = X;
+  targs.src_t = y;
+  targs.n_src = (uint32_t)n;
+  targs.seed = seed;
+  targs.state = state;
+  MlpUpdate uargs = srg_update_args(g, w, true);
+  uargs.lr_sched = lr_d;
+  uargs.state = state;
+  uargs.wd = weight_decay;
+  // one step: rows drawn on the device, forward, backward and gradient slices
+  // in one launch; their sum, AdamW and the BF16 weights in the next; loss out
   auto one_step = [&]() -> rtmc_status {
-    HIPCHK(c, mlp_sample_batch(X, y, (uint32_t)n, g.n_in, (int)batch, seed, state, Xb, yb, c->stream));
-    rtmc_status s2 = srg_forward(c, g, Xb, batch, true, w, w.y);
-    if (s2) return s2;
-    s2 = srg_backward(c, g, yb, batch, w);
-    if (s2) return s2;
-    HIPCHK(c, mlp_adamw_loop(reinterpret_cast<float*>(g.master.p), reinterpret_cast<float*>(g.mom1.p),
-                             reinterpret_cast<float*>(g.mom2.p), reinterpret_cast<const float*>(g.grad.p), L.total,
-                             lr_d, state, 0.9f, 0.999f, 1e-8f, weight_decay, c->stream));
-    s2 = srg_refresh_bf16(c, g);
-    if (s2) return s2;
+    HIPCHK(c, mlp_train_rows(targs, c->stream));
+    HIPCHK(c, mlp_train_update(uargs, c->stream));
     HIPCHK(c, mlp_step_done(state, w.acc, loss_d, c->stream));
     return RTMC_OK;
   };
@@ -1892,7 +1837,7 @@ rtmc_status rtmc_srg_train(rtmc_ctx* c, int32_t id, const float* X, const float*
     uint32_t wd_bits;
     std::memcpy(&wd_bits, &weight_decay, 4);
     const std::vector<uint64_t> key = {(uint64_t)(uintptr_t)X, (uint64_t)(uintptr_t)y, (uint64_t)n, (uint64_t)batch,
-                                       seed, (uint64_t)(uintptr_t)g.tbuf.p, (uint64_t)(uintptr_t)g.ws.p,
+                                       seed, (uint64_t)(uintptr_t)g.tbuf.p, (uint64_t)(uintptr_t)g.tws.p,
                                        (uint64_t)(uintptr_t)g.master.p, (uint64_t)steps, wd_bits};
     // the step runs on the context's own capture stream, ordered after the work above
     HIPCHK(c, hipEventRecord(c->ev0, c->stream));

@@ -4,12 +4,10 @@
 // BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16), with bias,
 // GELU and its derivative fused into the GEMM epilogues.
 //
-// One GEMM shape serves the forward and both backward products: C = A * B^T
-// with A [M, K] and B [N, K] both K-contiguous (row-major), K a multiple of 32.
-//   forward       Z_l  = H_{l-1} W_l^T        (A = H_{l-1} [B, K],  B = W_l [N, K])
-//   input grad    dH   = G_l W_l              (A = G_l [B, N],      B = W_l^T [K, N])
-//   weight grad   dW_l = G_l^T H_{l-1}        (A = G_l^T [N, B],    B = H_{l-1}^T [K, B])
-// so activations and gradients are written in both layouts by the epilogues.
+// Training runs as two launches per step (k_mlp_train_rows: forward,
+// backward and per-workgroup gradient slices of 32-row tiles with the
+// activations in LDS; k_mlp_train_update: the slices' sum, AdamW and the BF16
+// weight copies); inference as one (k_mlp_infer: all layers of a 128-row tile).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -39,199 +37,13 @@ __device__ inline float gelu_d(float x) {
   return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
 }
 
-// Workgroup tile 64 x 64, four waves of 32 x 32 (2 x 2 MFMA blocks of 16 x 16).
 // Fragment layout of the 16x16x32 BF16 MFMA (lane l):
 //   A: row l % 16, k = 8 (l / 16) .. + 7;  B: column l % 16, same k;
 //   C: column l % 16, rows 4 (l / 16) .. + 3.
-__global__ __launch_bounds__(256) void k_gemm_nt(MlpGemm g) {
-  const int w = threadIdx.x >> 6;
-  const uint32_t l = lane_id();
-  const int m0 = blockIdx.x * 64 + (w >> 1) * 32;
-  const int n0 = blockIdx.y * 64 + (w & 1) * 32;
-  const int r = l & 15, kg = (l >> 4) * 8;
-  f32x4 acc[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
-  const bf16x8 zero8 = {};
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
-    bf16x8 a[2], b[2];
-#pragma unroll
-    for (int i = 0; i < 2; ++i) {
-      const int m = m0 + 16 * i + r;
-      a[i] = m < g.M ? *(const GAS bf16x8*)(g.A + (size_t)m * g.lda + k0 + kg) : zero8;
-      const int n = n0 + 16 * i + r;
-      b[i] = n < g.N ? *(const GAS bf16x8*)(g.B + (size_t)n * g.ldb + k0 + kg) : zero8;
-    }
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
-  }
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int n = n0 + 16 * j + (l & 15);
-      if (n >= g.N) continue;
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int m = m0 + 16 * i + 4 * (l >> 4) + q;
-        if (m >= g.M) continue;
-        const float v = acc[i][j][q];
-        if (g.epi == MLP_EPI_F32) {
-          g.C[(size_t)m * g.ldc + n] = v;
-        } else if (g.epi == MLP_EPI_FWD_GELU) {
-          const float z = v + g.bias[n];
-          const float h = gelu(z);
-          if (g.Z) g.Z[(size_t)m * g.ldz + n] = z;
-          g.H[(size_t)m * g.ldh + n] = (__bf16)h;
-          if (g.Ht) g.Ht[(size_t)n * g.ldht + m] = (__bf16)h;
-        } else {  // MLP_EPI_BWD_GELU: dZ = dH * GELU'(Z)
-          const float d = v * gelu_d(g.Zs[(size_t)m * g.ldz + n]);
-          g.H[(size_t)m * g.ldh + n] = (__bf16)d;
-          if (g.Ht) g.Ht[(size_t)n * g.ldht + m] = (__bf16)d;
-        }
-      }
-    }
-}
-
-// Inputs: float [B, n_in] -> bf16 [B, 32] (zero padded) and its transpose [32, B].
-__global__ void k_pack_input(const float* __restrict__ x, int B, int n_in, __bf16* __restrict__ X,
-                             __bf16* __restrict__ Xt) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  for (int k = 0; k < 32; ++k) {
-    const __bf16 v = (__bf16)(k < n_in ? x[(size_t)b * n_in + k] : 0.0f);
-    X[(size_t)b * 32 + k] = v;
-    if (Xt) Xt[(size_t)k * B + b] = v;
-  }
-}
-
-// Output layer: y = H w + c (one wave per 64 rows, FP32 accumulation).
-__global__ void k_out_fwd(const __bf16* __restrict__ H, int B, int width, const float* __restrict__ w,
-                          const float* __restrict__ c, float* __restrict__ y) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= B) return;
-  float s = c[0];
-  const __bf16* h = H + (size_t)b * width;
-  for (int k = 0; k < width; ++k) s += (float)h[k] * w[k];
-  y[b] = s;
-}
-
-// Loss and output gradient of a batch: dy[b] = 2 (y[b] - t[b]) / B, and
-// acc = (mean squared error, sum of dy = the output bias gradient).  One workgroup, each thread summing
-// a fixed stride of rows, then a fixed tree: the sums do not depend on
-// scheduling, so training is reproducible bit for bit.
-__global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t, int B, float* __restrict__ dy,
-                      float* __restrict__ acc) {
-  __shared__ float part[2][256];
-  float e = 0.f, g = 0.f;
-  for (int b = threadIdx.x; b < B; b += blockDim.x) {
-    const float d = y[b] - t[b];
-    const float gb = 2.0f * d / (float)B;
-    dy[b] = gb;
-    g += gb;
-    e += d * d / (float)B;
-  }
-  part[0][threadIdx.x] = e;
-  part[1][threadIdx.x] = g;
-  __syncthreads();
-  for (int s = 128; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) {
-      part[0][threadIdx.x] += part[0][threadIdx.x + s];
-      part[1][threadIdx.x] += part[1][threadIdx.x + s];
-    }
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) {
-    acc[0] = part[0][0];
-    acc[1] = part[1][0];
-  }
-}
-
-// Backward of the output layer into the last hidden layer:
-//   G[b, k] = dy[b] w[k] GELU'(Z[b, k]) (bf16, both layouts).
-__global__ void k_out_bwd_hidden(const float* __restrict__ dy, const float* __restrict__ w,
-                                 const float* __restrict__ Z, int B, int width, __bf16* __restrict__ G,
-                                 __bf16* __restrict__ Gt) {
-  const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (size_t)B * width) return;
-  const int b = (int)(i / width), k = (int)(i % width);
-  const float d = dy[b] * w[k] * gelu_d(Z[i]);
-  G[i] = (__bf16)d;
-  Gt[(size_t)k * B + b] = (__bf16)d;
-}
-
-// Row sums of a [R, B] bf16 matrix into FP32 (bias gradients from G^T), or of
-// dy * H^T rows (output weights): out[r] = sum_b Mt[r, b] * (s ? s[b] : 1).
-__global__ void k_rowsum(const __bf16* __restrict__ Mt, int R, int B, const float* __restrict__ s,
-                         float* __restrict__ out) {
-  __shared__ float part[256];
-  const int r = blockIdx.x;
-  if (r >= R) return;
-  float acc = 0.f;
-  for (int b = threadIdx.x; b < B; b += blockDim.x) acc += (float)Mt[(size_t)r * B + b] * (s ? s[b] : 1.0f);
-  part[threadIdx.x] = acc;
-  __syncthreads();
-  for (int k = 128; k > 0; k >>= 1) {
-    if ((int)threadIdx.x < k) part[threadIdx.x] += part[threadIdx.x + k];
-    __syncthreads();
-  }
-  if (threadIdx.x == 0) out[r] = part[0];
-}
-
-// AdamW on the FP32 master parameters (Loshchilov and Hutter), then BF16
-// copies of the weight matrices in both layouts.
-__global__ void k_adamw(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                        const float* __restrict__ g, int64_t n, float lr, float b1, float b2, float eps, float wd,
-                        float c1, float c2) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i]);
-  }
-}
 
 // ---- a training loop on the device (one step is replayed as a graph).
 // state[0] counts the AdamW steps taken so far, state[1] is its value when
 // the loop began, so state[0] - state[1] is the loop's current step s.
-
-// Batch of step s drawn on the device: row r takes row floor(u n / 2^32) of
-// (X, y), u the first word of Philox4x32-10 under key seed at counter
-// (r, s, 0, 0): uniform sampling with replacement.
-__global__ void k_sample_batch(const float* __restrict__ X, const float* __restrict__ y, uint32_t n, int n_in,
-                               int batch, uint64_t seed, const uint32_t* __restrict__ state, float* __restrict__ Xb,
-                               float* __restrict__ yb) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= batch) return;
-  const uint32_t s = state[0] - state[1];
-  const U4 u = philox(seed, (uint32_t)r, s, 0u, 0u);
-  const uint32_t i = __umulhi(u.x, n);
-  for (int k = 0; k < n_in; ++k) Xb[(size_t)r * n_in + k] = X[(size_t)i * n_in + k];
-  yb[r] = y[i];
-}
-
-// AdamW at the loop step's learning rate, bias corrections of step t = state[0] + 1.
-__global__ void k_adamw_loop(float* __restrict__ p, float* __restrict__ m, float* __restrict__ v,
-                             const float* __restrict__ g, int64_t n, const float* __restrict__ lr_sched,
-                             const uint32_t* __restrict__ state, float b1, float b2, float eps, float wd) {
-  const uint32_t t = state[0] + 1u;
-  const float lr = lr_sched[state[0] - state[1]];
-  const float c1 = (float)(1.0 - pow((double)b1, (double)t)), c2 = (float)(1.0 - pow((double)b2, (double)t));
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
-    const float gi = g[i];
-    const float mi = b1 * m[i] + (1.0f - b1) * gi;
-    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
-    m[i] = mi;
-    v[i] = vi;
-    p[i] -= lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * p[i]);
-  }
-}
 
 // End of a loop step: its batch loss (before the update) to losses[s]; one step more.
 __global__ void k_step_done(uint32_t* state, const float* acc, float* losses) {
@@ -248,6 +60,377 @@ __global__ void k_to_bf16(const float* __restrict__ W, int rows, int cols, __bf1
   const __bf16 v = (__bf16)W[i];
   Wb[i] = v;
   if (Wtb) Wtb[(size_t)c * rows + r] = v;
+}
+
+// ---------------------------------------------------------------- fused training
+// One workgroup (four waves) per tile of 32 batch rows; each wave owns 64 of
+// the 256 columns of every [32 x 256] product (2 x 4 MFMA blocks).  The
+// roundings are those of the layer-by-layer form: inputs, weights, hidden
+// activations and hidden backward signals in BF16, pre-activations, sums and
+// the output layer in FP32.
+//   forward  Z_l = H_{l-1} W_l^T + b_l,  H_l = GELU(Z_l)    (A: H_{l-1} rows in LDS, B: W_l rows)
+//   output   y = H_4 . w_out + b_out,  dy = 2 (y - t) / B,  G_4 = dy w_out GELU'(Z_4)
+//   backward dW_l += G_l^T H_{l-1}      (A: G_l^T rows in LDS, B: H_{l-1}^T rows in LDS; K = the 32 rows)
+//            db_l += column sums of G_l
+//            G_{l-1} = (G_l W_l) GELU'(Z_{l-1})   (A: G_l rows in LDS, B: W_l^T rows)
+// LDS (bf16 elements; rows padded by 8 so that 16-byte fragment reads spread over the banks)
+constexpr int kTrLdX = 32 + 8;    // [32][40]: the tile's inputs, and X^T
+constexpr int kTrLdH = 256 + 8;   // [32][264]: activations or backward signal, row layout
+constexpr int kTrLdT = 32 + 8;    // [256][40]: transposed tiles
+constexpr int kTrOffX = 0;
+constexpr int kTrOffXt = kTrOffX + kTrainRows * kTrLdX;
+constexpr int kTrOffH = kTrOffXt + 32 * kTrLdT;
+constexpr int kTrOffHt = kTrOffH + kTrainRows * kTrLdH;  // H_1^T, H_2^T, H_3^T
+constexpr int kTrOffG = kTrOffHt + 3 * 256 * kTrLdT;
+constexpr int kTrOffGt = kTrOffG + kTrainRows * kTrLdH;
+constexpr int kTrBf16 = kTrOffGt + 256 * kTrLdT;
+constexpr size_t kTrLdsBytes = (size_t)kTrBf16 * 2 + (size_t)(4 * kTrainRows + 2 * kTrainRows) * 4;
+static_assert((kTrOffXt * 2) % 16 == 0 && (kTrOffH * 2) % 16 == 0 && (kTrOffHt * 2) % 16 == 0 &&
+                  (kTrOffG * 2) % 16 == 0 && (kTrOffGt * 2) % 16 == 0 && (kTrBf16 * 2) % 16 == 0,
+              "16-byte aligned LDS tiles");
+
+typedef __attribute__((address_space(3))) __bf16 lbf16;
+typedef __attribute__((address_space(3))) bf16x8 lbf16x8;
+typedef __attribute__((address_space(3))) float lf32;
+
+// out = v on a workgroup's first tile, out += v on its later ones
+__device__ inline void accum(float* out, float v, bool first) {
+  GAS float* o = (GAS float*)out;
+  *o = first ? v : *o + v;
+}
+
+extern __shared__ __align__(16) unsigned char tr_smem[];
+
+__global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
+  lbf16* sb = (lbf16*)tr_smem;
+  lf32* ypart = (lf32*)(tr_smem + (size_t)kTrBf16 * 2);  // [4][32]
+  lf32* sdy = ypart + 4 * kTrainRows;                      // [32]
+  lf32* stg = sdy + kTrainRows;                            // [32] targets, then loss terms
+  const int w = threadIdx.x >> 6;
+  const uint32_t l = lane_id();
+  const int r = l & 15, kg = (l >> 4) * 8, q4 = 4 * (l >> 4);
+  const int n0 = w * 64;
+  const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
+  float* part = p.part + (size_t)blockIdx.x * p.n_par;
+  float* zb = p.zbuf + (size_t)blockIdx.x * 3 * kTrainRows * 256;
+  const float* mst = p.master;
+  const uint32_t step = p.state ? p.state[0] - p.state[1] : 0u;
+  const int n_tiles = p.batch / kTrainRows;
+  // this lane's columns of the biases and of the output weights, loaded once
+  float bcol[4][4], wcol[4];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int col = n0 + 16 * j + r;
+#pragma unroll
+    for (int L = 0; L < 4; ++L) bcol[L][j] = ((const GAS float*)(mst + p.off_b[L]))[col];
+    wcol[j] = ((const GAS float*)(mst + p.off_wout))[col];
+  }
+
+  for (int tile = blockIdx.x, it = 0; tile < n_tiles; tile += gridDim.x, ++it) {
+    const bool first = it == 0;
+    __syncthreads();  // the previous tile's readers of every LDS tile are done
+    // ---- the tile's rows, given or drawn: eight threads per row, four inputs
+    // each, loads independent of one another (clamped to the row, then masked)
+    {
+      const int rr = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
+      const int row = tile * kTrainRows + rr;
+      const GAS float* xr;
+      const GAS float* tr;
+      if (p.src_x) {
+        const U4 u = philox(p.seed, (uint32_t)row, step, 0u, 0u);
+        const uint32_t i = __umulhi(u.x, p.n_src);
+        xr = (const GAS float*)p.src_x + (size_t)i * p.n_in;
+        tr = (const GAS float*)p.src_t + i;
+      } else {
+        xr = (const GAS float*)p.x + (size_t)row * p.n_in;
+        tr = (const GAS float*)p.t + row;
+      }
+      float v[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int k = c0 + e;
+        const float a = xr[k < p.n_in ? k : p.n_in - 1];
+        v[e] = k < p.n_in ? a : 0.0f;
+      }
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const __bf16 h = (__bf16)v[e];
+        sb[kTrOffX + rr * kTrLdX + c0 + e] = h;
+        sb[kTrOffXt + (c0 + e) * kTrLdT + rr] = h;
+      }
+      if ((threadIdx.x & 7) == 0) stg[rr] = *tr;
+    }
+    __syncthreads();
+
+    // ---- forward
+    f32x4 acc[2][4];
+#pragma unroll 1
+    for (int layer = 1; layer <= 4; ++layer) {
+      const int K = layer == 1 ? 32 : 256;
+      const lbf16* A = sb + (layer == 1 ? kTrOffX : kTrOffH);
+      const int lda = layer == 1 ? kTrLdX : kTrLdH;
+      const __bf16* W = p.W[layer - 1];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = zero4;
+      for (int k0 = 0; k0 < K; k0 += 32) {
+        bf16x8 b[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) b[j] = *(const GAS bf16x8*)(W + (size_t)(n0 + 16 * j + r) * K + k0 + kg);
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          const bf16x8 a = *(const lbf16x8*)(A + (16 * i + r) * lda + k0 + kg);
+#pragma unroll
+          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+        }
+      }
+      float bl[4];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) bl[j] = layer == 1 ? bcol[0][j] : (layer == 2 ? bcol[1][j] : (layer == 3 ? bcol[2][j] : bcol[3][j]));
+      if (layer < 4) {
+        __syncthreads();  // every wave has read the layer's input tile
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = n0 + 16 * j + r;
+          const float bc = bl[j];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int m = 16 * i + q4 + q;
+              const float z = acc[i][j][q] + bc;
+              ((GAS float*)zb)[((layer - 1) * kTrainRows + m) * 256 + col] = z;
+              const __bf16 h = (__bf16)gelu(z);
+              sb[kTrOffH + m * kTrLdH + col] = h;
+              sb[kTrOffHt + (layer - 1) * 256 * kTrLdT + col * kTrLdT + m] = h;
+            }
+        }
+        __syncthreads();
+      } else {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const float bc = bl[j];
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) acc[i][j][q] += bc;  // Z_4, kept in registers
+        }
+      }
+    }
+
+    // ---- output layer, loss, dy
+    {
+      float py[2][4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) py[i][q] = 0.f;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float wc = wcol[j];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) py[i][q] += (float)(__bf16)gelu(acc[i][j][q]) * wc;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float v = py[i][q];
+          v += __shfl_xor(v, 1, 64);
+          v += __shfl_xor(v, 2, 64);
+          v += __shfl_xor(v, 4, 64);
+          v += __shfl_xor(v, 8, 64);
+          if (r == 0) ypart[w * kTrainRows + 16 * i + q4 + q] = v;
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < kTrainRows) {
+      const int m = threadIdx.x;
+      const float y = mst[p.off_bout] + ((ypart[m] + ypart[kTrainRows + m]) +
+                                         (ypart[2 * kTrainRows + m] + ypart[3 * kTrainRows + m]));
+      const float d = y - stg[m];
+      sdy[m] = 2.0f * d / (float)p.batch;
+      stg[m] = d * d / (float)p.batch;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {  // the tile's loss and output-bias gradient, in row order
+      float e = 0.f, gb = 0.f;
+      for (int m = 0; m < kTrainRows; ++m) {
+        e += stg[m];
+        gb += sdy[m];
+      }
+      accum(p.loss_part + blockIdx.x, e, first);
+      accum(part + p.off_bout, gb, first);
+    }
+    // output weights: sum over the tile's rows of H_4 dy; and G_4
+    {
+      float dyv[2][4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dyv[i][q] = sdy[16 * i + q4 + q];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int col = n0 + 16 * j + r;
+        const float wc = wcol[j];
+        float sw = 0.f;
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int m = 16 * i + q4 + q;
+            const float z = acc[i][j][q];
+            sw += (float)(__bf16)gelu(z) * dyv[i][q];
+            const __bf16 g = (__bf16)(dyv[i][q] * wc * gelu_d(z));
+            sb[kTrOffG + m * kTrLdH + col] = g;
+            sb[kTrOffGt + col * kTrLdT + m] = g;
+          }
+        sw += __shfl_xor(sw, 16, 64);
+        sw += __shfl_xor(sw, 32, 64);
+        if (l < 16) accum(part + p.off_wout + col, sw, first);
+      }
+    }
+    __syncthreads();
+
+    // ---- backward
+#pragma unroll 1
+    for (int layer = 4; layer >= 1; --layer) {
+      const int kin = layer == 1 ? 32 : 256;
+      // weight gradient: rows n of G^T against rows kc of H_{l-1}^T, K = the tile's 32 rows
+      {
+        const lbf16* Bt = layer == 1 ? sb + kTrOffXt : sb + kTrOffHt + (layer - 2) * 256 * kTrLdT;
+        bf16x8 ga[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ga[i] = *(const lbf16x8*)(sb + kTrOffGt + (n0 + 16 * i + r) * kTrLdT + kg);
+        float* dW = part + p.off_W[layer - 1];
+        for (int jc = 0; jc < kin / 16; jc += 4) {
+          f32x4 c[4][4];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            if (jc + jj >= kin / 16) break;
+            const bf16x8 bfr = *(const lbf16x8*)(Bt + (16 * (jc + jj) + r) * kTrLdT + kg);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) c[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga[i], bfr, zero4, 0, 0, 0);
+          }
+          if (!first) {  // later tiles: add the slice's current values, all loads issued first
+#pragma unroll
+            for (int jj = 0; jj < 4; ++jj) {
+              if (jc + jj >= kin / 16) break;
+              const int kc = 16 * (jc + jj) + r;
+#pragma unroll
+              for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int q = 0; q < 4; ++q) c[i][jj][q] += ((const GAS float*)dW)[(size_t)(n0 + 16 * i + q4 + q) * kin + kc];
+            }
+          }
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            if (jc + jj >= kin / 16) break;
+            const int kc = 16 * (jc + jj) + r;
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+              for (int q = 0; q < 4; ++q) ((GAS float*)dW)[(size_t)(n0 + 16 * i + q4 + q) * kin + kc] = c[i][jj][q];
+          }
+        }
+      }
+      // bias gradient: column sums of G, in row order
+      {
+        const int n = threadIdx.x;
+        float sg = 0.f;
+        for (int m = 0; m < kTrainRows; ++m) sg += (float)sb[kTrOffG + m * kTrLdH + n];
+        accum(part + p.off_b[layer - 1] + n, sg, first);
+      }
+      if (layer > 1) {
+        // G_{l-1} = (G_l W_l) GELU'(Z_{l-1}): rows of G against rows kc of W_l^T
+        const __bf16* Wt = p.Wt[layer - 1];
+        f32x4 d[2][4];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) d[i][j] = zero4;
+        for (int k0 = 0; k0 < 256; k0 += 32) {
+          bf16x8 b[4];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) b[j] = *(const GAS bf16x8*)(Wt + (size_t)(n0 + 16 * j + r) * 256 + k0 + kg);
+#pragma unroll
+          for (int i = 0; i < 2; ++i) {
+            const bf16x8 a = *(const lbf16x8*)(sb + kTrOffG + (16 * i + r) * kTrLdH + k0 + kg);
+#pragma unroll
+            for (int j = 0; j < 4; ++j) d[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], d[i][j], 0, 0, 0);
+          }
+        }
+        __syncthreads();  // every wave is done with G_l and G_l^T
+        float zl[2][4][4];  // Z_{l-1} of this lane's elements, loaded together
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+              zl[i][j][q] = ((const GAS float*)zb)[((layer - 2) * kTrainRows + 16 * i + q4 + q) * 256 + n0 + 16 * j + r];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int col = n0 + 16 * j + r;
+#pragma unroll
+          for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int m = 16 * i + q4 + q;
+              const __bf16 g = (__bf16)(d[i][j][q] * gelu_d(zl[i][j][q]));
+              sb[kTrOffG + m * kTrLdH + col] = g;
+              sb[kTrOffGt + col * kTrLdT + m] = g;
+            }
+        }
+        __syncthreads();
+      }
+    }
+  }
+}
+
+// Sum of the workgroups' gradient slices (in workgroup order), then AdamW
+// (Loshchilov and Hutter) and the BF16 copies of the updated weights.
+__global__ __launch_bounds__(256) void k_mlp_train_update(MlpUpdate u) {
+  float lr = u.lr, c1 = u.c1, c2 = u.c2;
+  if (u.lr_sched) {
+    const uint32_t t = u.state[0] + 1u;
+    lr = u.lr_sched[u.state[0] - u.state[1]];
+    c1 = (float)(1.0 - pow((double)u.b1, (double)t));
+    c2 = (float)(1.0 - pow((double)u.b2, (double)t));
+  }
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < u.n_par; i += (int64_t)gridDim.x * blockDim.x) {
+    float g = 0.f;
+    for (int k = 0; k < u.n_part; ++k) g += ((const GAS float*)u.part)[(size_t)k * u.n_par + i];
+    ((GAS float*)u.grad)[i] = g;
+    if (!u.p) continue;
+    GAS float* P = (GAS float*)u.p;
+    GAS float* M = (GAS float*)u.m;
+    GAS float* V = (GAS float*)u.v;
+    const float mi = u.b1 * M[i] + (1.0f - u.b1) * g;
+    const float vi = u.b2 * V[i] + (1.0f - u.b2) * g * g;
+    M[i] = mi;
+    V[i] = vi;
+    const float pi = P[i] - lr * ((mi / c1) / (sqrtf(vi / c2) + u.eps) + u.wd * P[i]);
+    P[i] = pi;
+#pragma unroll
+    for (int L = 0; L < 4; ++L) {
+      const int64_t o = i - u.off_W[L];
+      if (o >= 0 && o < (int64_t)256 * u.kin[L]) {
+        const int rr = (int)(o / u.kin[L]), kk = (int)(o % u.kin[L]);
+        const __bf16 v = (__bf16)pi;
+        ((GAS __bf16*)u.Wb[L])[o] = v;
+        ((GAS __bf16*)u.Wtb[L])[(size_t)kk * 256 + rr] = v;
+      }
+    }
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    float e = 0.f;
+    for (int k = 0; k < u.n_part; ++k) e += u.loss_part[k];
+    u.acc[0] = e;
+  }
 }
 
 // ---------------------------------------------------------------- inference
@@ -376,64 +559,35 @@ hipError_t mlp_infer(const MlpInfer& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mlp_gemm(const MlpGemm& g, hipStream_t s) {
-  if (g.M <= 0 || g.N <= 0) return hipSuccess;
-  dim3 grid((g.M + 63) / 64, (g.N + 63) / 64);
-  k_gemm_nt<<<grid, 256, 0, s>>>(g);
-  return hipGetLastError();
-}
-
-hipError_t mlp_pack_input(const float* x, int B, int n_in, __bf16* X, __bf16* Xt, hipStream_t s) {
-  k_pack_input<<<(B + 255) / 256, 256, 0, s>>>(x, B, n_in, X, Xt);
-  return hipGetLastError();
-}
-
-hipError_t mlp_out_fwd(const __bf16* H, int B, int width, const float* w, const float* c, float* y, hipStream_t s) {
-  k_out_fwd<<<(B + 255) / 256, 256, 0, s>>>(H, B, width, w, c, y);
-  return hipGetLastError();
-}
-
-hipError_t mlp_mse(const float* y, const float* t, int B, float* dy, float* loss_acc, hipStream_t s) {
-  k_mse<<<1, 256, 0, s>>>(y, t, B, dy, loss_acc);
-  return hipGetLastError();
-}
-
-hipError_t mlp_out_bwd_hidden(const float* dy, const float* w, const float* Z, int B, int width, __bf16* G,
-                              __bf16* Gt, hipStream_t s) {
-  const size_t n = (size_t)B * width;
-  k_out_bwd_hidden<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(dy, w, Z, B, width, G, Gt);
-  return hipGetLastError();
-}
-
-hipError_t mlp_rowsum(const __bf16* Mt, int R, int B, const float* scale, float* out, hipStream_t s) {
-  k_rowsum<<<R, 256, 0, s>>>(Mt, R, B, scale, out);
-  return hipGetLastError();
-}
-
-hipError_t mlp_adamw(float* p, float* m, float* v, const float* g, int64_t n, float lr, float b1, float b2, float eps,
-                     float wd, float c1, float c2, hipStream_t s) {
-  int grid = (int)((n + 255) / 256);
-  if (grid > 4096) grid = 4096;
-  k_adamw<<<grid, 256, 0, s>>>(p, m, v, g, n, lr, b1, b2, eps, wd, c1, c2);
-  return hipGetLastError();
-}
-
-hipError_t mlp_sample_batch(const float* X, const float* y, uint32_t n, int n_in, int batch, uint64_t seed,
-                            const uint32_t* state, float* Xb, float* yb, hipStream_t s) {
-  k_sample_batch<<<(batch + 255) / 256, 256, 0, s>>>(X, y, n, n_in, batch, seed, state, Xb, yb);
-  return hipGetLastError();
-}
-
-hipError_t mlp_adamw_loop(float* p, float* m, float* v, const float* g, int64_t n, const float* lr_sched,
-                          const uint32_t* state, float b1, float b2, float eps, float wd, hipStream_t s) {
-  int grid = (int)((n + 255) / 256);
-  if (grid > 4096) grid = 4096;
-  k_adamw_loop<<<grid, 256, 0, s>>>(p, m, v, g, n, lr_sched, state, b1, b2, eps, wd);
-  return hipGetLastError();
-}
-
 hipError_t mlp_step_done(uint32_t* state, const float* acc, float* losses, hipStream_t s) {
   k_step_done<<<1, 1, 0, s>>>(state, acc, losses);
+  return hipGetLastError();
+}
+
+size_t mlp_train_lds_bytes() { return kTrLdsBytes; }
+
+int mlp_train_grid(int batch) {
+  const int tiles = batch / kTrainRows;
+  return tiles < kTrainMaxWg ? tiles : kTrainMaxWg;
+}
+
+hipError_t mlp_train_rows(const MlpTrain& p, hipStream_t s) {
+  if (p.batch <= 0 || p.batch % kTrainRows) return hipErrorInvalidValue;
+  static bool attr = false;  // the kernel needs more LDS than the default dynamic limit
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute((const void*)k_mlp_train_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)kTrLdsBytes);
+    if (e != hipSuccess) return e;
+    attr = true;
+  }
+  k_mlp_train_rows<<<mlp_train_grid(p.batch), 256, kTrLdsBytes, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t mlp_train_update(const MlpUpdate& u, hipStream_t s) {
+  int grid = (int)((u.n_par + 255) / 256);
+  if (grid > 4096) grid = 4096;
+  k_mlp_train_update<<<grid, 256, 0, s>>>(u);
   return hipGetLastError();
 }
 

@@ -139,6 +139,29 @@ def bench_inference(ctx, srg_id: int, n_in: int = 8, n: int = 1_000_000, reps: i
             "frac": flops / (ms * 1e-3) / 2.5e15}
 
 
+def bench_training(ctx, n_in: int = 8, batch: int = 1024, steps: int = 500, seed: int = 0):
+    """The device training loop (two launches per step, replayed as a graph)
+    on synthetic rows: steps per second, samples per second and the
+    forward + backward FLOP rate (3 x the forward's per sample)."""
+    import torch
+
+    dev = f"cuda:{ctx.device}"
+    g = torch.Generator().manual_seed(seed)
+    X = torch.randn(65536, n_in, generator=g).to(dev)
+    y = (0.5 + 0.3 * torch.sin(X[:, 0])).to(dev)
+    s = ctx.srg_create(n_in, 256, 4, seed=seed)
+    lr = np.full(steps, 1e-3, dtype=np.float32)
+    ctx.srg_train(s, X, y, batch, lr[:8], seed=1)  # captures the step's graph
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ctx.srg_train(s, X, y, batch, lr, seed=2)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    flops = 3 * forward_flops(n_in) * batch * steps
+    return {"batch": batch, "steps": steps, "us_per_step": dt / steps * 1e6, "samples_per_s": batch * steps / dt,
+            "tflops": flops / dt / 1e12, "frac": flops / dt / 2.5e15}
+
+
 def _traced_batches(device, tab, specs, points, batch_foams, pool, max_gen, log, what):
     """Generate the foams of `specs` in batches, trace each batch's jobs in a
     context of its own (so its scenes are freed), and return per job

@@ -372,16 +372,17 @@ def test_first_hit_axis_parallel_and_face_rays(ctx, torch, oracle_lib, tiny, shi
     m = fg.Mesh(tiny.verts + np.float32(shift), tiny.tris, tuple(v + shift for v in tiny.box_lo),
                 tuple(v + shift for v in tiny.box_hi), tiny.flags, {})
     L = max(h - l for l, h in zip(m.box_lo, m.box_hi))
-    for seed in (21, 22):
-        _first_hit_parity(ctx, torch, oracle_lib, m, _axis_rays(m, 3000, seed=seed), 0.9998, far_t=4 * L)
+    # 18 000 rays, so that the 99.99 % agreement is a measured rate (at most one near-tie)
+    rays = np.concatenate([_axis_rays(m, 3000, seed=seed) for seed in (21, 22)])
+    _first_hit_parity(ctx, torch, oracle_lib, m, rays, 0.9999, far_t=4 * L)
 
 
 @pytest.mark.slow
 def test_first_hit_sample_of_128_foam(ctx, torch, oracle_lib):
     """Subsample of rays on the 128^3, porosity 0.6 foam (about 1.9M triangles)."""
     m = fg.make_grf_foam(128, 0.6, 2.0, seed=1)
-    rays = np.concatenate([fg.top_rays(m, 3000, seed=11), fg.surface_rays(m, 3000, seed=12)])
-    _first_hit_parity(ctx, torch, oracle_lib, m, rays, 0.9998)
+    rays = np.concatenate([fg.top_rays(m, 5000, seed=11), fg.surface_rays(m, 5000, seed=12)])
+    _first_hit_parity(ctx, torch, oracle_lib, m, rays, 0.9999)
 
 
 # ---------------------------------------------------------------- cascades
