@@ -11,6 +11,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "device_util.h"
 #include "mlp_kernels.h"
 
@@ -573,12 +575,17 @@ int mlp_train_grid(int batch) {
 
 hipError_t mlp_train_rows(const MlpTrain& p, hipStream_t s) {
   if (p.batch <= 0 || p.batch % kTrainRows) return hipErrorInvalidValue;
-  static bool attr = false;  // the kernel needs more LDS than the default dynamic limit
-  if (!attr) {
-    const hipError_t e = hipFuncSetAttribute((const void*)k_mlp_train_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                             (int)kTrLdsBytes);
+  // the kernel needs more LDS than the default dynamic limit: raise it once per device
+  static std::atomic<bool> attr[64];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  if (!attr[dev].load()) {
+    e = hipFuncSetAttribute((const void*)k_mlp_train_rows, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)kTrLdsBytes);
     if (e != hipSuccess) return e;
-    attr = true;
+    attr[dev].store(true);
   }
   k_mlp_train_rows<<<mlp_train_grid(p.batch), 256, kTrLdsBytes, s>>>(p);
   return hipGetLastError();

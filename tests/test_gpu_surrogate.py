@@ -139,6 +139,23 @@ def test_gradient_deviation_is_the_bf16_storage(ctx, seed):
     assert rel_e < 0.25 * rel_r, (rel_e, rel_r)
 
 
+@pytest.mark.parametrize("batch", [32, 4128])
+def test_gradient_of_one_tile_and_of_many_tiles_per_workgroup(ctx, batch):
+    """One 32-row tile (one workgroup), and 129 tiles over the 64 workgroups
+    (two or three tiles each, so each adds later tiles into its gradient slice
+    before the slices are summed): the gradient still carries only the BF16
+    storage error against the host evaluation with the same rounding."""
+    s = ctx.srg_create(N_IN, 256, 4, seed=44)
+    p = ctx.srg_params(s)
+    X, t = _data(60, batch)
+    loss, g = ctx.srg_gradient(s, X, t)
+    ge = _bf16_rounded_grad(p, mlp_ref.round_bf16(X), t, N_IN)
+    rel_e = np.linalg.norm(g.astype(np.float64) - ge) / np.linalg.norm(ge)
+    assert rel_e < 5e-4, rel_e
+    lr, _ = mlp_ref.loss_and_grad(mlp_ref.gpu_visible_params(p, N_IN), mlp_ref.round_bf16(X), t, N_IN)
+    assert loss == pytest.approx(lr, rel=1e-2)
+
+
 def test_adamw_step_matches_numpy(ctx):
     """Three AdamW steps (decoupled weight decay, bias-corrected moments)
     element by element against numpy fed with the same gradients."""
