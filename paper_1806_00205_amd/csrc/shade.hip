@@ -461,7 +461,10 @@ __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(4))) void 
         tally_cnt(mine, wt, gt, T_E_DEP_FX, (unsigned long long)to_fx(E), jt, job);
       } else {
         if (code == -2) tally_cnt(mine, wt, gt, T_SUBSTRATE, 1ull, jt, job);
-        hit_frame(J, code, f0, f1, px, py, pz, nx, ny, nz);
+        // the hit point and normal only where they are used: a hit that may
+        // emit (above E_c, below the last generation), or the depth histogram
+        // (most daughters arrive below E_c and need no triangle gather)
+        if (a.n_zbins > 0 || (gen < a.max_gen && E > tb.Ec)) hit_frame(J, code, f0, f1, px, py, pz, nx, ny, nz);
         if (a.n_zbins > 0) {
           // the ray ends on a surface: its depth below the top of the cell, as
           // a fraction of the cell height (section 3.2, Fig. pen, penetration profile)
