@@ -65,8 +65,9 @@ __global__ void k_to_bf16(const float* __restrict__ W, int rows, int cols, __bf1
 }
 
 // ---------------------------------------------------------------- fused training
-// One workgroup (four waves) per tile of 32 batch rows; each wave owns 64 of
-// the 256 columns of every [32 x 256] product (2 x 4 MFMA blocks).  The
+// One workgroup (eight waves, two per SIMD) per tile of 32 batch rows; each
+// wave owns 32 of the 256 columns of every [32 x 256] product (2 x 2 MFMA
+// blocks), and 32 rows of every weight gradient.  The
 // roundings are those of the layer-by-layer form: inputs, weights, hidden
 // activations and hidden backward signals in BF16, pre-activations, sums and
 // the output layer in FP32.
@@ -86,7 +87,11 @@ constexpr int kTrOffHt = kTrOffH + kTrainRows * kTrLdH;  // H_1^T, H_2^T, H_3^T
 constexpr int kTrOffG = kTrOffHt + 3 * 256 * kTrLdT;
 constexpr int kTrOffGt = kTrOffG + kTrainRows * kTrLdH;
 constexpr int kTrBf16 = kTrOffGt + 256 * kTrLdT;
-constexpr size_t kTrLdsBytes = (size_t)kTrBf16 * 2 + (size_t)(4 * kTrainRows + 2 * kTrainRows) * 4;
+constexpr int kTrWaves = 8;                 // waves per workgroup: two per SIMD
+constexpr int kTrThreads = 64 * kTrWaves;
+constexpr int kTrCols = 256 / kTrWaves;     // columns of each product a wave owns
+constexpr int kTrCB = kTrCols / 16;         // ... as 16-wide MFMA blocks
+constexpr size_t kTrLdsBytes = (size_t)kTrBf16 * 2 + (size_t)(kTrWaves * kTrainRows + 2 * kTrainRows) * 4;
 static_assert((kTrOffXt * 2) % 16 == 0 && (kTrOffH * 2) % 16 == 0 && (kTrOffHt * 2) % 16 == 0 &&
                   (kTrOffG * 2) % 16 == 0 && (kTrOffGt * 2) % 16 == 0 && (kTrBf16 * 2) % 16 == 0,
               "16-byte aligned LDS tiles");
@@ -103,15 +108,15 @@ __device__ inline void accum(float* out, float v, bool first) {
 
 extern __shared__ __align__(16) unsigned char tr_smem[];
 
-__global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
+__global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_train_rows(MlpTrain p) {
   lbf16* sb = (lbf16*)tr_smem;
-  lf32* ypart = (lf32*)(tr_smem + (size_t)kTrBf16 * 2);  // [4][32]
-  lf32* sdy = ypart + 4 * kTrainRows;                      // [32]
+  lf32* ypart = (lf32*)(tr_smem + (size_t)kTrBf16 * 2);  // [kTrWaves][32]
+  lf32* sdy = ypart + kTrWaves * kTrainRows;               // [32]
   lf32* stg = sdy + kTrainRows;                            // [32] targets, then loss terms
   const int w = threadIdx.x >> 6;
   const uint32_t l = lane_id();
   const int r = l & 15, kg = (l >> 4) * 8, q4 = 4 * (l >> 4);
-  const int n0 = w * 64;
+  const int n0 = w * kTrCols;  // the wave's columns of every [32 x 256] product
   const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
   float* part = p.part + (size_t)blockIdx.x * p.n_par;
   float* zb = p.zbuf + (size_t)blockIdx.x * 3 * kTrainRows * 256;
@@ -119,9 +124,9 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
   const uint32_t step = p.state ? p.state[0] - p.state[1] : 0u;
   const int n_tiles = p.batch / kTrainRows;
   // this lane's columns of the biases and of the output weights, loaded once
-  float bcol[4][4], wcol[4];
+  float bcol[4][kTrCB], wcol[kTrCB];
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
+  for (int j = 0; j < kTrCB; ++j) {
     const int col = n0 + 16 * j + r;
 #pragma unroll
     for (int L = 0; L < 4; ++L) bcol[L][j] = ((const GAS float*)(mst + p.off_b[L]))[col];
@@ -133,7 +138,7 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
     __syncthreads();  // the previous tile's readers of every LDS tile are done
     // ---- the tile's rows, given or drawn: eight threads per row, four inputs
     // each, loads independent of one another (clamped to the row, then masked)
-    {
+    if (threadIdx.x < 8 * kTrainRows) {
       const int rr = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
       const int row = tile * kTrainRows + rr;
       const GAS float* xr;
@@ -165,7 +170,7 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
     __syncthreads();
 
     // ---- forward
-    f32x4 acc[2][4];
+    f32x4 acc[2][kTrCB];
 #pragma unroll 1
     for (int layer = 1; layer <= 4; ++layer) {
       const int K = layer == 1 ? 32 : 256;
@@ -175,25 +180,25 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
 #pragma unroll
       for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = zero4;
+        for (int j = 0; j < kTrCB; ++j) acc[i][j] = zero4;
       for (int k0 = 0; k0 < K; k0 += 32) {
-        bf16x8 b[4];
+        bf16x8 b[kTrCB];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) b[j] = *(const GAS bf16x8*)(W + (size_t)(n0 + 16 * j + r) * K + k0 + kg);
+        for (int j = 0; j < kTrCB; ++j) b[j] = *(const GAS bf16x8*)(W + (size_t)(n0 + 16 * j + r) * K + k0 + kg);
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
           const bf16x8 a = *(const lbf16x8*)(A + (16 * i + r) * lda + k0 + kg);
 #pragma unroll
-          for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
+          for (int j = 0; j < kTrCB; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], acc[i][j], 0, 0, 0);
         }
       }
-      float bl[4];
+      float bl[kTrCB];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) bl[j] = layer == 1 ? bcol[0][j] : (layer == 2 ? bcol[1][j] : (layer == 3 ? bcol[2][j] : bcol[3][j]));
+      for (int j = 0; j < kTrCB; ++j) bl[j] = layer == 1 ? bcol[0][j] : (layer == 2 ? bcol[1][j] : (layer == 3 ? bcol[2][j] : bcol[3][j]));
       if (layer < 4) {
         __syncthreads();  // every wave has read the layer's input tile
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kTrCB; ++j) {
           const int col = n0 + 16 * j + r;
           const float bc = bl[j];
 #pragma unroll
@@ -211,7 +216,7 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
         __syncthreads();
       } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kTrCB; ++j) {
           const float bc = bl[j];
 #pragma unroll
           for (int i = 0; i < 2; ++i)
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) py[i][q] = 0.f;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < kTrCB; ++j) {
         const float wc = wcol[j];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
@@ -251,8 +256,10 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
     __syncthreads();
     if (threadIdx.x < kTrainRows) {
       const int m = threadIdx.x;
-      const float y = mst[p.off_bout] + ((ypart[m] + ypart[kTrainRows + m]) +
-                                         (ypart[2 * kTrainRows + m] + ypart[3 * kTrainRows + m]));
+      float ys = 0.f;  // the waves' shares in wave order
+#pragma unroll
+      for (int q = 0; q < kTrWaves; ++q) ys += ypart[q * kTrainRows + m];
+      const float y = mst[p.off_bout] + ys;
       const float d = y - stg[m];
       sdy[m] = 2.0f * d / (float)p.batch;
       stg[m] = d * d / (float)p.batch;
@@ -275,7 +282,7 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) dyv[i][q] = sdy[16 * i + q4 + q];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
+      for (int j = 0; j < kTrCB; ++j) {
         const int col = n0 + 16 * j + r;
         const float wc = wcol[j];
         float sw = 0.f;
@@ -304,18 +311,18 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
       // weight gradient: rows n of G^T against rows kc of H_{l-1}^T, K = the tile's 32 rows
       {
         const lbf16* Bt = layer == 1 ? sb + kTrOffXt : sb + kTrOffHt + (layer - 2) * 256 * kTrLdT;
-        bf16x8 ga[4];
+        bf16x8 ga[kTrCB];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ga[i] = *(const lbf16x8*)(sb + kTrOffGt + (n0 + 16 * i + r) * kTrLdT + kg);
+        for (int i = 0; i < kTrCB; ++i) ga[i] = *(const lbf16x8*)(sb + kTrOffGt + (n0 + 16 * i + r) * kTrLdT + kg);
         float* dW = part + p.off_W[layer - 1];
         for (int jc = 0; jc < kin / 16; jc += 4) {
-          f32x4 c[4][4];
+          f32x4 c[kTrCB][4];
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) {
             if (jc + jj >= kin / 16) break;
             const bf16x8 bfr = *(const lbf16x8*)(Bt + (16 * (jc + jj) + r) * kTrLdT + kg);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) c[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga[i], bfr, zero4, 0, 0, 0);
+            for (int i = 0; i < kTrCB; ++i) c[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga[i], bfr, zero4, 0, 0, 0);
           }
           if (!first) {  // later tiles: add the slice's current values, all loads issued first
 #pragma unroll
@@ -323,7 +330,7 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
               if (jc + jj >= kin / 16) break;
               const int kc = 16 * (jc + jj) + r;
 #pragma unroll
-              for (int i = 0; i < 4; ++i)
+              for (int i = 0; i < kTrCB; ++i)
 #pragma unroll
                 for (int q = 0; q < 4; ++q) c[i][jj][q] += ((const GAS float*)dW)[(size_t)(n0 + 16 * i + q4 + q) * kin + kc];
             }
@@ -333,14 +340,14 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
             if (jc + jj >= kin / 16) break;
             const int kc = 16 * (jc + jj) + r;
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < kTrCB; ++i)
 #pragma unroll
               for (int q = 0; q < 4; ++q) ((GAS float*)dW)[(size_t)(n0 + 16 * i + q4 + q) * kin + kc] = c[i][jj][q];
           }
         }
       }
       // bias gradient: column sums of G, in row order
-      {
+      if (threadIdx.x < 256) {
         const int n = threadIdx.x;
         float sg = 0.f;
         for (int m = 0; m < kTrainRows; ++m) sg += (float)sb[kTrOffG + m * kTrLdH + n];
@@ -349,33 +356,33 @@ __global__ __launch_bounds__(256) void k_mlp_train_rows(MlpTrain p) {
       if (layer > 1) {
         // G_{l-1} = (G_l W_l) GELU'(Z_{l-1}): rows of G against rows kc of W_l^T
         const __bf16* Wt = p.Wt[layer - 1];
-        f32x4 d[2][4];
+        f32x4 d[2][kTrCB];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int j = 0; j < 4; ++j) d[i][j] = zero4;
+          for (int j = 0; j < kTrCB; ++j) d[i][j] = zero4;
         for (int k0 = 0; k0 < 256; k0 += 32) {
-          bf16x8 b[4];
+          bf16x8 b[kTrCB];
 #pragma unroll
-          for (int j = 0; j < 4; ++j) b[j] = *(const GAS bf16x8*)(Wt + (size_t)(n0 + 16 * j + r) * 256 + k0 + kg);
+          for (int j = 0; j < kTrCB; ++j) b[j] = *(const GAS bf16x8*)(Wt + (size_t)(n0 + 16 * j + r) * 256 + k0 + kg);
 #pragma unroll
           for (int i = 0; i < 2; ++i) {
             const bf16x8 a = *(const lbf16x8*)(sb + kTrOffG + (16 * i + r) * kTrLdH + k0 + kg);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) d[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], d[i][j], 0, 0, 0);
+            for (int j = 0; j < kTrCB; ++j) d[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], d[i][j], 0, 0, 0);
           }
         }
         __syncthreads();  // every wave is done with G_l and G_l^T
-        float zl[2][4][4];  // Z_{l-1} of this lane's elements, loaded together
+        float zl[2][kTrCB][4];  // Z_{l-1} of this lane's elements, loaded together
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < kTrCB; ++j)
 #pragma unroll
           for (int i = 0; i < 2; ++i)
 #pragma unroll
             for (int q = 0; q < 4; ++q)
               zl[i][j][q] = ((const GAS float*)zb)[((layer - 2) * kTrainRows + 16 * i + q4 + q) * 256 + n0 + 16 * j + r];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
+        for (int j = 0; j < kTrCB; ++j) {
           const int col = n0 + 16 * j + r;
 #pragma unroll
           for (int i = 0; i < 2; ++i)
@@ -404,8 +411,18 @@ __global__ __launch_bounds__(256) void k_mlp_train_update(MlpUpdate u) {
     c2 = (float)(1.0 - pow((double)u.b2, (double)t));
   }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < u.n_par; i += (int64_t)gridDim.x * blockDim.x) {
+    // slices in workgroup order; eight loads are in flight at a time, the
+    // additions stay in that order
     float g = 0.f;
-    for (int k = 0; k < u.n_part; ++k) g += ((const GAS float*)u.part)[(size_t)k * u.n_par + i];
+    int k = 0;
+    for (; k + 8 <= u.n_part; k += 8) {
+      float v[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v[q] = ((const GAS float*)u.part)[(size_t)(k + q) * u.n_par + i];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) g += v[q];
+    }
+    for (; k < u.n_part; ++k) g += ((const GAS float*)u.part)[(size_t)k * u.n_par + i];
     ((GAS float*)u.grad)[i] = g;
     if (!u.p) continue;
     GAS float* P = (GAS float*)u.p;
@@ -587,7 +604,7 @@ hipError_t mlp_train_rows(const MlpTrain& p, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr[dev].store(true);
   }
-  k_mlp_train_rows<<<mlp_train_grid(p.batch), 256, kTrLdsBytes, s>>>(p);
+  k_mlp_train_rows<<<mlp_train_grid(p.batch), kTrThreads, kTrLdsBytes, s>>>(p);
   return hipGetLastError();
 }
 
