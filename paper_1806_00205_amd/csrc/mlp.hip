@@ -227,6 +227,19 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
     }
 
     // ---- output layer, loss, dy
+    // H_4 (as BF16) and GELU'(Z_4) of this lane's elements, one erf each
+    float h4[2][kTrCB][4], gd4[2][kTrCB][4];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < kTrCB; ++j)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const float z = acc[i][j][q];
+          const float e = erf_as(z * 0.70710678118654752f);  // gelu and gelu_d, term for term
+          h4[i][j][q] = (float)(__bf16)(0.5f * z * (1.0f + e));
+          gd4[i][j][q] = 0.5f * (1.0f + e) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+        }
     {
       float py[2][4];
 #pragma unroll
@@ -239,7 +252,7 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
-          for (int q = 0; q < 4; ++q) py[i][q] += (float)(__bf16)gelu(acc[i][j][q]) * wc;
+          for (int q = 0; q < 4; ++q) py[i][q] += h4[i][j][q] * wc;
       }
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -291,9 +304,8 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int m = 16 * i + q4 + q;
-            const float z = acc[i][j][q];
-            sw += (float)(__bf16)gelu(z) * dyv[i][q];
-            const __bf16 g = (__bf16)(dyv[i][q] * wc * gelu_d(z));
+            sw += h4[i][j][q] * dyv[i][q];
+            const __bf16 g = (__bf16)(dyv[i][q] * wc * gd4[i][j][q]);
             sb[kTrOffG + m * kTrLdH + col] = g;
             sb[kTrOffGt + col * kTrLdT + m] = g;
           }
