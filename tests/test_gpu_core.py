@@ -240,6 +240,30 @@ def test_bvh_structure(ctx, n, p, seed):
     assert 1 <= info["bvh_depth"] < 100
 
 
+@pytest.mark.parametrize("k", [2, 3, 5, 64, 257])
+def test_bvh_of_a_few_triangles(ctx, k):
+    """Trees of a few triangles (one workgroup of the level-by-level refit,
+    the root reached after one or a few levels, a tree deeper than its
+    triangle count suggests when codes collide): every box exact, the depth
+    that of the tree."""
+    m = fg.make_grf_foam(16, 0.5, 2.0, seed=0)
+    sub = fg.Mesh(m.verts, m.tris[:k], m.box_lo, m.box_hi, m.flags, {})
+    sid = ctx.load_scene(sub)
+    info = ctx.scene_info(sid)
+    nodes, tris = ctx.bvh_download(sid)
+    _check_bvh(nodes, tris, k)
+    links = nodes[:, 12:14].view(np.uint32)
+
+    def height(p):  # internal levels below and including node p (a leaf adds none)
+        h = 0
+        for side in range(2):
+            c = int(links[p, side])
+            if not c & 0x80000000:
+                h = max(h, height(c))
+        return h + 1
+    assert info["bvh_depth"] == height(0)
+
+
 def test_bvh_single_and_empty(ctx):
     m = fg.flat_plane()
     one = fg.Mesh(m.verts, m.tris[:1], m.box_lo, m.box_hi, m.flags, {})
