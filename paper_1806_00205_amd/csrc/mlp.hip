@@ -22,21 +22,34 @@ namespace {
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// erf by Abramowitz and Stegun 7.1.26 (absolute error <= 1.5e-7): branch
-// free, one reciprocal and one exponential, far below the BF16 rounding the
-// activations then take.
-__device__ inline float erf_as(float x) {
-  const float ax = fabsf(x);
-  const float t = __builtin_amdgcn_rcpf(1.0f + 0.3275911f * ax);
-  const float poly =
-      t * (0.254829592f + t * (-0.284496736f + t * (1.421413741f + t * (-1.453152027f + t * 1.061405429f))));
-  return copysignf(1.0f - poly * __expf(-ax * ax), x);
+// Upper tail of the standard normal for a >= 0, Q(a) = Phi(-a) = erfc(a /
+// sqrt 2) / 2, with erfc from Abramowitz and Stegun 7.1.26 (absolute error
+// <= 1.5e-7): Q = t R(t) g with t = 1 / (1 + p a / sqrt 2), R a quartic and
+// g = exp(-a^2 / 2), which the derivative reuses (phi(a) = g / sqrt(2 pi)).
+// One reciprocal and one exponential, all else explicit fused operations, so
+// every kernel rounds it alike.
+struct NormTail {
+  float q, g;
+};
+__device__ inline NormTail norm_tail(float a) {
+  const float t = __builtin_amdgcn_rcpf(fmaf(0.23164188826636f, a, 1.0f));
+  float r = fmaf(t, 0.5307027145f, -0.7265760135f);
+  r = fmaf(t, r, 0.7107068705f);
+  r = fmaf(t, r, -0.142248368f);
+  r = fmaf(t, r, 0.127414796f);
+  const float g = __builtin_amdgcn_exp2f(a * (a * -0.72134752044448170f));  // 2^(-a^2 log2(e) / 2)
+  return {(t * r) * g, g};
 }
 
-// GELU with the normal CDF, x Phi(x), and its derivative
-__device__ inline float gelu(float x) { return 0.5f * x * (1.0f + erf_as(x * 0.70710678118654752f)); }
+// GELU with the normal CDF, x Phi(x) = max(x, 0) - |x| Q(|x|) (no
+// cancellation in the negative tail), and its derivative Phi(x) + x phi(x)
+__device__ inline float gelu(float x) {
+  const float a = fabsf(x);
+  return fmaf(-a, norm_tail(a).q, fmaxf(x, 0.0f));
+}
 __device__ inline float gelu_d(float x) {
-  return 0.5f * (1.0f + erf_as(x * 0.70710678118654752f)) + x * 0.39894228040143268f * __expf(-0.5f * x * x);
+  const NormTail n = norm_tail(fabsf(x));
+  return fmaf(x * 0.39894228040143268f, n.g, x >= 0.0f ? 1.0f - n.q : n.q);
 }
 
 // Fragment layout of the 16x16x32 BF16 MFMA (lane l):
@@ -227,7 +240,7 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
     }
 
     // ---- output layer, loss, dy
-    // H_4 (as BF16) and GELU'(Z_4) of this lane's elements, one erf each
+    // H_4 (as BF16) and GELU'(Z_4) of this lane's elements, one normal tail each
     float h4[2][kTrCB][4], gd4[2][kTrCB][4];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -236,9 +249,10 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const float z = acc[i][j][q];
-          const float e = erf_as(z * 0.70710678118654752f);  // gelu and gelu_d, term for term
-          h4[i][j][q] = (float)(__bf16)(0.5f * z * (1.0f + e));
-          gd4[i][j][q] = 0.5f * (1.0f + e) + z * 0.39894228040143268f * __expf(-0.5f * z * z);
+          const float a = fabsf(z);
+          const NormTail n = norm_tail(a);  // gelu and gelu_d, term for term
+          h4[i][j][q] = (float)(__bf16)fmaf(-a, n.q, fmaxf(z, 0.0f));
+          gd4[i][j][q] = fmaf(z * 0.39894228040143268f, n.g, z >= 0.0f ? 1.0f - n.q : n.q);
         }
     {
       float py[2][4];
