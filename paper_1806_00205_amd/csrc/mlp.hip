@@ -502,20 +502,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
   f32x4 acc[8][4];
 
-  // layer 1: K = 32 (one MFMA step), inputs straight from memory
+  // layer 1: K = 32 (one MFMA step).  The tile's inputs (rows of n_in floats,
+  // consecutive in memory) go to the first 32 columns of the LDS tile as
+  // BF16, columns n_in .. 31 and rows past n as zeros: one pass of
+  // independent unconditional loads, 16 entries per thread, a row's entries in
+  // neighbouring lanes.
   {
     bf16x8 b[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) b[j] = *(const GAS bf16x8*)(p.W[0] + (size_t)(n0 + 16 * j + r) * 32 + kg);
+    const int64_t nrows = p.n - row0;
+    float v[kInfRows * 32 / 256];
+#pragma unroll
+    for (int m = 0; m < kInfRows * 32 / 256; ++m) {
+      const int e = (int)threadIdx.x + 256 * m, rr = e >> 5, k = e & 31;
+      const bool in = rr < nrows && k < p.n_in;
+      // every lane loads (from the tile's first input when its entry is padding), then masks
+      const float xv = ((const GAS float*)p.x)[row0 * p.n_in + (in ? rr * p.n_in + k : 0)];
+      v[m] = in ? xv : 0.0f;
+    }
+#pragma unroll
+    for (int m = 0; m < kInfRows * 32 / 256; ++m) {
+      const int e = (int)threadIdx.x + 256 * m;
+      act[(e >> 5) * kInfLd + (e & 31)] = (__bf16)v[m];
+    }
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < 8; ++i) {
-      const int64_t row = row0 + 16 * i + r;
-      bf16x8 a = {};
-      if (row < p.n) {
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (kg + e < p.n_in) a[e] = (__bf16)((const GAS float*)p.x)[row * p.n_in + kg + e];
-      }
+      const bf16x8 a = *(const lds_bf16x8*)((__attribute__((address_space(3))) __bf16*)act + (16 * i + r) * kInfLd + kg);
 #pragma unroll
       for (int j = 0; j < 4; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[j], zero4, 0, 0, 0);
     }
