@@ -302,10 +302,17 @@ def main():
     ap.add_argument("--sizes", default="64,96,128,192", help="foam grids (voxels per side)")
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--batch-foams", type=int, default=32)
+    ap.add_argument("--timing", action="store_true",
+                    help="only time the kernels: 1e6-query inference and the batch-1024 training loop")
     args = ap.parse_args()
     import paper_1806_00205_amd as rt
 
     ctx = rt.Context(0)
+    if args.timing:
+        srg = ctx.srg_create(8, 256, 4, seed=0)
+        print(json.dumps({"inference": bench_inference(ctx, srg), "training": bench_training(ctx)}), flush=True)
+        ctx.close()
+        return
     res, _ = run_experiment(ctx, n_train=args.train_foams, points_per_foam=args.points, n_test=args.test_foams,
                             train_primaries=args.train_primaries, eval_primaries=args.eval_primaries,
                             steps=args.steps, sizes=tuple(int(x) for x in args.sizes.split(",")),
