@@ -320,16 +320,17 @@ rtmc_status rtmc_copy_probe(rtmc_ctx* ctx, void* dst, const void* src, size_t by
  * Architecture: n_in inputs -> depth hidden layers of width GELU units -> 1
  * output; BF16 operands on the matrix cores with FP32 accumulation; FP32
  * master weights updated with AdamW.  Only width 256 and depth 4 are built.
- * GELU(z) = z Phi(z) with erf evaluated by Abramowitz-Stegun 7.1.26
- * (absolute error <= 1.5e-7).
+ * GELU(z) = z Phi(z), evaluated as max(z, 0) - |z| Phi(-|z|) with the normal
+ * tail from the erfc of Abramowitz-Stegun 7.1.26 (absolute error <= 2.1e-7).
  * Parameter vector order (FP32): W1 [width x n_in] (row = output unit), b1
  * [width], W2 [width x width], b2, ..., W_depth, b_depth, w_out [width],
  * b_out [1]; rtmc_srg_param_count gives its length.
  * X: device float [n, n_in] (features already normalised by the caller);
  * y: device float [n].  Training and gradient calls need batch % 32 == 0
- * (at most 2^22 rows); they run as two kernels (forward and backward of
- * 32-row tiles, then the fixed-order sum of the per-workgroup gradient parts
- * with the update), so gradients and training are reproducible bit for bit.
+ * (at most 2^22 rows); they run in passes of at most 16384 rows (forward and
+ * backward signals of 32-row tiles, then the weight gradients as GEMMs over
+ * the pass's rows), then the update; every sum has a fixed order, so
+ * gradients and training are reproducible bit for bit.
  * ENOTIMPL when the device offers less than 122 KB of LDS per workgroup. */
 rtmc_status rtmc_srg_create(rtmc_ctx* ctx, int32_t n_in, int32_t width, int32_t depth, uint64_t seed,
                             int32_t* srg_id); /* 1 <= n_in <= 32; He-uniform weights, zero biases */

@@ -48,7 +48,7 @@ struct Surrogate {
   DevBuf master, mom1, mom2, grad;  // FP32, padded layout
   DevBuf wbf;                       // BF16 weights: W_l and W_l^T per layer
   int64_t step = 0;
-  // fused training: per-workgroup gradient slices, loss slices, pre-activations, loss word
+  // training: per-workgroup bias and loss slices, pre-activations, transposed tiles, loss word
   DevBuf tws;
   int tws_grid = 0;
   // device training loop: state words, learning rates, losses
@@ -1519,28 +1519,36 @@ rtmc_status srg_refresh_bf16(rtmc_ctx* c, Surrogate& g) {
   return RTMC_OK;
 }
 
-// ---- fused training (two launches per step, mlp.hip)
+// ---- fused training (mlp.hip): per pass of at most kTrainChunk rows one
+// mlp_train_rows and one mlp_train_dw, then one mlp_train_update
 struct SrgTrainWs {
   float *part, *loss_part, *zbuf, *acc;
-  int grid;
+  __bf16 *gt, *ht;
+  int grid, ldk;
 };
 
 rtmc_status srg_train_ws(rtmc_ctx* c, Surrogate& g, int64_t batch, SrgTrainWs& w) {
   if (mlp_train_lds_bytes() > c->lds_per_block)
     return fail(c, RTMC_ENOTIMPL, "surrogate training needs %zu bytes of LDS per workgroup (device limit %zu)",
                 mlp_train_lds_bytes(), c->lds_per_block);
-  const int grid = mlp_train_grid((int)batch);
+  const int ldk = (int)std::min<int64_t>(batch, kTrainChunk);
+  const int grid = mlp_train_grid(ldk);  // the first pass is the largest
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
-  const size_t o_loss = up((size_t)grid * g.n_pad * 4), o_z = o_loss + up((size_t)kTrainMaxWg * 4);
-  const size_t o_acc = o_z + up((size_t)grid * 3 * kTrainRows * 256 * 4), total = o_acc + 256;
+  const size_t o_loss = up((size_t)grid * kTrainSmall * 4), o_z = o_loss + up((size_t)kTrainMaxWg * 4);
+  const size_t o_gt = o_z + up((size_t)grid * 3 * kTrainRows * 256 * 4);
+  const size_t o_ht = o_gt + up((size_t)4 * 256 * ldk * 2), o_acc = o_ht + up((size_t)(32 + 3 * 256) * ldk * 2);
+  const size_t total = o_acc + 256;
   rtmc_status st = ensure(c, g.tws, total);
   if (st) return st;
   char* b = static_cast<char*>(g.tws.p);
   w.part = reinterpret_cast<float*>(b);
   w.loss_part = reinterpret_cast<float*>(b + o_loss);
   w.zbuf = reinterpret_cast<float*>(b + o_z);
+  w.gt = reinterpret_cast<__bf16*>(b + o_gt);
+  w.ht = reinterpret_cast<__bf16*>(b + o_ht);
   w.acc = reinterpret_cast<float*>(b + o_acc);
   w.grid = grid;
+  w.ldk = ldk;
   return RTMC_OK;
 }
 
@@ -1552,37 +1560,63 @@ MlpTrain srg_train_args(const Surrogate& g, const SrgTrainWs& w, int64_t batch) 
   for (int l = 1; l <= 4; ++l) {
     t.W[l - 1] = wb + srg_wbf_off(g, l, false);
     t.Wt[l - 1] = wb + srg_wbf_off(g, l, true);
-    t.off_W[l - 1] = L.W[l];
     t.off_b[l - 1] = L.b[l];
   }
   t.off_wout = L.wout;
   t.off_bout = L.bout;
-  t.n_par = L.total;
   t.batch = (int)batch;
   t.n_in = g.n_in;
   t.zbuf = w.zbuf;
+  t.gt = w.gt;
+  t.ht = w.ht;
+  t.ldk = w.ldk;
   t.part = w.part;
   t.loss_part = w.loss_part;
   return t;
 }
 
-// Reduction of the slices into g.grad and the loss into w.acc[0]; with an
-// update, AdamW on the masters and the BF16 weight copies.
-MlpUpdate srg_update_args(Surrogate& g, const SrgTrainWs& w, bool update) {
+// The gradient of the batch into g.grad and its loss into w.acc[0]: the
+// passes of mlp_train_rows and mlp_train_dw in row order.
+rtmc_status srg_gradient_passes(rtmc_ctx* c, Surrogate& g, const SrgTrainWs& w, MlpTrain t) {
+  const SrgLayout L = srg_layout(g);
+  MlpDw d{};
+  d.gt = w.gt;
+  d.ht = w.ht;
+  d.ldk = w.ldk;
+  d.grad = reinterpret_cast<float*>(g.grad.p);
+  for (int l = 1; l <= 4; ++l) {
+    d.off_W[l - 1] = L.W[l];
+    d.off_b[l - 1] = L.b[l];
+  }
+  d.off_wout = L.wout;
+  d.off_bout = L.bout;
+  d.part = w.part;
+  d.loss_part = w.loss_part;
+  d.n_part = w.grid;
+  d.acc = w.acc;
+  for (int64_t r0 = 0; r0 < t.batch; r0 += w.ldk) {
+    t.row0 = (int)r0;
+    t.rows = (int)std::min<int64_t>(w.ldk, t.batch - r0);
+    t.first_pass = r0 == 0;
+    HIPCHK(c, mlp_train_rows(t, c->stream));
+    d.rows = t.rows;
+    d.first_pass = t.first_pass;
+    d.last_pass = r0 + t.rows >= t.batch;
+    HIPCHK(c, mlp_train_dw(d, c->stream));
+  }
+  return RTMC_OK;
+}
+
+// AdamW on the masters from g.grad and the BF16 copies of W and W^T.
+MlpUpdate srg_update_args(Surrogate& g) {
   const SrgLayout L = srg_layout(g);
   __bf16* wb = reinterpret_cast<__bf16*>(g.wbf.p);
   MlpUpdate u{};
-  u.part = w.part;
-  u.loss_part = w.loss_part;
-  u.n_part = w.grid;
   u.n_par = L.total;
-  u.grad = reinterpret_cast<float*>(g.grad.p);
-  u.acc = w.acc;
-  if (update) {
-    u.p = reinterpret_cast<float*>(g.master.p);
-    u.m = reinterpret_cast<float*>(g.mom1.p);
-    u.v = reinterpret_cast<float*>(g.mom2.p);
-  }
+  u.grad = reinterpret_cast<const float*>(g.grad.p);
+  u.p = reinterpret_cast<float*>(g.master.p);
+  u.m = reinterpret_cast<float*>(g.mom1.p);
+  u.v = reinterpret_cast<float*>(g.mom2.p);
   u.b1 = 0.9f;
   u.b2 = 0.999f;
   u.eps = 1e-8f;
@@ -1738,8 +1772,8 @@ rtmc_status rtmc_srg_gradient(rtmc_ctx* c, int32_t id, const float* X, const flo
   MlpTrain t = srg_train_args(g, w, batch);
   t.x = X;
   t.t = y;
-  HIPCHK(c, mlp_train_rows(t, c->stream));
-  HIPCHK(c, mlp_train_update(srg_update_args(g, w, false), c->stream));
+  st = srg_gradient_passes(c, g, w, t);
+  if (st) return st;
   float acc = 0.f;
   HIPCHK(c, hipMemcpyAsync(&acc, w.acc, 4, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1766,9 +1800,10 @@ rtmc_status rtmc_srg_train_step(rtmc_ctx* c, int32_t id, const float* X, const f
   MlpTrain t = srg_train_args(g, w, batch);
   t.x = X;
   t.t = y;
-  HIPCHK(c, mlp_train_rows(t, c->stream));
+  st = srg_gradient_passes(c, g, w, t);
+  if (st) return st;
   g.step += 1;
-  MlpUpdate u = srg_update_args(g, w, true);
+  MlpUpdate u = srg_update_args(g);
   u.lr = lr;
   u.wd = weight_decay;
   u.c1 = 1.0f - (float)std::pow((double)u.b1, (double)g.step);
@@ -1816,14 +1851,15 @@ rtmc_status rtmc_srg_train(rtmc_ctx* c, int32_t id, const float* X, const float*
   targs.n_src = (uint32_t)n;
   targs.seed = seed;
   targs.state = state;
-  MlpUpdate uargs = srg_update_args(g, w, true);
+  MlpUpdate uargs = srg_update_args(g);
   uargs.lr_sched = lr_d;
   uargs.state = state;
   uargs.wd = weight_decay;
-  // one step: rows drawn on the device, forward, backward and gradient slices
-  // in one launch; their sum, AdamW and the BF16 weights in the next; loss out
+  // one step: rows drawn on the device, forward, backward signals and the
+  // weight gradients (per pass of rows), AdamW and the BF16 weights; loss out
   auto one_step = [&]() -> rtmc_status {
-    HIPCHK(c, mlp_train_rows(targs, c->stream));
+    rtmc_status s2 = srg_gradient_passes(c, g, w, targs);
+    if (s2) return s2;
     HIPCHK(c, mlp_train_update(uargs, c->stream));
     HIPCHK(c, mlp_step_done(state, w.acc, loss_d, c->stream));
     return RTMC_OK;

@@ -4,10 +4,11 @@
 // BF16 operands, FP32 accumulation (v_mfma_f32_16x16x32_bf16), with bias,
 // GELU and its derivative fused into the GEMM epilogues.
 //
-// Training runs as two launches per step (k_mlp_train_rows: forward,
-// backward and per-workgroup gradient slices of 32-row tiles with the
-// activations in LDS; k_mlp_train_update: the slices' sum, AdamW and the BF16
-// weight copies); inference as one (k_mlp_infer: all layers of a 128-row tile).
+// Training runs as three launches per step (k_mlp_train_rows: forward and
+// backward signals of 32-row tiles with the activations in LDS;
+// k_mlp_train_dw: the weight gradients as GEMMs over the batch's rows;
+// k_mlp_train_update: AdamW and the BF16 weight copies); inference as one
+// (k_mlp_infer: all layers of a 128-row tile).
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -80,15 +81,15 @@ __global__ void k_to_bf16(const float* __restrict__ W, int rows, int cols, __bf1
 // ---------------------------------------------------------------- fused training
 // One workgroup (eight waves, two per SIMD) per tile of 32 batch rows; each
 // wave owns 32 of the 256 columns of every [32 x 256] product (2 x 2 MFMA
-// blocks), and 32 rows of every weight gradient.  The
-// roundings are those of the layer-by-layer form: inputs, weights, hidden
-// activations and hidden backward signals in BF16, pre-activations, sums and
-// the output layer in FP32.
+// blocks).  The roundings are those of the layer-by-layer form: inputs,
+// weights, hidden activations and hidden backward signals in BF16,
+// pre-activations, sums and the output layer in FP32.
 //   forward  Z_l = H_{l-1} W_l^T + b_l,  H_l = GELU(Z_l)    (A: H_{l-1} rows in LDS, B: W_l rows)
 //   output   y = H_4 . w_out + b_out,  dy = 2 (y - t) / B,  G_4 = dy w_out GELU'(Z_4)
-//   backward dW_l += G_l^T H_{l-1}      (A: G_l^T rows in LDS, B: H_{l-1}^T rows in LDS; K = the 32 rows)
-//            db_l += column sums of G_l
+//   backward db_l += column sums of G_l
 //            G_{l-1} = (G_l W_l) GELU'(Z_{l-1})   (A: G_l rows in LDS, B: W_l^T rows)
+// H_{l-1}^T and G_l^T leave the workgroup (BF16) for the weight gradients
+// dW_l = G_l^T H_{l-1}, which k_mlp_train_dw sums over all rows of the pass.
 // LDS (bf16 elements; rows padded by 8 so that 16-byte fragment reads spread over the banks)
 constexpr int kTrLdX = 32 + 8;    // [32][40]: the tile's inputs, and X^T
 constexpr int kTrLdH = 256 + 8;   // [32][264]: activations or backward signal, row layout
@@ -119,6 +120,15 @@ __device__ inline void accum(float* out, float v, bool first) {
   *o = first ? v : *o + v;
 }
 
+// A transposed [n][32] tile of the LDS (row stride kTrLdT) to rows of a
+// global [.][ldk] array at column c0: 64 bytes per row, 16 per thread.
+__device__ inline void tile_out(const lbf16* src, int n, __bf16* dst, int ldk, int c0) {
+  for (int e = threadIdx.x; e < n * 4; e += kTrThreads) {
+    const int row = e >> 2, seg = e & 3;
+    *(GAS bf16x8*)(dst + (size_t)row * ldk + c0 + 8 * seg) = *(const lbf16x8*)(src + row * kTrLdT + 8 * seg);
+  }
+}
+
 extern __shared__ __align__(16) unsigned char tr_smem[];
 
 __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_mlp_train_rows(MlpTrain p) {
@@ -131,11 +141,11 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
   const int r = l & 15, kg = (l >> 4) * 8, q4 = 4 * (l >> 4);
   const int n0 = w * kTrCols;  // the wave's columns of every [32 x 256] product
   const f32x4 zero4 = {0.f, 0.f, 0.f, 0.f};
-  float* part = p.part + (size_t)blockIdx.x * p.n_par;
+  float* part = p.part + (size_t)blockIdx.x * kTrainSmall;
   float* zb = p.zbuf + (size_t)blockIdx.x * 3 * kTrainRows * 256;
   const float* mst = p.master;
   const uint32_t step = p.state ? p.state[0] - p.state[1] : 0u;
-  const int n_tiles = p.batch / kTrainRows;
+  const int n_tiles = p.rows / kTrainRows;
   // this lane's columns of the biases and of the output weights, loaded once
   float bcol[4][kTrCB], wcol[kTrCB];
 #pragma unroll
@@ -147,13 +157,14 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
   }
 
   for (int tile = blockIdx.x, it = 0; tile < n_tiles; tile += gridDim.x, ++it) {
-    const bool first = it == 0;
+    const bool first = it == 0 && p.first_pass;  // the workgroup's first tile of the batch
+    const int c0 = tile * kTrainRows;              // the tile's first column in gt / ht
     __syncthreads();  // the previous tile's readers of every LDS tile are done
     // ---- the tile's rows, given or drawn: eight threads per row, four inputs
     // each, loads independent of one another (clamped to the row, then masked)
     if (threadIdx.x < 8 * kTrainRows) {
       const int rr = threadIdx.x >> 3, c0 = (threadIdx.x & 7) * 4;
-      const int row = tile * kTrainRows + rr;
+      const int row = p.row0 + tile * kTrainRows + rr;
       const GAS float* xr;
       const GAS float* tr;
       if (p.src_x) {
@@ -181,6 +192,7 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
       if ((threadIdx.x & 7) == 0) stg[rr] = *tr;
     }
     __syncthreads();
+    tile_out(sb + kTrOffXt, 32, p.ht, p.ldk, c0);
 
     // ---- forward
     f32x4 acc[2][kTrCB];
@@ -227,6 +239,8 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
             }
         }
         __syncthreads();
+        tile_out(sb + kTrOffHt + (layer - 1) * 256 * kTrLdT, 256, p.ht + (size_t)(32 + (layer - 1) * 256) * p.ldk,
+                 p.ldk, c0);
       } else {
 #pragma unroll
         for (int j = 0; j < kTrCB; ++j) {
@@ -299,7 +313,7 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
         gb += sdy[m];
       }
       accum(p.loss_part + blockIdx.x, e, first);
-      accum(part + p.off_bout, gb, first);
+      accum(part + 1280, gb, first);
     }
     // output weights: sum over the tile's rows of H_4 dy; and G_4
     {
@@ -325,7 +339,7 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
           }
         sw += __shfl_xor(sw, 16, 64);
         sw += __shfl_xor(sw, 32, 64);
-        if (l < 16) accum(part + p.off_wout + col, sw, first);
+        if (l < 16) accum(part + 1024 + col, sw, first);
       }
     }
     __syncthreads();
@@ -333,51 +347,14 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
     // ---- backward
 #pragma unroll 1
     for (int layer = 4; layer >= 1; --layer) {
-      const int kin = layer == 1 ? 32 : 256;
-      // weight gradient: rows n of G^T against rows kc of H_{l-1}^T, K = the tile's 32 rows
-      {
-        const lbf16* Bt = layer == 1 ? sb + kTrOffXt : sb + kTrOffHt + (layer - 2) * 256 * kTrLdT;
-        bf16x8 ga[kTrCB];
-#pragma unroll
-        for (int i = 0; i < kTrCB; ++i) ga[i] = *(const lbf16x8*)(sb + kTrOffGt + (n0 + 16 * i + r) * kTrLdT + kg);
-        float* dW = part + p.off_W[layer - 1];
-        for (int jc = 0; jc < kin / 16; jc += 4) {
-          f32x4 c[kTrCB][4];
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
-            if (jc + jj >= kin / 16) break;
-            const bf16x8 bfr = *(const lbf16x8*)(Bt + (16 * (jc + jj) + r) * kTrLdT + kg);
-#pragma unroll
-            for (int i = 0; i < kTrCB; ++i) c[i][jj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ga[i], bfr, zero4, 0, 0, 0);
-          }
-          if (!first) {  // later tiles: add the slice's current values, all loads issued first
-#pragma unroll
-            for (int jj = 0; jj < 4; ++jj) {
-              if (jc + jj >= kin / 16) break;
-              const int kc = 16 * (jc + jj) + r;
-#pragma unroll
-              for (int i = 0; i < kTrCB; ++i)
-#pragma unroll
-                for (int q = 0; q < 4; ++q) c[i][jj][q] += ((const GAS float*)dW)[(size_t)(n0 + 16 * i + q4 + q) * kin + kc];
-            }
-          }
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) {
-            if (jc + jj >= kin / 16) break;
-            const int kc = 16 * (jc + jj) + r;
-#pragma unroll
-            for (int i = 0; i < kTrCB; ++i)
-#pragma unroll
-              for (int q = 0; q < 4; ++q) ((GAS float*)dW)[(size_t)(n0 + 16 * i + q4 + q) * kin + kc] = c[i][jj][q];
-          }
-        }
-      }
+      // G_l^T for the weight gradient
+      tile_out(sb + kTrOffGt, 256, p.gt + (size_t)(layer - 1) * 256 * p.ldk, p.ldk, c0);
       // bias gradient: column sums of G, in row order
       if (threadIdx.x < 256) {
         const int n = threadIdx.x;
         float sg = 0.f;
         for (int m = 0; m < kTrainRows; ++m) sg += (float)sb[kTrOffG + m * kTrLdH + n];
-        accum(part + p.off_b[layer - 1] + n, sg, first);
+        accum(part + 256 * (layer - 1) + n, sg, first);
       }
       if (layer > 1) {
         // G_{l-1} = (G_l W_l) GELU'(Z_{l-1}): rows of G against rows kc of W_l^T
@@ -426,8 +403,99 @@ __global__ __launch_bounds__(kTrThreads) __attribute__((amdgpu_waves_per_eu(2, 2
   }
 }
 
-// Sum of the workgroups' gradient slices (in workgroup order), then AdamW
-// (Loshchilov and Hutter) and the BF16 copies of the updated weights.
+// Weight gradients of one pass: dW_l = G_l^T H_{l-1} over its rows (K), one
+// workgroup per 16 x 16 block of one layer's gradient (the 16 x 2 blocks of
+// layer 1, then 16 x 16 per hidden layer), its four waves taking every fourth
+// K step of 32 rows (eight steps' fragments loaded at a time) and their sums
+// added in wave order; written on the first pass, added after.  On the last
+// pass further workgroups sum the slices of k_mlp_train_rows into the other
+// gradient entries, one wave per entry (lane k adds slices k, k + 64, ... in
+// order, then a fixed butterfly), and the loss into acc[0].
+constexpr int kDwBlocks = 16 * 2 + 3 * 16 * 16;
+constexpr int kDwSmallWg = (1281 + 1 + 3) / 4;  // 1281 entries and the loss, four waves per workgroup
+
+__device__ inline float wave_sum_f(float v) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_mlp_train_dw(MlpDw d) {
+  const int w = threadIdx.x >> 6;
+  const uint32_t l = lane_id();
+  if (blockIdx.x >= kDwBlocks) {  // slices and loss (last pass only)
+    const int e = (int)(blockIdx.x - kDwBlocks) * 4 + w;
+    if (e > 1281) return;
+    const float* src = e < 1281 ? d.part + e : d.loss_part;
+    const size_t stride = e < 1281 ? (size_t)kTrainSmall : 1;
+    float v = 0.f;
+    for (int k = (int)l; k < d.n_part; k += 64) v += ((const GAS float*)src)[(size_t)k * stride];
+    v = wave_sum_f(v);
+    if (l == 0) {
+      int64_t o;
+      if (e < 1024)
+        o = d.off_b[e >> 8] + (e & 255);
+      else if (e < 1280)
+        o = d.off_wout + (e - 1024);
+      else if (e == 1280)
+        o = d.off_bout;
+      else
+        o = -1;
+      if (o >= 0)
+        ((GAS float*)d.grad)[o] = v;
+      else
+        ((GAS float*)d.acc)[0] = v;
+    }
+    return;
+  }
+  int b = blockIdx.x, layer, nb, kb;
+  if (b < 32) {
+    layer = 0;
+    nb = b >> 1;
+    kb = b & 1;
+  } else {
+    b -= 32;
+    layer = 1 + (b >> 8);
+    nb = (b >> 4) & 15;
+    kb = b & 15;
+  }
+  const int kin = layer == 0 ? 32 : 256;
+  const int r = l & 15, kg = (l >> 4) * 8;
+  const __bf16* A = d.gt + ((size_t)layer * 256 + 16 * nb + r) * d.ldk + kg;  // G_l^T rows
+  const __bf16* B = d.ht + ((size_t)(layer == 0 ? 0 : 32 + (layer - 1) * 256) + 16 * kb + r) * d.ldk + kg;
+  const int steps = d.rows / 32;
+  f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  for (int s0 = w; s0 < steps; s0 += 32) {
+    bf16x8 a[8], bb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int s = min(s0 + 4 * u, steps - 1);  // past the end: a valid step, not used
+      a[u] = *(const GAS bf16x8*)(A + 32 * s);
+      bb[u] = *(const GAS bf16x8*)(B + 32 * s);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (s0 + 4 * u < steps) acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[u], bb[u], acc, 0, 0, 0);
+  }
+  __shared__ f32x4 red[4][64];
+  red[w][l] = acc;
+  __syncthreads();
+  if (w == 0) {
+    const f32x4 v0 = red[0][l], v1 = red[1][l], v2 = red[2][l], v3 = red[3][l];
+    GAS float* G = (GAS float*)d.grad + d.off_W[layer];
+    const int kc = 16 * kb + r;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int n = 16 * nb + 4 * (l >> 4) + q;
+      const float v = ((v0[q] + v1[q]) + v2[q]) + v3[q];
+      GAS float* o = G + (size_t)n * kin + kc;
+      *o = d.first_pass ? v : *o + v;
+    }
+  }
+}
+
+// AdamW (Loshchilov and Hutter) from the gradient, then the BF16 copies of
+// the updated weights.
 __global__ __launch_bounds__(256) void k_mlp_train_update(MlpUpdate u) {
   float lr = u.lr, c1 = u.c1, c2 = u.c2;
   if (u.lr_sched) {
@@ -437,20 +505,7 @@ __global__ __launch_bounds__(256) void k_mlp_train_update(MlpUpdate u) {
     c2 = (float)(1.0 - pow((double)u.b2, (double)t));
   }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < u.n_par; i += (int64_t)gridDim.x * blockDim.x) {
-    // slices in workgroup order; eight loads are in flight at a time, the
-    // additions stay in that order
-    float g = 0.f;
-    int k = 0;
-    for (; k + 8 <= u.n_part; k += 8) {
-      float v[8];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) v[q] = ((const GAS float*)u.part)[(size_t)(k + q) * u.n_par + i];
-#pragma unroll
-      for (int q = 0; q < 8; ++q) g += v[q];
-    }
-    for (; k < u.n_part; ++k) g += ((const GAS float*)u.part)[(size_t)k * u.n_par + i];
-    ((GAS float*)u.grad)[i] = g;
-    if (!u.p) continue;
+    const float g = ((const GAS float*)u.grad)[i];
     GAS float* P = (GAS float*)u.p;
     GAS float* M = (GAS float*)u.m;
     GAS float* V = (GAS float*)u.v;
@@ -470,11 +525,6 @@ __global__ __launch_bounds__(256) void k_mlp_train_update(MlpUpdate u) {
         ((GAS __bf16*)u.Wtb[L])[(size_t)kk * 256 + rr] = v;
       }
     }
-  }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    float e = 0.f;
-    for (int k = 0; k < u.n_part; ++k) e += u.loss_part[k];
-    u.acc[0] = e;
   }
 }
 
@@ -625,13 +675,15 @@ hipError_t mlp_step_done(uint32_t* state, const float* acc, float* losses, hipSt
 
 size_t mlp_train_lds_bytes() { return kTrLdsBytes; }
 
-int mlp_train_grid(int batch) {
-  const int tiles = batch / kTrainRows;
+int mlp_train_grid(int rows) {
+  const int tiles = rows / kTrainRows;
   return tiles < kTrainMaxWg ? tiles : kTrainMaxWg;
 }
 
 hipError_t mlp_train_rows(const MlpTrain& p, hipStream_t s) {
-  if (p.batch <= 0 || p.batch % kTrainRows) return hipErrorInvalidValue;
+  if (p.batch <= 0 || p.batch % kTrainRows || p.rows <= 0 || p.rows % kTrainRows || p.rows > p.ldk ||
+      p.row0 < 0 || p.row0 + p.rows > p.batch)
+    return hipErrorInvalidValue;
   // the kernel needs more LDS than the default dynamic limit: raise it once per device
   static std::atomic<bool> attr[64];
   int dev = 0;
@@ -644,7 +696,13 @@ hipError_t mlp_train_rows(const MlpTrain& p, hipStream_t s) {
     if (e != hipSuccess) return e;
     attr[dev].store(true);
   }
-  k_mlp_train_rows<<<mlp_train_grid(p.batch), kTrThreads, kTrLdsBytes, s>>>(p);
+  k_mlp_train_rows<<<mlp_train_grid(p.rows), kTrThreads, kTrLdsBytes, s>>>(p);
+  return hipGetLastError();
+}
+
+hipError_t mlp_train_dw(const MlpDw& d, hipStream_t s) {
+  if (d.rows <= 0 || d.rows % kTrainRows || d.rows > d.ldk || d.n_part <= 0) return hipErrorInvalidValue;
+  k_mlp_train_dw<<<kDwBlocks + (d.last_pass ? kDwSmallWg : 0), 256, 0, s>>>(d);
   return hipGetLastError();
 }
 

@@ -140,7 +140,7 @@ def bench_inference(ctx, srg_id: int, n_in: int = 8, n: int = 1_000_000, reps: i
 
 
 def bench_training(ctx, n_in: int = 8, batch: int = 1024, steps: int = 500, seed: int = 0):
-    """The device training loop (two launches per step, replayed as a graph)
+    """The device training loop (three launches per step, replayed as a graph)
     on synthetic rows: steps per second, samples per second and the
     forward + backward FLOP rate (3 x the forward's per sample)."""
     import torch

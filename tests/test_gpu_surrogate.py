@@ -139,12 +139,14 @@ def test_gradient_deviation_is_the_bf16_storage(ctx, seed):
     assert rel_e < 0.25 * rel_r, (rel_e, rel_r)
 
 
-@pytest.mark.parametrize("batch", [32, 4128])
+@pytest.mark.parametrize("batch", [32, 4128, 16384 + 4128])
 def test_gradient_of_one_tile_and_of_many_tiles_per_workgroup(ctx, batch):
-    """One 32-row tile (one workgroup), and 129 tiles over the 64 workgroups
-    (two or three tiles each, so each adds later tiles into its gradient slice
-    before the slices are summed): the gradient still carries only the BF16
-    storage error against the host evaluation with the same rounding."""
+    """One 32-row tile (one workgroup); 129 tiles in 129 workgroups; and a
+    batch of two passes (16384 rows as two tiles in each of 256 workgroups,
+    whose bias and loss sums each workgroup adds up in its slice, then 4128
+    rows whose weight gradients are added to the first pass's): the gradient
+    still carries only the BF16 storage error against the host evaluation with
+    the same rounding."""
     s = ctx.srg_create(N_IN, 256, 4, seed=44)
     p = ctx.srg_params(s)
     X, t = _data(60, batch)
