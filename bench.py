@@ -388,6 +388,8 @@ def bench_surrogate(ctx, rtmc):
     srg = ctx.srg_create(8, 256, 4, seed=0)
     inf = bench_inference(ctx, srg, n=1_000_000, reps=20)
     train = bench_training(ctx)
+    # the same loop at a batch that fills the GPU (256 workgroups, four passes of 16384 rows)
+    train["batch_65536"] = bench_training(ctx, batch=65536, steps=30)
     # held-out experiment (python -m paper_1806_00205_amd.surrogate --train-foams 1024 --points 96
     # --test-foams 256 --steps 8000): MAE 0.0100 over 256 x 25 points judged by RTMC at 1e6 primaries,
     # which need 4006 primaries per yield for sigma = MAE

@@ -303,14 +303,15 @@ def main():
     ap.add_argument("--workers", type=int, default=min(16, len(os.sched_getaffinity(0))))
     ap.add_argument("--batch-foams", type=int, default=32)
     ap.add_argument("--timing", action="store_true",
-                    help="only time the kernels: 1e6-query inference and the batch-1024 training loop")
+                    help="only time the kernels: 1e6-query inference and the training loop at batch 1024 and 65536")
     args = ap.parse_args()
     import paper_1806_00205_amd as rt
 
     ctx = rt.Context(0)
     if args.timing:
         srg = ctx.srg_create(8, 256, 4, seed=0)
-        print(json.dumps({"inference": bench_inference(ctx, srg), "training": bench_training(ctx)}), flush=True)
+        print(json.dumps({"inference": bench_inference(ctx, srg), "training": bench_training(ctx),
+                          "training_batch_65536": bench_training(ctx, batch=65536, steps=30)}), flush=True)
         ctx.close()
         return
     res, _ = run_experiment(ctx, n_train=args.train_foams, points_per_foam=args.points, n_test=args.test_foams,
