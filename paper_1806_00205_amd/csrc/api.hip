@@ -1577,9 +1577,11 @@ MlpTrain srg_train_args(const Surrogate& g, const SrgTrainWs& w, int64_t batch) 
 
 // The gradient of the batch into g.grad and its loss into w.acc[0]: the
 // passes of mlp_train_rows and mlp_train_dw in row order.
-rtmc_status srg_gradient_passes(rtmc_ctx* c, Surrogate& g, const SrgTrainWs& w, MlpTrain t) {
+rtmc_status srg_gradient_passes(rtmc_ctx* c, Surrogate& g, const SrgTrainWs& w, MlpTrain t,
+                                const MlpDw* loop = nullptr) {
   const SrgLayout L = srg_layout(g);
   MlpDw d{};
+  if (loop) d = *loop;  // the device loop's step bookkeeping
   d.gt = w.gt;
   d.ht = w.ht;
   d.ldk = w.ldk;
@@ -1834,13 +1836,15 @@ rtmc_status rtmc_srg_train(rtmc_ctx* c, int32_t id, const float* X, const float*
   SrgTrainWs w;
   st = srg_train_ws(c, g, batch, w);
   if (st) return st;
-  // loop buffer: 2 state words (padded to 256 B), lr[steps], losses[steps]
+  // loop buffer: 2 state words and the step's 3 AdamW constants (padded to
+  // 256 B), lr[steps], losses[steps]
   auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
   const size_t o_lr = 256, o_loss = o_lr + up((size_t)steps * 4), total = o_loss + up((size_t)steps * 4);
   st = ensure(c, g.tbuf, total);
   if (st) return st;
   char* base = static_cast<char*>(g.tbuf.p);
   uint32_t* state = reinterpret_cast<uint32_t*>(base);
+  float* sched = reinterpret_cast<float*>(base + 64);
   float* lr_d = reinterpret_cast<float*>(base + o_lr);
   float* loss_d = reinterpret_cast<float*>(base + o_loss);
   HIPCHK(c, hipMemcpyAsync(lr_d, lr, (size_t)steps * 4, hipMemcpyHostToDevice, c->stream));
@@ -1852,16 +1856,22 @@ rtmc_status rtmc_srg_train(rtmc_ctx* c, int32_t id, const float* X, const float*
   targs.seed = seed;
   targs.state = state;
   MlpUpdate uargs = srg_update_args(g);
-  uargs.lr_sched = lr_d;
-  uargs.state = state;
+  uargs.sched = sched;
   uargs.wd = weight_decay;
+  MlpDw loop{};
+  loop.state = state;
+  loop.losses = loss_d;
+  loop.lr_sched = lr_d;
+  loop.sched = sched;
+  loop.b1 = uargs.b1;
+  loop.b2 = uargs.b2;
   // one step: rows drawn on the device, forward, backward signals and the
-  // weight gradients (per pass of rows), AdamW and the BF16 weights; loss out
+  // weight gradients (per pass of rows; the last pass also records the loss
+  // and advances the step), AdamW and the BF16 weights
   auto one_step = [&]() -> rtmc_status {
-    rtmc_status s2 = srg_gradient_passes(c, g, w, targs);
+    rtmc_status s2 = srg_gradient_passes(c, g, w, targs, &loop);
     if (s2) return s2;
     HIPCHK(c, mlp_train_update(uargs, c->stream));
-    HIPCHK(c, mlp_step_done(state, w.acc, loss_d, c->stream));
     return RTMC_OK;
   };
   if (!use_graph) {

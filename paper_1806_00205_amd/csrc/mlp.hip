@@ -57,17 +57,6 @@ __device__ inline float gelu_d(float x) {
 //   A: row l % 16, k = 8 (l / 16) .. + 7;  B: column l % 16, same k;
 //   C: column l % 16, rows 4 (l / 16) .. + 3.
 
-// ---- a training loop on the device (one step is replayed as a graph).
-// state[0] counts the AdamW steps taken so far, state[1] is its value when
-// the loop began, so state[0] - state[1] is the loop's current step s.
-
-// End of a loop step: its batch loss (before the update) to losses[s]; one step more.
-__global__ void k_step_done(uint32_t* state, const float* acc, float* losses) {
-  const uint32_t s = state[0] - state[1];
-  losses[s] = acc[0];
-  state[0] = state[0] + 1u;
-}
-
 __global__ void k_to_bf16(const float* __restrict__ W, int rows, int cols, __bf16* __restrict__ Wb,
                           __bf16* __restrict__ Wtb) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -441,10 +430,19 @@ __global__ __launch_bounds__(256) void k_mlp_train_dw(MlpDw d) {
         o = d.off_bout;
       else
         o = -1;
-      if (o >= 0)
+      if (o >= 0) {
         ((GAS float*)d.grad)[o] = v;
-      else
+      } else {
         ((GAS float*)d.acc)[0] = v;
+        if (d.state) {  // device loop: the step's loss and AdamW constants, then one step more
+          const uint32_t s = d.state[0] - d.state[1], t = d.state[0] + 1u;
+          d.losses[s] = v;
+          d.sched[0] = d.lr_sched[s];
+          d.sched[1] = (float)(1.0 - pow((double)d.b1, (double)t));
+          d.sched[2] = (float)(1.0 - pow((double)d.b2, (double)t));
+          d.state[0] = t;
+        }
+      }
     }
     return;
   }
@@ -498,11 +496,10 @@ __global__ __launch_bounds__(256) void k_mlp_train_dw(MlpDw d) {
 // the updated weights.
 __global__ __launch_bounds__(256) void k_mlp_train_update(MlpUpdate u) {
   float lr = u.lr, c1 = u.c1, c2 = u.c2;
-  if (u.lr_sched) {
-    const uint32_t t = u.state[0] + 1u;
-    lr = u.lr_sched[u.state[0] - u.state[1]];
-    c1 = (float)(1.0 - pow((double)u.b1, (double)t));
-    c2 = (float)(1.0 - pow((double)u.b2, (double)t));
+  if (u.sched) {
+    lr = u.sched[0];
+    c1 = u.sched[1];
+    c2 = u.sched[2];
   }
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < u.n_par; i += (int64_t)gridDim.x * blockDim.x) {
     const float g = ((const GAS float*)u.grad)[i];
@@ -668,10 +665,6 @@ hipError_t mlp_infer(const MlpInfer& p, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t mlp_step_done(uint32_t* state, const float* acc, float* losses, hipStream_t s) {
-  k_step_done<<<1, 1, 0, s>>>(state, acc, losses);
-  return hipGetLastError();
-}
 
 size_t mlp_train_lds_bytes() { return kTrLdsBytes; }
 

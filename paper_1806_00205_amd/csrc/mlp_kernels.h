@@ -9,10 +9,6 @@ namespace rtmc {
 
 // Surrogate MLP pieces (mlp.hip)
 hipError_t mlp_to_bf16(const float* W, int rows, int cols, __bf16* Wb, __bf16* Wtb, hipStream_t s);
-// Training loop on the device; state[0] = AdamW steps so far, state[1] = its
-// value when the loop began (so the loop's step is their difference).
-// mlp_step_done: the step's loss acc[0] to losses[state[0] - state[1]], then one step more.
-hipError_t mlp_step_done(uint32_t* state, const float* acc, float* losses, hipStream_t s);
 
 // Training of the 4 x 256 GELU network, three launches per step (the batch in
 // passes of at most kTrainChunk rows, each pass one mlp_train_rows and one
@@ -27,7 +23,11 @@ hipError_t mlp_step_done(uint32_t* state, const float* acc, float* losses, hipSt
 // (src_x, src_t), u the first word of Philox4x32-10(key seed, counter (r, s, 0, 0)).
 // mlp_train_dw: dW_l = G_l^T H_{l-1} over the pass's rows into grad (written on
 // the first pass, added after); on the last pass also the sums of the slices
-// (in a fixed order) into grad's other entries and the loss into acc[0].
+// (in a fixed order) into grad's other entries and the loss into acc[0], and,
+// in the device training loop (state set: state[0] = AdamW steps so far,
+// state[1] its value when the loop began, s = state[0] - state[1] the loop's
+// step), the loss to losses[s], the step's learning rate lr_sched[s] and bias
+// corrections 1 - b^(state[0] + 1) to sched[0..2], then state[0] + 1.
 // mlp_train_update: AdamW from grad and the BF16 weight copies.
 // Every sum has a fixed order, so a step is reproducible bit for bit.
 constexpr int kTrainRows = 32;       // batch rows per tile
@@ -70,17 +70,21 @@ struct MlpDw {
   const float* loss_part;
   int n_part;
   float* acc;              // acc[0] = loss
+  uint32_t* state;         // device training loop only (else null)
+  float* losses;
+  const float* lr_sched;
+  float* sched;            // [3]: lr, c1, c2 of the step
+  float b1, b2;
 };
 hipError_t mlp_train_dw(const MlpDw& d, hipStream_t s);
 struct MlpUpdate {
   int64_t n_par;
   const float* grad;       // [n_par]
-  // AdamW with learning rate lr_sched[state[0] - state[1]] and step t =
-  // state[0] + 1 when lr_sched is set, else lr and the bias corrections c1, c2
+  // AdamW with learning rate and bias corrections sched[0..2] when sched is
+  // set (the device loop), else lr, c1, c2
   float* p;
   float *m, *v;
-  const float* lr_sched;
-  const uint32_t* state;
+  const float* sched;
   float lr, c1, c2, b1, b2, eps, wd;
   __bf16* Wb[4];           // BF16 copies written after the update
   __bf16* Wtb[4];
