@@ -9,8 +9,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/rtmc.h"
@@ -788,9 +790,9 @@ rtmc_status rtmc_set_stream(rtmc_ctx* c, void* hip_stream) {
   return RTMC_OK;
 }
 
-rtmc_status rtmc_load_mesh(rtmc_ctx* c, const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+namespace {
+rtmc_status load_mesh_impl(rtmc_ctx* c, const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
                            const double box_lo[3], const double box_hi[3], uint32_t flags, int32_t* scene_id) {
-  if (!c) return RTMC_EINVAL;
   c->err.clear();
   if (!scene_id || !box_lo || !box_hi || n_verts < 0 || n_tris < 0 || (n_verts > 0 && !verts) ||
       (n_tris > 0 && !tris))
@@ -801,66 +803,129 @@ rtmc_status rtmc_load_mesh(rtmc_ctx* c, const float* verts, int64_t n_verts, con
     if (!std::isfinite(box_lo[a]) || !std::isfinite(box_hi[a]) || !(box_hi[a] > box_lo[a]))
       return fail(c, RTMC_EINVAL, "box axis %d is empty or not finite", a);
   }
-  for (int64_t i = 0; i < n_verts * 3; ++i) {
-    const float x = verts[i];
-    const int a = (int)(i % 3);
-    if (!finite_f(x)) return fail(c, RTMC_EINVAL, "vertex %lld is not finite", (long long)(i / 3));
-    if ((double)x < box_lo[a] || (double)x > box_hi[a])
-      return fail(c, RTMC_EINVAL, "vertex %lld lies outside the box", (long long)(i / 3));
-  }
+  // validation and packing run over host threads in contiguous ranges; the
+  // first offending vertex or triangle in index order is the one reported
+  const int nth = n_verts + n_tris < (1 << 16) ? 1 : (int)std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+  auto ranges = [nth](int64_t n, auto&& f) {
+    std::vector<std::thread> ts;
+    for (int t = 0; t < nth; ++t) {
+      const int64_t lo = n * t / nth, hi = n * (t + 1) / nth;
+      if (t + 1 < nth)
+        ts.emplace_back(f, t, lo, hi);
+      else
+        f(t, lo, hi);
+    }
+    for (auto& th : ts) th.join();
+  };
+  // vertices: the first non-finite or out-of-box coordinate
+  std::vector<int64_t> bad_v(nth, -1);
+  std::vector<int> bad_v_kind(nth, 0);
+  ranges(n_verts, [&](int t, int64_t lo, int64_t hi) {
+    for (int64_t v = lo; v < hi; ++v)
+      for (int a = 0; a < 3; ++a) {
+        const float x = verts[3 * v + a];
+        const int kind = !finite_f(x) ? 1 : ((double)x < box_lo[a] || (double)x > box_hi[a]) ? 2 : 0;
+        if (kind) {
+          bad_v[t] = v;
+          bad_v_kind[t] = kind;
+          return;
+        }
+      }
+  });
+  for (int t = 0; t < nth; ++t)
+    if (bad_v[t] >= 0)
+      return fail(c, RTMC_EINVAL, bad_v_kind[t] == 1 ? "vertex %lld is not finite" : "vertex %lld lies outside the box",
+                  (long long)bad_v[t]);
   Scene s;
   s.n_in = n_tris;
   std::memcpy(s.lo, box_lo, sizeof(s.lo));
   std::memcpy(s.hi, box_hi, sizeof(s.hi));
   s.flags = flags;
-  std::vector<float> packed;
-  packed.reserve((size_t)n_tris * 12);
-  for (int64_t j = 0; j < n_tris; ++j) {
-    const int32_t* t = tris + 3 * j;
-    for (int k = 0; k < 3; ++k)
-      if (t[k] < 0 || t[k] >= n_verts)
-        return fail(c, RTMC_EINVAL, "triangle %lld has vertex index %d out of range", (long long)j, t[k]);
-    double v[3][3];
-    for (int k = 0; k < 3; ++k)
-      for (int a = 0; a < 3; ++a) v[k][a] = verts[3 * (int64_t)t[k] + a];
-    const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
-    const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
-    const double nx = e1[1] * e2[2] - e1[2] * e2[1];
-    const double ny = e1[2] * e2[0] - e1[0] * e2[2];
-    const double nz = e1[0] * e2[1] - e1[1] * e2[0];
-    if (nx == 0.0 && ny == 0.0 && nz == 0.0) {
-      s.dropped++;
-      continue;
-    }
-    // a surface in a face of the cell would be met exactly where a ray leaves
-    // the cell (re-entry, substrate, escape), and which comes first would be
-    // decided by rounding
-    for (int a = 0; a < 3; ++a) {
-      const bool on_lo = v[0][a] == box_lo[a] && v[1][a] == box_lo[a] && v[2][a] == box_lo[a];
-      const bool on_hi = v[0][a] == box_hi[a] && v[1][a] == box_hi[a] && v[2][a] == box_hi[a];
-      if (on_lo || on_hi)
-        return fail(c, RTMC_EINVAL, "triangle %lld lies in the %s face of the cell on axis %d", (long long)j,
-                    on_lo ? "lower" : "upper", a);
-    }
-    for (int k = 0; k < 3; ++k) {
-      packed.push_back((float)v[k][0]);
-      packed.push_back((float)v[k][1]);
-      packed.push_back((float)v[k][2]);
-      float w = 0.0f;
-      if (k == 0) {
-        int32_t id = (int32_t)j;
-        std::memcpy(&w, &id, 4);
+  // triangles, first pass: index range, zero area (dropped: the FP64 cross
+  // product of the edges is exactly zero), a surface lying in a face of the
+  // cell (refused: it would be met exactly where a ray leaves the cell --
+  // re-entry, substrate, escape -- and which comes first would be decided by
+  // rounding); kept[j] marks the triangles that go on
+  std::unique_ptr<uint8_t[]> kept(new uint8_t[(size_t)std::max<int64_t>(n_tris, 1)]);
+  std::vector<int64_t> n_kept(nth, 0), bad_t(nth, -1);
+  std::vector<int> bad_t_kind(nth, 0), bad_t_arg(nth, 0);
+  ranges(n_tris, [&](int th, int64_t lo, int64_t hi) {
+    for (int64_t j = lo; j < hi; ++j) {
+      const int32_t* t = tris + 3 * j;
+      for (int k = 0; k < 3; ++k)
+        if (t[k] < 0 || t[k] >= n_verts) {
+          bad_t[th] = j;
+          bad_t_kind[th] = 1;
+          bad_t_arg[th] = t[k];
+          return;
+        }
+      double v[3][3];
+      for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 3; ++a) v[k][a] = verts[3 * (int64_t)t[k] + a];
+      const double e1[3] = {v[1][0] - v[0][0], v[1][1] - v[0][1], v[1][2] - v[0][2]};
+      const double e2[3] = {v[2][0] - v[0][0], v[2][1] - v[0][1], v[2][2] - v[0][2]};
+      const double nx = e1[1] * e2[2] - e1[2] * e2[1];
+      const double ny = e1[2] * e2[0] - e1[0] * e2[2];
+      const double nz = e1[0] * e2[1] - e1[1] * e2[0];
+      if (nx == 0.0 && ny == 0.0 && nz == 0.0) {
+        kept[j] = 0;
+        continue;
       }
-      packed.push_back(w);
+      for (int a = 0; a < 3; ++a) {
+        const bool on_lo = v[0][a] == box_lo[a] && v[1][a] == box_lo[a] && v[2][a] == box_lo[a];
+        const bool on_hi = v[0][a] == box_hi[a] && v[1][a] == box_hi[a] && v[2][a] == box_hi[a];
+        if (on_lo || on_hi) {
+          bad_t[th] = j;
+          bad_t_kind[th] = on_lo ? 2 : 3;
+          bad_t_arg[th] = a;
+          return;
+        }
+      }
+      kept[j] = 1;
+      ++n_kept[th];
     }
+  });
+  for (int t = 0; t < nth; ++t) {
+    if (bad_t[t] < 0) continue;
+    if (bad_t_kind[t] == 1)
+      return fail(c, RTMC_EINVAL, "triangle %lld has vertex index %d out of range", (long long)bad_t[t], bad_t_arg[t]);
+    return fail(c, RTMC_EINVAL, "triangle %lld lies in the %s face of the cell on axis %d", (long long)bad_t[t],
+                bad_t_kind[t] == 2 ? "lower" : "upper", bad_t_arg[t]);
   }
-  s.n_tris = (int64_t)packed.size() / 12;
+  // second pass: the kept triangles' 48-byte records (V0, V1, V2; V0.w = the
+  // caller's index) in index order, each range at its prefix offset
+  std::vector<int64_t> off(nth + 1, 0);
+  for (int t = 0; t < nth; ++t) off[t + 1] = off[t] + n_kept[t];
+  const int64_t n_out = off[nth];
+  s.dropped = n_tris - n_out;
+  std::unique_ptr<float[]> packed(new float[(size_t)std::max<int64_t>(n_out, 1) * 12]);
+  ranges(n_tris, [&](int th, int64_t lo, int64_t hi) {
+    float* o = packed.get() + 12 * off[th];
+    for (int64_t j = lo; j < hi; ++j) {
+      if (!kept[j]) continue;
+      const int32_t* t = tris + 3 * j;
+      for (int k = 0; k < 3; ++k) {
+        o[0] = verts[3 * (int64_t)t[k]];
+        o[1] = verts[3 * (int64_t)t[k] + 1];
+        o[2] = verts[3 * (int64_t)t[k] + 2];
+        float w = 0.0f;
+        if (k == 0) {
+          const int32_t id = (int32_t)j;
+          std::memcpy(&w, &id, 4);
+        }
+        o[3] = w;
+        o += 4;
+      }
+    }
+  });
+  s.n_tris = n_out;
+  const size_t bytes = (size_t)n_out * 48;
   HIPCHK(c, hipSetDevice(c->device));
-  s.tris_in.p = dev_alloc(c, packed.size() * 4);
+  s.tris_in.p = dev_alloc(c, bytes);
   if (!s.tris_in.p) return fail(c, RTMC_ENOMEM, "device allocation for %lld triangles failed", (long long)s.n_tris);
-  s.tris_in.bytes = packed.size() * 4;
-  if (!packed.empty()) {
-    hipError_t e = hipMemcpyAsync(s.tris_in.p, packed.data(), packed.size() * 4, hipMemcpyHostToDevice, c->stream);
+  s.tris_in.bytes = bytes;
+  if (n_out > 0) {
+    hipError_t e = hipMemcpyAsync(s.tris_in.p, packed.get(), bytes, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) {
       dev_free(c, s.tris_in);
@@ -870,6 +935,17 @@ rtmc_status rtmc_load_mesh(rtmc_ctx* c, const float* verts, int64_t n_verts, con
   c->scenes.push_back(s);
   *scene_id = (int32_t)c->scenes.size() - 1;
   return RTMC_OK;
+}
+}  // namespace
+
+rtmc_status rtmc_load_mesh(rtmc_ctx* c, const float* verts, int64_t n_verts, const int32_t* tris, int64_t n_tris,
+                           const double box_lo[3], const double box_hi[3], uint32_t flags, int32_t* scene_id) {
+  if (!c) return RTMC_EINVAL;
+  try {  // host threads and buffers may fail to start or allocate; nothing is thrown across the C interface
+    return load_mesh_impl(c, verts, n_verts, tris, n_tris, box_lo, box_hi, flags, scene_id);
+  } catch (const std::exception& e) {
+    return fail(c, RTMC_ENOMEM, "mesh ingest: %s", e.what());
+  }
 }
 
 rtmc_status rtmc_build_bvh(rtmc_ctx* c, int32_t scene_id) {
