@@ -3,6 +3,7 @@ import numpy as np
 import pytest
 
 from oracle import mlp_ref
+from tests.philox_ref import philox4x32_10
 
 pytestmark = pytest.mark.gpu
 
@@ -199,6 +200,35 @@ def test_training_loop_graph_replays_equal_eager(ctx):
         torch.cuda.synchronize()
 
 
+def test_training_loop_of_two_passes_per_step(ctx):
+    """A batch of 16384 + 2048 rows takes two passes of the weight-gradient
+    kernel per step, the step's bookkeeping (loss, AdamW constants, step
+    counter) on the last one only: the loop's losses are those of the
+    same-seed loop replayed as a graph, and its first loss is the batch loss
+    of the rows the first step draws, evaluated on the host."""
+    import torch
+    X, t = _data(51, 50000)
+    Xd, td = torch.tensor(X, device="cuda:0"), torch.tensor(t, device="cuda:0")
+    batch = 16384 + 2048
+    a = ctx.srg_create(N_IN, 256, 4, seed=12)
+    b = ctx.srg_create(N_IN, 256, 4, seed=12)
+    p0 = ctx.srg_params(a)
+    lr = np.full(5, 1e-3, dtype=np.float32)
+    la = ctx.srg_train(a, Xd, td, batch, lr, seed=5, use_graph=False)
+    lb = ctx.srg_train(b, Xd, td, batch, lr, seed=5, use_graph=True)
+    assert np.array_equal(la, lb)
+    assert np.array_equal(ctx.srg_params(a), ctx.srg_params(b))
+    # rows of step 0: batch row r is source row floor(u n / 2^32), u the first
+    # word of Philox4x32-10 keyed by the seed at counter (r, 0, 0, 0)
+    ctr = np.zeros((batch, 4), dtype=np.uint32)
+    ctr[:, 0] = np.arange(batch, dtype=np.uint32)
+    u = philox4x32_10(ctr, np.array([5, 0], dtype=np.uint32))[:, 0].astype(np.uint64)
+    rows = ((u * np.uint64(len(X))) >> np.uint64(32)).astype(np.int64)
+    lr0, _ = mlp_ref.loss_and_grad(mlp_ref.gpu_visible_params(p0, N_IN), mlp_ref.round_bf16(X[rows]), t[rows], N_IN)
+    assert float(la[0]) == pytest.approx(lr0, rel=1e-2)
+    assert np.all(np.isfinite(la)) and la[-1] < la[0]
+
+
 def test_training_loop_converges(ctx):
     import torch
     s = ctx.srg_create(N_IN, 256, 4, seed=8)
@@ -238,7 +268,7 @@ def test_rejects_bad_shapes(ctx):
         ctx.srg_create(N_IN, 128, 4, seed=0)
 
 
-@pytest.mark.parametrize("n_in,B", [(8, 128 * 3 + 1), (5, 64), (32, 1000)])
+@pytest.mark.parametrize("n_in,B", [(8, 128 * 3 + 1), (5, 64), (32, 1000), (1, 130), (31, 257)])
 def test_fused_prediction_matches_reference_any_width(ctx, n_in, B):
     """The fused inference kernel (all layers in one workgroup, activations in
     LDS) against the FP64 reference, for input counts that fill a different
